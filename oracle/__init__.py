@@ -1,0 +1,227 @@
+"""FP64 CPU oracle for SOP overdamped Langevin dynamics -- test infrastructure.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The arithmetic lives in ``sop_oracle.c`` (plain C, FP64,
+single-threaded); this module only marshals arrays through ctypes.  It never
+imports the HIP library's package, and the HIP library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sop_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, E_ARG, E_FENE, E_OVERFLOW, E_NONFINITE, E_TIP = 0, -1, -5, -6, -7, -8
+NTERMS = 5
+TERM_NAMES = ("fene", "native", "repulsive", "external", "virial")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("k_fene", "R0", "eps_h", "eps_l", "sigma", "r_list", "kBT", "zeta", "h")] + [
+        ("list_every", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64)]
+
+
+class SystemC(C.Structure):
+    _fields_ = [
+        ("n_res", C.c_int64), ("n_traj", C.c_int64),
+        ("res_offsets", C.c_void_p), ("stream_ids", C.c_void_p),
+        ("n_bonds", C.c_int64), ("bonds", C.c_void_p), ("bond_r0", C.c_void_p),
+        ("n_native", C.c_int64), ("natives", C.c_void_p), ("native_r0", C.c_void_p),
+        ("fixed", C.c_void_p),
+        ("n_pull", C.c_int32), ("has_tip", C.c_int32),
+        ("pull_traj", C.c_void_p), ("pull_res", C.c_void_p), ("pull_kappa", C.c_void_p),
+        ("pull_anchor0", C.c_void_p), ("pull_v", C.c_void_p),
+        ("tip_radius", C.c_double), ("tip_eps", C.c_double), ("tip_sigma", C.c_double),
+        ("tip_c0", C.c_double * 3), ("tip_v", C.c_double * 3),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        vp, i64, u32, u64 = C.c_void_p, C.c_int64, C.c_uint32, C.c_uint64
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_uniform.argtypes = [u32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_gauss3.argtypes = [u64, u32, u32, i64, vp]
+        dp = C.POINTER(C.c_double)
+        L.orc_fene.argtypes = [C.c_double] * 4 + [dp, C.POINTER(C.c_int)]
+        L.orc_fene.restype = C.c_double
+        L.orc_native.argtypes = [C.c_double] * 3 + [dp]
+        L.orc_native.restype = C.c_double
+        L.orc_repulsive.argtypes = [C.c_double] * 3 + [dp]
+        L.orc_repulsive.restype = C.c_double
+        L.orc_pairlist.argtypes = [vp, vp, vp, vp, i64]
+        L.orc_pairlist.restype = i64
+        L.orc_pairlist_bruteforce.argtypes = [vp, vp, vp, vp, i64]
+        L.orc_pairlist_bruteforce.restype = i64
+        L.orc_forces.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp]
+        L.orc_forces.restype = C.c_int
+        L.orc_forces_rows.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp]
+        L.orc_forces_rows.restype = C.c_int
+        L.orc_run.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, vp]
+        L.orc_run.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class OracleSystem:
+    """Holds contiguous copies of a synthetic System's arrays for the C side."""
+
+    def __init__(self, sysm, params):
+        self.sysm = sysm
+        self.p = Params(params.k_fene, params.R0, params.eps_h, params.eps_l, params.sigma,
+                        params.r_list, params.kBT, params.zeta, params.h,
+                        int(params.list_every), 0, int(params.seed))
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        s = SystemC()
+        s.n_res, s.n_traj = sysm.n_res, sysm.n_traj
+        s.res_offsets = _ptr(arr(sysm.res_offsets, np.int64))
+        s.stream_ids = _ptr(arr(sysm.stream_ids, np.uint32))
+        s.n_bonds = len(sysm.bonds)
+        s.bonds = _ptr(arr(np.asarray(sysm.bonds).reshape(-1, 2), np.int32))
+        s.bond_r0 = _ptr(arr(sysm.bond_r0, np.float64))
+        s.n_native = len(sysm.natives)
+        s.natives = _ptr(arr(np.asarray(sysm.natives).reshape(-1, 2), np.int32))
+        s.native_r0 = _ptr(arr(sysm.native_r0, np.float64))
+        s.fixed = None if sysm.fixed is None else _ptr(arr(sysm.fixed, np.uint8))
+        pulls = list(sysm.pulls)
+        s.n_pull = len(pulls)
+        if pulls:
+            s.pull_traj = _ptr(arr([p.traj for p in pulls], np.int32))
+            s.pull_res = _ptr(arr([p.residue for p in pulls], np.int32))
+            s.pull_kappa = _ptr(arr([p.kappa for p in pulls], np.float64))
+            s.pull_anchor0 = _ptr(arr(np.stack([p.anchor0 for p in pulls]), np.float64))
+            s.pull_v = _ptr(arr(np.stack([p.v for p in pulls]), np.float64))
+        if sysm.tip is not None:
+            t = sysm.tip
+            s.has_tip = 1
+            s.tip_radius, s.tip_eps, s.tip_sigma = t.radius, t.eps, t.sigma
+            s.tip_c0 = (C.c_double * 3)(*[float(v) for v in t.c0])
+            s.tip_v = (C.c_double * 3)(*[float(v) for v in t.v])
+        self.s = s
+
+    # -- pieces ---------------------------------------------------------
+    def pairlist(self, x, brute=False):
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        fn = L.orc_pairlist_bruteforce if brute else L.orc_pairlist
+        m = fn(C.byref(self.s), C.byref(self.p), _ptr(x), None, 0)
+        if m < 0:
+            raise RuntimeError(f"oracle pairlist failed: {m}")
+        ij = np.zeros((max(m, 1), 2), dtype=np.int32)
+        m2 = fn(C.byref(self.s), C.byref(self.p), _ptr(x), _ptr(ij), m)
+        assert m2 == m
+        return ij[:m]
+
+    def forces(self, x, step=0, pairs=None, check=True):
+        """Forces, per-trajectory energies (n_traj,5) and external-force reports."""
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if pairs is None:
+            pairs = self.pairlist(x)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+        F = np.zeros((self.sysm.n_res, 3))
+        E = np.zeros((self.sysm.n_traj, NTERMS))
+        fe = np.zeros(self.sysm.n_traj)
+        st = L.orc_forces(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(pairs),
+                          len(pairs), _ptr(F), _ptr(E), _ptr(fe))
+        if check and st != OK:
+            raise RuntimeError(f"oracle forces status {st}")
+        return F, E, fe, st
+
+    def forces_rows(self, x, rows, x_list=None, step=0):
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        xl = x if x_list is None else np.ascontiguousarray(x_list, dtype=np.float64)
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        F = np.zeros((len(rows), 3))
+        st = L.orc_forces_rows(C.byref(self.s), C.byref(self.p), _ptr(x), _ptr(xl), int(step),
+                               _ptr(rows), len(rows), _ptr(F))
+        if st != OK:
+            raise RuntimeError(f"oracle forces_rows status {st}")
+        return F
+
+    def run(self, x, n_steps, step0=0, energy_every=0):
+        """Integrate n_steps from step0; returns (x_new, E records, f records, status)."""
+        L = lib()
+        x = np.array(x, dtype=np.float64, copy=True, order="C")
+        nrec_max = 0 if energy_every <= 0 else (n_steps // energy_every + 2)
+        E = np.zeros((max(nrec_max, 1), self.sysm.n_traj, NTERMS))
+        fe = np.zeros((max(nrec_max, 1), self.sysm.n_traj))
+        nrec = C.c_int64(0)
+        st = L.orc_run(C.byref(self.s), C.byref(self.p), _ptr(x), int(step0), int(n_steps),
+                       int(energy_every), _ptr(E), _ptr(fe), nrec_max, C.byref(nrec))
+        return x, E[:nrec.value], fe[:nrec.value], st
+
+
+# -- scalar helpers ------------------------------------------------------
+
+def philox(ctr, key):
+    out = np.zeros(4, dtype=np.uint32)
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(w):
+    return lib().orc_uniform(int(w) & 0xFFFFFFFF)
+
+
+def gauss3(seed, local, stream, step):
+    g = np.zeros(3)
+    lib().orc_gauss3(int(seed), int(local), int(stream), int(step), _ptr(g))
+    return g
+
+
+def fene(r, r0, k, R0):
+    d = C.c_double(0.0)
+    b = C.c_int(0)
+    e = lib().orc_fene(r, r0, k, R0, C.byref(d), C.byref(b))
+    return e, d.value, bool(b.value)
+
+
+def native(r, r0, eps):
+    d = C.c_double(0.0)
+    e = lib().orc_native(r, r0, eps, C.byref(d))
+    return e, d.value
+
+
+def repulsive(r, sigma, eps):
+    d = C.c_double(0.0)
+    e = lib().orc_repulsive(r, sigma, eps, C.byref(d))
+    return e, d.value
