@@ -1,0 +1,261 @@
+/*
+ * libsop -- overdamped Langevin dynamics of the Self Organized Polymer (SOP)
+ * model on AMD Instinct MI355X (gfx950).
+ *
+ * The library advances r_i(t+h) = r_i(t) + f_i h/xi + g_i sqrt(2 kB T h/xi)
+ * (first-order Ermak-McCammon scheme: paper Eq. 2, Algorithm 7) for many
+ * residues at once, where f_i = -grad_i V with V the SOP potential of Eq. 1:
+ *   - FENE backbone bonds  -(k R0^2/2) ln(1 - (r - r0)^2 / R0^2),
+ *   - native contacts      eps_h [(r0/r)^12 - 2 (r0/r)^6],
+ *   - every other pair of a trajectory (i,i+2 included) eps_l (sigma/r)^6,
+ *     evaluated over a Verlet list of pairs closer than r_list, rebuilt every
+ *     list_every steps (Section III.A, Algorithm 3),
+ * and g_i are standard Gaussians (Section III.C) drawn by Box-Muller from a
+ * counter-based Philox4x32-10 stream.  Optional external terms carry the
+ * pulling and indentation protocols (Section IV.B): a harmonic cantilever on
+ * chosen residues and a spherical tip moving at constant velocity.
+ *
+ * Units are the caller's; the reference workloads use kcal/mol, Angstrom and
+ * a reduced time tau.  Positions are held on the device in single precision
+ * as a compensated pair (hi, lo) with x = hi + lo; forces are single
+ * precision; energy and virial sums are double precision.
+ *
+ * Conventions for every call:
+ *   - Pointers named *host* or documented as host arrays are host memory,
+ *     borrowed for the duration of the call and copied.  The workspace is
+ *     device memory owned by the caller.
+ *   - Every call returns a sop_status; nothing throws across the ABI.  On
+ *     failure, sop_last_error() describes the cause.
+ *   - A context is not thread safe; use one context per host thread.  All
+ *     device work of a context runs in order on the stream given to
+ *     sop_create (0 means the default stream).
+ *   - Device-side failures (broken bond, list overflow, non-finite values,
+ *     tip penetration) are detected asynchronously.  They are reported by the
+ *     next synchronizing call (sop_synchronize, sop_get_*) and stay reported
+ *     ("sticky") until sop_set_coordinates loads new coordinates.
+ */
+#ifndef SOP_H
+#define SOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sop_status {
+    SOP_OK = 0,
+    SOP_E_ARG = -1,           /* invalid argument */
+    SOP_E_STATE = -2,         /* call made in the wrong order */
+    SOP_E_WORKSPACE = -3,     /* workspace missing, misaligned or too small */
+    SOP_E_HIP = -4,           /* HIP runtime error */
+    SOP_E_FENE = -5,          /* a bond stretched to |r - r0| >= R0 */
+    SOP_E_LIST_OVERFLOW = -6, /* a residue has more list partners than the capacity */
+    SOP_E_NONFINITE = -7,     /* a force or position became NaN or infinite */
+    SOP_E_TIP = -8            /* a residue reached the tip surface */
+} sop_status;
+
+/* Energy terms recorded per trajectory (double precision). */
+enum {
+    SOP_TERM_FENE = 0,
+    SOP_TERM_NATIVE = 1,
+    SOP_TERM_REPULSIVE = 2,
+    SOP_TERM_EXTERNAL = 3,
+    SOP_TERM_VIRIAL = 4, /* -sum over bonded, native and listed pairs of r dV/dr */
+    SOP_NTERMS = 5
+};
+
+/* Force-field, thermostat and list parameters (Eq. 1, Eq. 2, Algorithm 3). */
+typedef struct sop_params {
+    double k_fene;         /* FENE spring constant k */
+    double R0;             /* FENE tolerance R0 */
+    double eps_h;          /* native contact depth */
+    double eps_l;          /* repulsion strength (eps_r in Eq. 1) */
+    double sigma;          /* repulsion range */
+    double r_list;         /* Verlet-list cutoff: pairs with r < r_list at a rebuild */
+    double kBT;            /* thermal energy */
+    double zeta;           /* friction coefficient (xi) */
+    double h;              /* time step */
+    int32_t list_every;    /* rebuild period in steps (> 0) */
+    int32_t list_capacity; /* list partners per residue; 0 selects 256 */
+    uint64_t seed;         /* Philox key (low word, high word) */
+} sop_params;
+
+typedef struct sop_ctx sop_ctx;
+
+/* ---- lifetime ----------------------------------------------------------- */
+
+/* Create a context.  `hip_stream` is a hipStream_t borrowed for the context's
+ * lifetime (0 = default stream).  Host only: touches no device. */
+sop_status sop_create(const sop_params *params, void *hip_stream, sop_ctx **out);
+
+/* Destroy a context.  Frees host memory and library-owned streams and
+ * graphs; the caller's workspace is not freed. */
+sop_status sop_destroy(sop_ctx *ctx);
+
+/* ---- topology (Algorithm 2's P_p / PairsMap, built once on the host) ------ */
+
+/*
+ * Load n_traj independent trajectories ("systems") stored back to back:
+ * trajectory t owns global residues [res_offsets[t], res_offsets[t+1]).
+ *   res_offsets  int64[n_traj+1], res_offsets[0] = 0, non-decreasing
+ *   stream_ids   uint32[n_traj] Philox stream of each trajectory, or NULL for
+ *                0..n_traj-1
+ *   bonds        int32[2*n_bonds], pairs of global residue ids (FENE terms)
+ *   bond_r0      double[n_bonds], reference lengths r0 > 0
+ *   natives      int32[2*n_native], pairs of global residue ids (12-6 terms)
+ *   native_r0    double[n_native], reference distances r0 > 0
+ *   fixed        uint8[n_res] (nonzero = residue never moves) or NULL
+ * Returns SOP_E_ARG for an id out of range, a pair spanning two trajectories,
+ * a self pair, a duplicate pair, a pair both bonded and native, r0 <= 0, or
+ * more than 4095 bonds on one residue.  Host only.  Invalidates any bound
+ * workspace.
+ */
+sop_status sop_load_topology(sop_ctx *ctx, int32_t n_traj, const int64_t *res_offsets,
+                             const uint32_t *stream_ids, int64_t n_bonds, const int32_t *bonds,
+                             const double *bond_r0, int64_t n_native, const int32_t *natives,
+                             const double *native_r0, const uint8_t *fixed);
+
+/*
+ * Harmonic cantilever on one residue of trajectory `traj`:
+ * V = (kappa/2) |A(t) - r_c|^2, A(t) = anchor0 + v t, t = step * h.
+ * The reported external force of the trajectory adds kappa (A - r_c).v/|v|
+ * (or kappa |A - r_c| when v = 0).  At most one cantilever per residue.
+ * Call after sop_load_topology and before sop_bind_workspace.  Host only.
+ */
+sop_status sop_set_pulling(sop_ctx *ctx, int32_t traj, int64_t residue, double kappa,
+                           const double anchor0[3], const double v[3]);
+
+/*
+ * Spherical tip acting on every residue: with s = |r_i - T(t)| - radius and
+ * T(t) = c0 + v t, V = eps (sigma/s)^6; s <= 0 is the SOP_E_TIP error.  The
+ * reported external force adds sum_i f_i.v/|v| over the trajectory's
+ * residues.  radius < 0 removes the tip.  Call before sop_bind_workspace.
+ */
+sop_status sop_set_tip(sop_ctx *ctx, double radius, double eps, double sigma, const double c0[3],
+                       const double v[3]);
+
+/* ---- schedule ------------------------------------------------------------ */
+
+/*
+ * Lanes of a 64-wide wavefront that cooperate on one residue's pair loops
+ * (1, 2, 4, 8 or 16; 0 selects a default from the system size).  Changes
+ * the list layout; call before sop_bind_workspace.
+ */
+sop_status sop_set_lanes(sop_ctx *ctx, int32_t lanes);
+
+/* Lanes per residue in effect (after a topology is loaded). */
+sop_status sop_get_lanes(const sop_ctx *ctx, int32_t *lanes);
+
+/*
+ * HIP graphs: 0 launches every kernel from the host; k > 0 captures k whole
+ * list periods (k rebuilds and k*list_every steps) per graph and replays it
+ * while that many steps remain from a period start.  Graphs are used only when
+ * the energy interval is 0 or a multiple of k*list_every.  Default: 1.
+ */
+sop_status sop_set_graph_steps(sop_ctx *ctx, int32_t k);
+
+/* Record energies every k steps (k = 0: never).  Energies of step n are
+ * those of the configuration the forces of step n use, before its update. */
+sop_status sop_set_energy_interval(sop_ctx *ctx, int64_t k);
+
+/* ---- workspace ----------------------------------------------------------- */
+
+/* Bytes of device memory the bound workspace must provide (256-byte aligned
+ * start).  Depends on the topology, the list capacity and the lanes. */
+sop_status sop_workspace_size(const sop_ctx *ctx, size_t *bytes);
+
+/*
+ * Bind caller-owned device memory (e.g. a torch uint8 CUDA tensor) that must
+ * outlive the context or the next bind.  Uploads the topology into it.
+ * Coordinates must be set again after a bind.
+ */
+sop_status sop_bind_workspace(sop_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* ---- coordinates and steps ------------------------------------------------ */
+
+/* Load positions from host double[3*n_res] (x0,y0,z0,x1,...), split into the
+ * device's compensated single-precision pair.  Clears sticky errors and
+ * marks the Verlet list stale.  Synchronous with respect to the host. */
+sop_status sop_set_coordinates(sop_ctx *ctx, const double *xyz_host);
+
+/* Copy positions (hi + lo, double) into host double[3*n_res].  Synchronizes. */
+sop_status sop_get_coordinates(sop_ctx *ctx, double *xyz_host);
+
+/* Step counter n (time t_n = n h) that seeds the noise and moves the
+ * external anchors.  Setting it marks the list stale. */
+sop_status sop_set_step(sop_ctx *ctx, int64_t step);
+sop_status sop_get_step(const sop_ctx *ctx, int64_t *step);
+
+/*
+ * Advance n_steps steps, asynchronously on the context's stream.  Before the
+ * forces of step n the Verlet list is rebuilt when n % list_every == 0 or
+ * when it is stale.
+ */
+sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
+
+/*
+ * Same as sop_step, launched kernel by kernel with HIP events on the
+ * context's stream around each list rebuild and each fused step kernel;
+ * waits after every step.  ms_out[0] = mean duration of the fused step
+ * kernel, ms_out[1] = mean duration of one list rebuild (all its kernels),
+ * ms_out[2] is reserved (0).  For measurement only.
+ */
+sop_status sop_step_timed(sop_ctx *ctx, int64_t n_steps, double *ms_out);
+
+/* ---- pair list ------------------------------------------------------------- */
+
+/* Rebuild the Verlet list from the current positions now. */
+sop_status sop_build_pairlist(sop_ctx *ctx);
+
+/*
+ * Copy the current list as the sorted set of pairs (i < j), lexicographic,
+ * into host int32[2*cap].  *n_pairs receives the list size; if it exceeds
+ * cap, nothing is copied and SOP_E_ARG is returned.  Synchronizes.
+ */
+sop_status sop_get_pairlist(sop_ctx *ctx, int64_t cap, int32_t *ij_host, int64_t *n_pairs);
+
+/* ---- forces and energies ---------------------------------------------------- */
+
+/*
+ * Forces and energies at the current positions and step without moving
+ * anything (the list is rebuilt first only if stale).  f_host: double[3*n_res]
+ * or NULL; energies_host: double[n_traj*SOP_NTERMS] or NULL; f_ext_host:
+ * double[n_traj] or NULL (reported external force).  Synchronizes.
+ */
+sop_status sop_compute_forces(sop_ctx *ctx, double *f_host, double *energies_host,
+                              double *f_ext_host);
+
+/* Latest recorded energies, double[n_traj*SOP_NTERMS], and the step they
+ * belong to (-1 if none yet).  Synchronizes. */
+sop_status sop_get_energies(sop_ctx *ctx, double *energies_host, int64_t *step);
+
+/* Latest recorded external-force reports, double[n_traj].  Synchronizes. */
+sop_status sop_get_external_force(sop_ctx *ctx, double *f_ext_host);
+
+/*
+ * The random numbers of Section III.C as the step kernel draws them for step
+ * `step`: per residue the four Philox4x32-10 words (key = seed, counter =
+ * (index inside the trajectory, stream id, step low word, step high word))
+ * into words_host uint32[4*n_res], and the three Box-Muller Gaussians
+ * (single precision, widened) into g_host double[3*n_res]; either may be
+ * NULL.  Does not advance anything.  Synchronizes.
+ */
+sop_status sop_sample_noise(sop_ctx *ctx, int64_t step, uint32_t *words_host, double *g_host);
+
+/* ---- synchronization and errors ----------------------------------------------- */
+
+/* Wait for the context's stream and return any device-side error. */
+sop_status sop_synchronize(sop_ctx *ctx);
+
+const char *sop_status_string(sop_status status);
+
+/* Description of the last failure of this context ("" if none). */
+const char *sop_last_error(const sop_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOP_H */

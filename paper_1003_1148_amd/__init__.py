@@ -1,0 +1,17 @@
+"""MI355X-native overdamped Langevin dynamics of the SOP protein model.
+
+The compute path is the HIP library libsop.so (C ABI in include/sop.h);
+this package holds its kernels (csrc/), its build script and a thin ctypes
+binding.
+"""
+from ._sop import (  # noqa: F401
+    Context,
+    SopError,
+    NTERMS,
+    TERM_NAMES,
+    LIB_PATH,
+    declared_functions,
+    from_system,
+    lib,
+    status_string,
+)

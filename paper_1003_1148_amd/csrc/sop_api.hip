@@ -1,0 +1,974 @@
+// Host side of the C ABI: topology -> per-residue CSR (Algorithm 2's P_p and
+// PairsMap, bonds and natives in both directions), workspace layout, the
+// step driver with HIP-graph replays of whole list periods, and the
+// asynchronous device error word.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sop_internal.hpp"
+
+using namespace sop;
+
+struct sop_ctx {
+    sop_params p{};
+    hipStream_t stream = nullptr;
+
+    // topology (host copies)
+    int n_traj = 0;
+    long long n_res = 0;
+    std::vector<long long> res_offsets;
+    std::vector<unsigned> stream_ids;
+    std::vector<int2> trow;
+    std::vector<float2> tent;
+    std::vector<int> traj_lo, traj_hi, traj_of, local;
+    std::vector<unsigned char> fixed;
+    std::vector<PullDev> pulls;
+    std::vector<int> pull_slot;
+    TipDev tip{};
+
+    // schedule
+    int lanes_req = 0, lanes = 1, cap = 256;
+    int graph_steps = 1;
+    long long energy_every = 0;
+
+    // device state
+    bool topo = false, bound = false, coords = false, list_valid = false;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    DevBufs b{};
+    GridDev grid{};
+    int n_cells_cap = 0;
+    int cur = 0;
+    long long step = 0;
+    long long energy_step = -1;
+    unsigned sticky = 0;
+    std::string last_error;
+
+    // graphs over whole list periods, keyed by [layer parity][energy at first step]
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graphs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+};
+
+namespace {
+
+sop_status fail(sop_ctx *c, sop_status s, const std::string &msg)
+{
+    if (c)
+        c->last_error = msg;
+    return s;
+}
+
+sop_status hip_fail(sop_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, SOP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                 \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess)                              \
+            return hip_fail((ctx), e_, #expr);             \
+    } while (0)
+
+sop_status status_from_bits(unsigned bits)
+{
+    if (bits & ERR_FENE)
+        return SOP_E_FENE;
+    if (bits & ERR_OVERFLOW)
+        return SOP_E_LIST_OVERFLOW;
+    if (bits & ERR_TIP)
+        return SOP_E_TIP;
+    if (bits & ERR_NONFINITE)
+        return SOP_E_NONFINITE;
+    return SOP_OK;
+}
+
+const char *bits_message(unsigned bits)
+{
+    if (bits & ERR_FENE)
+        return "a FENE bond reached |r - r0| >= R0";
+    if (bits & ERR_OVERFLOW)
+        return "a residue has more list partners than the list capacity";
+    if (bits & ERR_TIP)
+        return "a residue reached the tip surface";
+    if (bits & ERR_NONFINITE)
+        return "a force or position became non-finite";
+    return "";
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout: returns total bytes; fills pointers when base != null.
+size_t layout(const sop_ctx *c, char *base, DevBufs *b)
+{
+    const size_t n = (size_t)c->n_res;
+    const size_t T = (size_t)c->n_traj;
+    const int G = 64 / c->lanes;
+    const size_t list_elems = ((n + G - 1) / G) * (size_t)G * (size_t)c->cap;
+    const size_t ncell = (size_t)c->n_cells_cap;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return p;
+    };
+    DevBufs d{};
+    d.hi[0] = (float4 *)take(n * sizeof(float4));
+    d.hi[1] = (float4 *)take(n * sizeof(float4));
+    d.lo[0] = (float4 *)take(n * sizeof(float4));
+    d.lo[1] = (float4 *)take(n * sizeof(float4));
+    d.trow = (int2 *)take(n * sizeof(int2));
+    d.tent = (float2 *)take(c->tent.size() * sizeof(float2));
+    d.list = (int *)take(list_elems * sizeof(int));
+    d.list_cnt = (int *)take(n * sizeof(int));
+    d.cell_of = (int *)take(n * sizeof(int));
+    d.cell_slot = (int *)take(n * sizeof(int));
+    d.cell_count = (int *)take(ncell * sizeof(int));
+    d.cell_start = (int *)take((ncell + 1) * sizeof(int));
+    d.cpos = (float4 *)take(n * sizeof(float4));
+    d.traj_lo = (int *)take(n * sizeof(int));
+    d.traj_hi = (int *)take(n * sizeof(int));
+    d.pull_slot = (int *)take(n * sizeof(int));
+    d.pulls = (PullDev *)take(std::max<size_t>(c->pulls.size(), 1) * sizeof(PullDev));
+    d.stream_ids = (unsigned *)take(T * sizeof(unsigned));
+    d.res_offsets = (long long *)take((T + 1) * sizeof(long long));
+    d.res_energy = (double *)take(n * RES_E * sizeof(double));
+    d.energy = (double *)take(T * SOP_NTERMS * sizeof(double));
+    d.f_ext = (double *)take(T * sizeof(double));
+    d.fout = (float4 *)take(n * sizeof(float4));
+    d.step_base = (long long *)take(sizeof(long long));
+    d.step_next = (long long *)take(sizeof(long long));
+    d.err = (unsigned *)take(sizeof(unsigned));
+    if (b)
+        *b = d;
+    return off;
+}
+
+int default_lanes(long long n)
+{
+    // enough wavefronts to cover the 1024 SIMDs several times over
+    if (n >= 262144)
+        return 2;
+    if (n >= 65536)
+        return 4;
+    if (n >= 8192)
+        return 8;
+    return 16;
+}
+
+void destroy_graphs(sop_ctx *c)
+{
+    for (auto &row : c->graphs)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+StepConsts step_consts(const sop_ctx *c)
+{
+    StepConsts k{};
+    k.k_fene = (float)c->p.k_fene;
+    k.R0sq = (float)(c->p.R0 * c->p.R0);
+    k.eps_h = (float)c->p.eps_h;
+    k.eps_l = (float)c->p.eps_l;
+    k.sigma2 = (float)(c->p.sigma * c->p.sigma);
+    k.c_drift = (float)(c->p.h / c->p.zeta);
+    k.c_noise = (float)std::sqrt(2.0 * c->p.kBT * c->p.h / c->p.zeta);
+    k.key0 = (unsigned)(c->p.seed & 0xffffffffu);
+    k.key1 = (unsigned)(c->p.seed >> 32);
+    k.h = c->p.h;
+    return k;
+}
+
+float list_rc2(const sop_ctx *c) { return (float)(c->p.r_list * c->p.r_list); }
+
+// Cell edge slightly above the cutoff so that any pair passing the
+// single-precision predicate lies in adjacent cells despite rounding of the
+// cell index.
+float cell_edge(const sop_ctx *c) { return (float)(c->p.r_list * 1.002 + 0.05); }
+
+void set_grid(sop_ctx *c, const double *xyz)
+{
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (long long i = 0; i < c->n_res; ++i)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], xyz[3 * i + a]);
+            hi[a] = std::max(hi[a], xyz[3 * i + a]);
+        }
+    const double e = cell_edge(c);
+    long long g[3];
+    for (int a = 0; a < 3; ++a) {
+        double ext = c->n_res ? hi[a] - lo[a] : 0.0;
+        g[a] = std::max<long long>(3, (long long)std::ceil(ext / e) + 2);
+    }
+    while (g[0] * g[1] * g[2] > c->n_cells_cap) {
+        int m = 0;
+        for (int a = 1; a < 3; ++a)
+            if (g[a] > g[m])
+                m = a;
+        g[m] = std::max<long long>(3, (g[m] * 3) / 4);
+        if (g[0] == 3 && g[1] == 3 && g[2] == 3)
+            break;
+    }
+    c->grid.inv_cell = 1.0f / (float)e;
+    c->grid.gx = (int)g[0];
+    c->grid.gy = (int)g[1];
+    c->grid.gz = (int)g[2];
+    c->grid.n_cells = (int)(g[0] * g[1] * g[2]);
+}
+
+sop_status check_device_errors(sop_ctx *c)
+{
+    if (!c->bound)
+        return SOP_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned bits = 0;
+    HIP_TRY(c, hipMemcpy(&bits, c->b.err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    c->sticky |= bits;
+    if (c->sticky)
+        return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
+    return SOP_OK;
+}
+
+sop_status need_ready(sop_ctx *c)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (!c->topo)
+        return fail(c, SOP_E_STATE, "no topology loaded");
+    if (!c->bound)
+        return fail(c, SOP_E_STATE, "no workspace bound");
+    if (!c->coords)
+        return fail(c, SOP_E_STATE, "no coordinates set");
+    return SOP_OK;
+}
+
+void rebuild(sop_ctx *c, hipStream_t s, bool advance)
+{
+    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, c->grid, list_rc2(c), s, advance,
+                   c->p.list_every);
+}
+
+void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy)
+{
+    launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+                c->pulls.empty() ? 0 : 1, energy, 0, base, off, s);
+    if (energy)
+        launch_reduce_energy(c->b, c->n_traj, s);
+}
+
+// Capture `periods` list periods (rebuild + list_every steps each) starting at
+// layer parity `par`; energies are recorded at the first step when `energy`.
+sop_status capture_graph(sop_ctx *c, int par, int energy)
+{
+    if (!c->cap_stream)
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int saved = c->cur;
+    c->cur = par;
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    for (int q = 0; q < c->graph_steps; ++q) {
+        rebuild(c, c->cap_stream, true);
+        for (int k = 0; k < c->p.list_every; ++k) {
+            one_step(c, c->cap_stream, c->b.step_base, k, energy && q == 0 && k == 0);
+            c->cur ^= 1;
+        }
+    }
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->cur = saved;
+    if (e != hipSuccess)
+        return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return hip_fail(c, e, "hipGraphInstantiate");
+    c->graphs[par][energy] = ex;
+    return SOP_OK;
+}
+
+bool valid_pair(const sop_ctx *c, long long i, long long j)
+{
+    if (i < 0 || j < 0 || i >= c->n_res || j >= c->n_res || i == j)
+        return false;
+    return c->traj_of[i] == c->traj_of[j];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sop_status_string(sop_status s)
+{
+    switch (s) {
+    case SOP_OK: return "ok";
+    case SOP_E_ARG: return "invalid argument";
+    case SOP_E_STATE: return "call out of order";
+    case SOP_E_WORKSPACE: return "workspace missing or too small";
+    case SOP_E_HIP: return "HIP runtime error";
+    case SOP_E_FENE: return "FENE bond broken";
+    case SOP_E_LIST_OVERFLOW: return "pair list overflow";
+    case SOP_E_NONFINITE: return "non-finite force or position";
+    case SOP_E_TIP: return "residue reached the tip surface";
+    }
+    return "unknown status";
+}
+
+const char *sop_last_error(const sop_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+
+sop_status sop_create(const sop_params *params, void *hip_stream, sop_ctx **out)
+{
+    if (!params || !out)
+        return SOP_E_ARG;
+    const sop_params &p = *params;
+    const bool ok = p.k_fene > 0 && p.R0 > 0 && p.eps_h >= 0 && p.eps_l >= 0 && p.sigma > 0 &&
+                    p.r_list > 0 && p.kBT >= 0 && p.zeta > 0 && p.h > 0 && p.list_every > 0 &&
+                    p.list_capacity >= 0 && std::isfinite(p.r_list) && std::isfinite(p.h);
+    if (!ok)
+        return SOP_E_ARG;
+    sop_ctx *c = new (std::nothrow) sop_ctx();
+    if (!c)
+        return SOP_E_ARG;
+    c->p = p;
+    c->stream = (hipStream_t)hip_stream;
+    int cap = p.list_capacity ? p.list_capacity : 256;
+    c->cap = ((cap + 15) / 16) * 16;
+    *out = c;
+    return SOP_OK;
+}
+
+sop_status sop_destroy(sop_ctx *c)
+{
+    if (!c)
+        return SOP_E_ARG;
+    destroy_graphs(c);
+    if (c->cap_stream)
+        (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return SOP_OK;
+}
+
+sop_status sop_load_topology(sop_ctx *c, int32_t n_traj, const int64_t *res_offsets,
+                             const uint32_t *stream_ids, int64_t n_bonds, const int32_t *bonds,
+                             const double *bond_r0, int64_t n_native, const int32_t *natives,
+                             const double *native_r0, const uint8_t *fixed)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (n_traj <= 0 || !res_offsets || n_bonds < 0 || n_native < 0 ||
+        (n_bonds > 0 && (!bonds || !bond_r0)) || (n_native > 0 && (!natives || !native_r0)))
+        return fail(c, SOP_E_ARG, "bad topology arguments");
+    if (res_offsets[0] != 0)
+        return fail(c, SOP_E_ARG, "res_offsets[0] must be 0");
+    for (int t = 0; t < n_traj; ++t)
+        if (res_offsets[t + 1] < res_offsets[t])
+            return fail(c, SOP_E_ARG, "res_offsets must be non-decreasing");
+    const long long n = res_offsets[n_traj];
+    if (n <= 0 || n >= (1LL << 31) - 64)
+        return fail(c, SOP_E_ARG, "residue count out of range");
+
+    c->topo = false;
+    c->bound = false;
+    c->coords = false;
+    destroy_graphs(c);
+    c->n_traj = n_traj;
+    c->n_res = n;
+    c->res_offsets.assign(res_offsets, res_offsets + n_traj + 1);
+    c->stream_ids.resize(n_traj);
+    for (int t = 0; t < n_traj; ++t)
+        c->stream_ids[t] = stream_ids ? stream_ids[t] : (unsigned)t;
+    c->traj_of.assign(n, 0);
+    c->traj_lo.assign(n, 0);
+    c->traj_hi.assign(n, 0);
+    c->local.assign(n, 0);
+    for (int t = 0; t < n_traj; ++t)
+        for (long long i = res_offsets[t]; i < res_offsets[t + 1]; ++i) {
+            c->traj_of[i] = t;
+            c->traj_lo[i] = (int)res_offsets[t];
+            c->traj_hi[i] = (int)res_offsets[t + 1];
+            c->local[i] = (int)(i - res_offsets[t]);
+        }
+    c->fixed.assign(n, 0);
+    if (fixed)
+        for (long long i = 0; i < n; ++i)
+            c->fixed[i] = fixed[i] ? 1 : 0;
+
+    // validate pairs: range, same trajectory, no self/duplicate, r0 > 0
+    std::vector<std::pair<long long, int>> keys;  // (i*n + j, kind)
+    keys.reserve((size_t)(n_bonds + n_native));
+    for (int kind = 0; kind < 2; ++kind) {
+        const long long m = kind ? n_native : n_bonds;
+        const int32_t *pr = kind ? natives : bonds;
+        const double *r0 = kind ? native_r0 : bond_r0;
+        for (long long k = 0; k < m; ++k) {
+            long long i = pr[2 * k], j = pr[2 * k + 1];
+            if (!valid_pair(c, i, j))
+                return fail(c, SOP_E_ARG, (kind ? "native " : "bond ") + std::to_string(k) +
+                                              ": index out of range, self pair, or pair across trajectories");
+            if (!(r0[k] > 0.0) || !std::isfinite(r0[k]))
+                return fail(c, SOP_E_ARG, (kind ? "native " : "bond ") + std::to_string(k) + ": r0 <= 0");
+            if (i > j)
+                std::swap(i, j);
+            keys.push_back({i * n + j, kind});
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t k = 1; k < keys.size(); ++k)
+        if (keys[k].first == keys[k - 1].first)
+            return fail(c, SOP_E_ARG, keys[k].second != keys[k - 1].second
+                                          ? "a pair is both bonded and native"
+                                          : "duplicate pair");
+
+    // per-residue rows: bonds then natives, partners ascending
+    std::vector<std::vector<std::pair<int, float>>> rb(n), rn(n);
+    for (long long k = 0; k < n_bonds; ++k) {
+        int i = bonds[2 * k], j = bonds[2 * k + 1];
+        rb[i].push_back({j, (float)bond_r0[k]});
+        rb[j].push_back({i, (float)bond_r0[k]});
+    }
+    for (long long k = 0; k < n_native; ++k) {
+        int i = natives[2 * k], j = natives[2 * k + 1];
+        rn[i].push_back({j, (float)native_r0[k]});
+        rn[j].push_back({i, (float)native_r0[k]});
+    }
+    c->trow.assign(n, int2{0, 0});
+    c->tent.clear();
+    c->tent.reserve((size_t)(2 * (n_bonds + n_native)));
+    for (long long i = 0; i < n; ++i) {
+        std::sort(rb[i].begin(), rb[i].end());
+        std::sort(rn[i].begin(), rn[i].end());
+        if (rb[i].size() > 4095 || rn[i].size() >= (1u << 19))
+            return fail(c, SOP_E_ARG, "too many bonds or natives on residue " + std::to_string(i));
+        c->trow[i] = int2{(int)c->tent.size(), (int)(rb[i].size() | (rn[i].size() << 12))};
+        for (auto &e : rb[i]) {
+            int bits = e.first;
+            float f;
+            std::memcpy(&f, &bits, 4);
+            c->tent.push_back(float2{f, e.second});
+        }
+        for (auto &e : rn[i]) {
+            int bits = e.first;
+            float f;
+            std::memcpy(&f, &bits, 4);
+            c->tent.push_back(float2{f, e.second});
+        }
+    }
+    c->pulls.clear();
+    c->pull_slot.assign(n, -1);
+    c->tip = TipDev{};
+    c->lanes = c->lanes_req ? c->lanes_req : default_lanes(n);
+    c->n_cells_cap = (int)std::min<long long>(std::max<long long>(4 * n, 4096), 1LL << 22);
+    c->topo = true;
+    return SOP_OK;
+}
+
+sop_status sop_set_pulling(sop_ctx *c, int32_t traj, int64_t residue, double kappa,
+                           const double anchor0[3], const double v[3])
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (!c->topo)
+        return fail(c, SOP_E_STATE, "load a topology first");
+    if (c->bound)
+        return fail(c, SOP_E_STATE, "set protocols before binding the workspace");
+    if (traj < 0 || traj >= c->n_traj || residue < c->res_offsets[traj] ||
+        residue >= c->res_offsets[traj + 1] || !anchor0 || !v || !(kappa >= 0))
+        return fail(c, SOP_E_ARG, "bad cantilever arguments");
+    if (c->pull_slot[residue] >= 0)
+        return fail(c, SOP_E_ARG, "residue already has a cantilever");
+    PullDev pd{};
+    double vv = 0;
+    for (int a = 0; a < 3; ++a) {
+        pd.anchor0[a] = anchor0[a];
+        pd.v[a] = v[a];
+        vv += v[a] * v[a];
+    }
+    pd.has_dir = vv > 0 ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        pd.vhat[a] = vv > 0 ? v[a] / std::sqrt(vv) : 0.0;
+    pd.kappa = kappa;
+    pd.residue = (int)residue;
+    c->pull_slot[residue] = (int)c->pulls.size();
+    c->pulls.push_back(pd);
+    return SOP_OK;
+}
+
+sop_status sop_set_tip(sop_ctx *c, double radius, double eps, double sigma, const double c0[3],
+                       const double v[3])
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (!c->topo)
+        return fail(c, SOP_E_STATE, "load a topology first");
+    if (c->bound)
+        return fail(c, SOP_E_STATE, "set protocols before binding the workspace");
+    if (radius < 0) {
+        c->tip = TipDev{};
+        return SOP_OK;
+    }
+    if (!c0 || !v || !(sigma > 0) || !(eps >= 0))
+        return fail(c, SOP_E_ARG, "bad tip arguments");
+    TipDev t{};
+    double vv = 0;
+    for (int a = 0; a < 3; ++a) {
+        t.c0[a] = c0[a];
+        t.v[a] = v[a];
+        vv += v[a] * v[a];
+    }
+    t.has_dir = vv > 0 ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        t.vhat[a] = vv > 0 ? v[a] / std::sqrt(vv) : 0.0;
+    t.radius = radius;
+    t.eps = eps;
+    t.sigma = sigma;
+    t.on = 1;
+    c->tip = t;
+    return SOP_OK;
+}
+
+sop_status sop_set_lanes(sop_ctx *c, int32_t lanes)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
+        return fail(c, SOP_E_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
+    if (c->bound)
+        return fail(c, SOP_E_STATE, "set lanes before binding the workspace");
+    c->lanes_req = lanes;
+    if (c->topo)
+        c->lanes = lanes ? lanes : default_lanes(c->n_res);
+    return SOP_OK;
+}
+
+sop_status sop_get_lanes(const sop_ctx *c, int32_t *lanes)
+{
+    if (!c || !lanes)
+        return SOP_E_ARG;
+    if (!c->topo)
+        return SOP_E_STATE;
+    *lanes = c->lanes;
+    return SOP_OK;
+}
+
+sop_status sop_set_graph_steps(sop_ctx *c, int32_t k)
+{
+    if (!c || k < 0)
+        return SOP_E_ARG;
+    c->graph_steps = k;
+    return SOP_OK;
+}
+
+sop_status sop_set_energy_interval(sop_ctx *c, int64_t k)
+{
+    if (!c || k < 0)
+        return SOP_E_ARG;
+    c->energy_every = k;
+    return SOP_OK;
+}
+
+sop_status sop_workspace_size(const sop_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes)
+        return SOP_E_ARG;
+    if (!c->topo)
+        return SOP_E_STATE;
+    *bytes = layout(c, nullptr, nullptr);
+    return SOP_OK;
+}
+
+sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (!c->topo)
+        return fail(c, SOP_E_STATE, "load a topology first");
+    const size_t need = layout(c, nullptr, nullptr);
+    if (!dev || ((uintptr_t)dev & 255) || bytes < need)
+        return fail(c, SOP_E_WORKSPACE, "workspace null, not 256-byte aligned, or smaller than " +
+                                            std::to_string(need) + " bytes");
+    destroy_graphs(c);
+    c->bound = false;
+    c->coords = false;
+    c->list_valid = false;
+    c->ws = dev;
+    c->ws_bytes = bytes;
+    layout(c, (char *)dev, &c->b);
+    const DevBufs &b = c->b;
+    const size_t n = (size_t)c->n_res;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, hipMemcpyAsync(b.trow, c->trow.data(), n * sizeof(int2), hipMemcpyHostToDevice, s));
+    if (!c->tent.empty())
+        HIP_TRY(c, hipMemcpyAsync(b.tent, c->tent.data(), c->tent.size() * sizeof(float2),
+                                  hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b.traj_lo, c->traj_lo.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b.traj_hi, c->traj_hi.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b.pull_slot, c->pull_slot.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    if (!c->pulls.empty())
+        HIP_TRY(c, hipMemcpyAsync(b.pulls, c->pulls.data(), c->pulls.size() * sizeof(PullDev),
+                                  hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b.stream_ids, c->stream_ids.data(), c->n_traj * sizeof(unsigned),
+                              hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b.res_offsets, c->res_offsets.data(), (c->n_traj + 1) * sizeof(long long),
+                              hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(b.list_cnt, 0, n * sizeof(int), s));
+    HIP_TRY(c, hipMemsetAsync(b.res_energy, 0, n * RES_E * sizeof(double), s));
+    HIP_TRY(c, hipMemsetAsync(b.energy, 0, (size_t)c->n_traj * SOP_NTERMS * sizeof(double), s));
+    HIP_TRY(c, hipMemsetAsync(b.f_ext, 0, (size_t)c->n_traj * sizeof(double), s));
+    HIP_TRY(c, hipMemsetAsync(b.err, 0, sizeof(unsigned), s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->bound = true;
+    c->sticky = 0;
+    c->energy_step = -1;
+    return SOP_OK;
+}
+
+sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
+{
+    if (!c || !xyz)
+        return SOP_E_ARG;
+    if (!c->topo || !c->bound)
+        return fail(c, SOP_E_STATE, "load a topology and bind a workspace first");
+    const long long n = c->n_res;
+    for (long long k = 0; k < 3 * n; ++k)
+        if (!std::isfinite(xyz[k]))
+            return fail(c, SOP_E_ARG, "non-finite coordinate");
+    std::vector<float4> hi(n), lo(n);
+    for (long long i = 0; i < n; ++i) {
+        float h[3], l[3];
+        for (int a = 0; a < 3; ++a) {
+            h[a] = (float)xyz[3 * i + a];
+            l[a] = (float)(xyz[3 * i + a] - (double)h[a]);
+        }
+        unsigned tag = (unsigned)c->local[i] | (c->fixed[i] ? 0x80000000u : 0u);
+        float tw, lw;
+        int tr = c->traj_of[i];
+        std::memcpy(&tw, &tag, 4);
+        std::memcpy(&lw, &tr, 4);
+        hi[i] = float4{h[0], h[1], h[2], tw};
+        lo[i] = float4{l[0], l[1], l[2], lw};
+    }
+    set_grid(c, xyz);
+    destroy_graphs(c);  // the grid is a kernel argument of captured rebuilds
+    hipStream_t s = c->stream;
+    for (int k = 0; k < 2; ++k) {
+        HIP_TRY(c, hipMemcpyAsync(c->b.hi[k], hi.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->b.lo[k], lo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(c, hipMemsetAsync(c->b.err, 0, sizeof(unsigned), s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->cur = 0;
+    c->sticky = 0;
+    c->coords = true;
+    c->list_valid = false;
+    c->last_error.clear();
+    return SOP_OK;
+}
+
+sop_status sop_get_coordinates(sop_ctx *c, double *xyz)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (!xyz)
+        return fail(c, SOP_E_ARG, "null output");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const long long n = c->n_res;
+    std::vector<float4> hi(n), lo(n);
+    HIP_TRY(c, hipMemcpy(hi.data(), c->b.hi[c->cur], n * sizeof(float4), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(lo.data(), c->b.lo[c->cur], n * sizeof(float4), hipMemcpyDeviceToHost));
+    for (long long i = 0; i < n; ++i) {
+        xyz[3 * i + 0] = (double)hi[i].x + (double)lo[i].x;
+        xyz[3 * i + 1] = (double)hi[i].y + (double)lo[i].y;
+        xyz[3 * i + 2] = (double)hi[i].z + (double)lo[i].z;
+    }
+    return check_device_errors(c);
+}
+
+sop_status sop_set_step(sop_ctx *c, int64_t step)
+{
+    if (!c || step < 0)
+        return SOP_E_ARG;
+    c->step = step;
+    c->list_valid = false;
+    return SOP_OK;
+}
+
+sop_status sop_get_step(const sop_ctx *c, int64_t *step)
+{
+    if (!c || !step)
+        return SOP_E_ARG;
+    *step = c->step;
+    return SOP_OK;
+}
+
+sop_status sop_build_pairlist(sop_ctx *c)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    rebuild(c, c->stream, false);
+    HIP_TRY(c, hipGetLastError());
+    c->list_valid = true;
+    return SOP_OK;
+}
+
+sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pairs)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (!n_pairs || cap < 0 || (cap > 0 && !ij))
+        return fail(c, SOP_E_ARG, "bad pairlist arguments");
+    if (!c->list_valid)
+        return fail(c, SOP_E_STATE, "no list built since the coordinates were set");
+    st = check_device_errors(c);
+    if (st != SOP_OK)
+        return st;
+    const long long n = c->n_res;
+    const int G = 64 / c->lanes;
+    std::vector<int> cnt(n);
+    std::vector<int> list(((n + G - 1) / G) * (size_t)G * c->cap);
+    HIP_TRY(c, hipMemcpy(cnt.data(), c->b.list_cnt, n * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(list.data(), c->b.list, list.size() * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<std::pair<int, int>> pairs;
+    for (long long i = 0; i < n; ++i)
+        for (int p = 0; p < std::min(cnt[i], c->cap); ++p) {
+            int j = list[list_index_host((int)i, p, c->cap, c->lanes)];
+            if (i < j)
+                pairs.push_back({(int)i, j});
+        }
+    std::sort(pairs.begin(), pairs.end());
+    *n_pairs = (int64_t)pairs.size();
+    if ((int64_t)pairs.size() > cap)
+        return fail(c, SOP_E_ARG, "output capacity too small");
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        ij[2 * k] = pairs[k].first;
+        ij[2 * k + 1] = pairs[k].second;
+    }
+    return SOP_OK;
+}
+
+sop_status sop_compute_forces(sop_ctx *c, double *f, double *energies, double *f_ext)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (!c->list_valid) {
+        rebuild(c, c->stream, false);
+        c->list_valid = true;
+    }
+    launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+                c->pulls.empty() ? 0 : 1, true, 1, nullptr, c->step, c->stream);
+    launch_reduce_energy(c->b, c->n_traj, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    st = check_device_errors(c);
+    if (st != SOP_OK)
+        return st;
+    c->energy_step = c->step;
+    const long long n = c->n_res;
+    if (f) {
+        std::vector<float4> fo(n);
+        HIP_TRY(c, hipMemcpy(fo.data(), c->b.fout, n * sizeof(float4), hipMemcpyDeviceToHost));
+        for (long long i = 0; i < n; ++i) {
+            f[3 * i] = fo[i].x;
+            f[3 * i + 1] = fo[i].y;
+            f[3 * i + 2] = fo[i].z;
+        }
+    }
+    if (energies)
+        HIP_TRY(c, hipMemcpy(energies, c->b.energy, (size_t)c->n_traj * SOP_NTERMS * sizeof(double),
+                             hipMemcpyDeviceToHost));
+    if (f_ext)
+        HIP_TRY(c, hipMemcpy(f_ext, c->b.f_ext, (size_t)c->n_traj * sizeof(double), hipMemcpyDeviceToHost));
+    return SOP_OK;
+}
+
+sop_status sop_step(sop_ctx *c, int64_t n_steps)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (n_steps < 0)
+        return fail(c, SOP_E_ARG, "negative step count");
+    if (c->sticky)
+        return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
+    const int L = c->p.list_every;
+    const long long E = c->energy_every;
+    const long long span = (long long)L * std::max(c->graph_steps, 1);
+    // graphs replay whole list periods; energies must fall on graph starts
+    const bool graphs_ok = c->graph_steps > 0 && (E == 0 || E % span == 0);
+    bool base_set = false;
+    long long q = 0;
+    while (q < n_steps) {
+        if (graphs_ok && c->step % L == 0 && n_steps - q >= span) {
+            const int en = (E > 0 && c->step % E == 0) ? 1 : 0;
+            if (!c->graphs[c->cur][en]) {
+                st = capture_graph(c, c->cur, en);
+                if (st != SOP_OK)
+                    return st;
+            }
+            if (!base_set) {
+                launch_set_step(c->b.step_next, c->step, c->stream);
+                base_set = true;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->graphs[c->cur][en], c->stream));
+            if (en)
+                c->energy_step = c->step;
+            c->list_valid = true;
+            c->step += span;
+            if (span & 1)
+                c->cur ^= 1;
+            q += span;
+            continue;
+        }
+        if (!c->list_valid || c->step % L == 0) {
+            rebuild(c, c->stream, false);
+            c->list_valid = true;
+        }
+        const bool en = E > 0 && c->step % E == 0;
+        one_step(c, c->stream, nullptr, c->step, en);
+        if (en)
+            c->energy_step = c->step;
+        c->cur ^= 1;
+        ++c->step;
+        ++q;
+        base_set = false;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOP_OK;
+}
+
+sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (n_steps < 0 || !ms_out)
+        return fail(c, SOP_E_ARG, "bad timing arguments");
+    if (c->sticky)
+        return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
+    const int L = c->p.list_every;
+    const long long E = c->energy_every;
+    hipEvent_t ev[4];
+    for (auto &e : ev)
+        HIP_TRY(c, hipEventCreate(&e));
+    double sum[3] = {0, 0, 0};
+    long long cnt[3] = {0, 0, 0};
+    sop_status out = SOP_OK;
+    for (long long q = 0; q < n_steps && out == SOP_OK; ++q) {
+        float ms = 0.0f;
+        bool rebuilt = false;
+        if (!c->list_valid || c->step % L == 0) {
+            (void)hipEventRecord(ev[0], c->stream);
+            rebuild(c, c->stream, false);
+            (void)hipEventRecord(ev[1], c->stream);
+            c->list_valid = true;
+            rebuilt = true;
+        }
+        const bool en = E > 0 && c->step % E == 0;
+        (void)hipEventRecord(ev[2], c->stream);
+        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+                    c->pulls.empty() ? 0 : 1, en, 0, nullptr, c->step, c->stream);
+        (void)hipEventRecord(ev[3], c->stream);
+        if (en)
+            launch_reduce_energy(c->b, c->n_traj, c->stream);
+        hipError_t e = hipEventSynchronize(ev[3]);
+        if (e != hipSuccess) {
+            out = hip_fail(c, e, "hipEventSynchronize");
+            break;
+        }
+        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) {
+            sum[0] += ms;
+            cnt[0]++;
+        }
+        if (rebuilt && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) {
+            sum[1] += ms;
+            cnt[1]++;
+        }
+        if (en)
+            c->energy_step = c->step;
+        c->cur ^= 1;
+        ++c->step;
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    for (int k = 0; k < 3; ++k)
+        ms_out[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    if (out == SOP_OK)
+        HIP_TRY(c, hipGetLastError());
+    return out;
+}
+
+sop_status sop_get_energies(sop_ctx *c, double *energies, int64_t *step)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    st = check_device_errors(c);
+    if (st != SOP_OK)
+        return st;
+    if (energies)
+        HIP_TRY(c, hipMemcpy(energies, c->b.energy, (size_t)c->n_traj * SOP_NTERMS * sizeof(double),
+                             hipMemcpyDeviceToHost));
+    if (step)
+        *step = c->energy_step;
+    return SOP_OK;
+}
+
+sop_status sop_get_external_force(sop_ctx *c, double *f_ext)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (!f_ext)
+        return fail(c, SOP_E_ARG, "null output");
+    st = check_device_errors(c);
+    if (st != SOP_OK)
+        return st;
+    HIP_TRY(c, hipMemcpy(f_ext, c->b.f_ext, (size_t)c->n_traj * sizeof(double), hipMemcpyDeviceToHost));
+    return SOP_OK;
+}
+
+sop_status sop_sample_noise(sop_ctx *c, int64_t step, uint32_t *words, double *g)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (step < 0)
+        return fail(c, SOP_E_ARG, "negative step");
+    // cpos and fout are scratch outside a list rebuild or a force evaluation
+    launch_noise(c->b, c->cur, (int)c->n_res, step_consts(c), step, (uint4 *)c->b.cpos, c->b.fout,
+                 c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const long long n = c->n_res;
+    if (words)
+        HIP_TRY(c, hipMemcpy(words, c->b.cpos, n * sizeof(uint4), hipMemcpyDeviceToHost));
+    if (g) {
+        std::vector<float4> gv(n);
+        HIP_TRY(c, hipMemcpy(gv.data(), c->b.fout, n * sizeof(float4), hipMemcpyDeviceToHost));
+        for (long long i = 0; i < n; ++i) {
+            g[3 * i] = gv[i].x;
+            g[3 * i + 1] = gv[i].y;
+            g[3 * i + 2] = gv[i].z;
+        }
+    }
+    return SOP_OK;
+}
+
+sop_status sop_synchronize(sop_ctx *c)
+{
+    if (!c)
+        return SOP_E_ARG;
+    return check_device_errors(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sop.h"
+
+namespace sop {
+
+// Device-side error bits (sticky until new coordinates are loaded).
+enum : unsigned {
+    ERR_FENE = 1u << 0,
+    ERR_OVERFLOW = 1u << 1,
+    ERR_NONFINITE = 1u << 2,
+    ERR_TIP = 1u << 3,
+};
+
+// Per-residue energy record written on energy steps:
+// FENE, native, repulsive, external, virial, external-force report.
+constexpr int RES_E = 6;
+
+struct PullDev {
+    double anchor0[3];
+    double v[3];
+    double vhat[3];
+    double kappa;
+    int32_t residue;
+    int32_t has_dir;
+};
+
+struct TipDev {
+    double c0[3];
+    double v[3];
+    double vhat[3];
+    double radius;
+    double eps;
+    double sigma;
+    int32_t on;
+    int32_t has_dir;
+};
+
+// Cell grid used to rebuild the list: wrapped (periodic-index) grid of
+// gx*gy*gz cells of edge `cell`, so any position maps to a valid cell.
+struct GridDev {
+    float inv_cell;
+    int gx, gy, gz;
+    int n_cells;
+};
+
+// Device buffers carved out of the caller's workspace.
+struct DevBufs {
+    float4 *hi[2];
+    float4 *lo[2];
+    int2 *trow;       // per residue: {first entry, n_bond | n_native << 12}
+    float2 *tent;     // {partner id bits, r0}: bonds first, then natives
+    int *list;        // lane-sliced list (see list_index)
+    int *list_cnt;    // partners per residue
+    int *cell_of;     // cell of each residue
+    int *cell_slot;   // arrival slot of each residue in its cell
+    int *cell_count;  // residues per cell
+    int *cell_start;  // exclusive scan of cell_count (n_cells + 1)
+    float4 *cpos;     // positions in cell order, w = residue id bits
+    int *traj_lo;     // per residue: first residue of its trajectory
+    int *traj_hi;     // per residue: one past the last residue of its trajectory
+    int *pull_slot;   // per residue: cantilever index or -1
+    PullDev *pulls;
+    unsigned *stream_ids;  // per trajectory
+    long long *res_offsets;  // n_traj + 1
+    double *res_energy;    // n_res * RES_E
+    double *energy;        // n_traj * SOP_NTERMS, last record
+    double *f_ext;         // n_traj, last record
+    float4 *fout;          // forces (compute_forces)
+    long long *step_base;  // graph replays: step of the period's first step
+    long long *step_next;
+    unsigned *err;
+};
+
+struct StepConsts {
+    float k_fene, R0sq, eps_h, eps_l, sigma2;
+    float c_drift, c_noise;
+    unsigned key0, key1;
+    double h;
+};
+
+// ---- kernel launchers (sop_kernels.hip) ----------------------------------
+void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int lanes, const GridDev &g,
+                    float rc2, hipStream_t s, bool advance_step_base, int list_every);
+// mode: 0 = step, 1 = forces only
+void launch_step(const DevBufs &b, int cur, int n_res, int cap, int lanes, const StepConsts &c,
+                 const TipDev &tip, int has_pull, bool energy, int mode,
+                 const long long *step_base, long long step_off, hipStream_t s);
+void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
+void launch_set_step(long long *dst, long long value, hipStream_t s);
+void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long long step, uint4 *words,
+                  float4 *g, hipStream_t s);
+
+// Index of entry p of residue r in the lane-sliced list.
+inline size_t list_index_host(int r, int p, int cap, int lanes)
+{
+    const int G = 64 / lanes;
+    const size_t slice = (size_t)(r / G);
+    const int g = r % G;
+    return slice * (size_t)cap * G + (size_t)(p / lanes) * 64 + (size_t)g * lanes + (p % lanes);
+}
+
+}  // namespace sop

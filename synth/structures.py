@@ -40,6 +40,7 @@ class RunParams:
     h: float = 0.08           # time step, tau
     list_every: int = 10      # list rebuild period, steps
     seed: int = 0x5eed1003
+    list_capacity: int = 0    # list partners per residue on the GPU (0 = library default)
 
 
 def default_params(**kw) -> RunParams:
@@ -302,17 +303,21 @@ def _fibonacci_sphere(m):
 
 
 def _place_copies(sub, frames, centres, rng, base_rot, min_gap=BOND, tries=64):
-    """Place rotated copies, re-drawing the spin angle while any copy clashes."""
-    placed, tree_pts = [], np.zeros((0, 3))
+    """Place rotated copies, re-drawing the spin angle while a copy comes closer
+    than min_gap to an already placed copy (only copies whose bounding spheres
+    can touch are checked)."""
+    rmax = np.linalg.norm(sub, axis=1).max()
+    placed = []
     for F, c in zip(frames, centres):
-        tree = cKDTree(tree_pts) if len(tree_pts) else None
+        near = [placed[k] for k in range(len(placed))
+                if np.linalg.norm(centres[k] - c) < 2.0 * rmax + min_gap]
+        tree = cKDTree(np.concatenate(near)) if near else None
         for _ in range(tries):
             R = F @ base_rot(rng.uniform(0.0, 2.0 * np.pi))
             y = sub @ R.T + c
             if tree is None or not tree.query_ball_point(y, min_gap, return_length=True).any():
                 break
         placed.append(y)
-        tree_pts = np.concatenate([tree_pts, y]) if len(tree_pts) else y
     return placed
 
 

@@ -1,0 +1,331 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: Philox words and pair lists bit-exact; forces within a relative L2
+error of 1e-5; 200-step trajectories within 1e-4 A per residue; graph
+replays, repeated runs and checkpoint/resume bit-identical.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import RunParams, make_config
+from synth.structures import Tip
+
+pytestmark = pytest.mark.gpu
+
+FORCE_TOL = 1e-5
+TRAJ_TOL = 1e-4
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1003_1148_amd as P
+    P.lib()
+    return P
+
+
+_CACHE = {}
+
+
+def cfg(name):
+    if name not in _CACHE:
+        if name == "c3s":
+            _CACHE[name] = make_config("c3", n_traj=96)
+        elif name == "c2cap":
+            _CACHE[name] = cap_of(make_config("c2"), 80 * 250)
+        else:
+            _CACHE[name] = make_config(name)
+    return _CACHE[name]
+
+
+def cap_of(s, n):
+    """The first n residues of a single-trajectory system (whole chains)."""
+    from synth.structures import System
+    keep_b = (s.bonds < n).all(1)
+    keep_n = (s.natives < n).all(1)
+    fixed = None if s.fixed is None else s.fixed[:n].copy()
+    return System(s.name + f"-first{n}", s.x[:n].copy(), np.array([0, n], np.int64),
+                  s.stream_ids.copy(), s.chain_id[:n].copy(), s.bonds[keep_b], s.bond_r0[keep_b],
+                  s.natives[keep_n], s.native_r0[keep_n], fixed, [], s.tip, s.steps)
+
+
+def perturbed(s, sd=0.15, seed=1):
+    """Start coordinates displaced by N(0, sd^2) per axis; sd = 0.15 A keeps
+    every FENE bond of the largest workload well inside |r - r0| < R0."""
+    rng = np.random.default_rng(seed)
+    return s.x + sd * rng.standard_normal(s.x.shape)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def ctx_for(P, s, p=None, x=None, **kw):
+    p = p or RunParams()
+    return P.from_system(s, p, coordinates=x, **kw)
+
+
+# --------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0", "c3s"])
+def test_philox_words_bit_exact(P, orc, name):
+    s = cfg(name)
+    p = RunParams(seed=0xA5A5F00D12345678)
+    log(f"noise {name} n={s.n_res}")
+    c = ctx_for(P, s, p)
+    rng = np.random.default_rng(0)
+    rows = rng.choice(s.n_res, size=min(400, s.n_res), replace=False)
+    for step in [0, 7, 2**32 + 5]:
+        w, g = c.sample_noise(step)
+        for i in rows:
+            t = int(np.searchsorted(s.res_offsets, i, side="right") - 1)
+            local = i - s.res_offsets[t]
+            ctr = np.array([local, s.stream_ids[t], step & 0xFFFFFFFF, step >> 32], np.uint32)
+            key = np.array([p.seed & 0xFFFFFFFF, p.seed >> 32], np.uint32)
+            assert np.array_equal(w[i], orc.philox(ctr, key)), (i, step)
+            ref = orc.gauss3(p.seed, local, s.stream_ids[t], step)
+            assert np.allclose(g[i], ref, rtol=0, atol=4e-6), (i, step, g[i], ref)
+
+
+def test_free_particle_msd_on_gpu(P):
+    m, n = 40000, 10
+    rng = np.random.default_rng(21)
+    from synth.structures import System
+    x = rng.uniform(-1e4, 1e4, size=(m, 3))
+    s = System("free", x, np.arange(m + 1, dtype=np.int64), np.arange(m, dtype=np.uint32),
+               np.zeros(m, np.int32), np.zeros((0, 2), np.int32), np.zeros(0),
+               np.zeros((0, 2), np.int32), np.zeros(0))
+    p = RunParams(r_list=1e-3)
+    c = ctx_for(P, s, p)
+    c.step(n)
+    x1 = c.get_coordinates()
+    msd = ((x1 - x) ** 2).sum(1).mean()
+    expect = 6.0 * p.kBT / p.zeta * n * p.h
+    assert abs(msd / expect - 1.0) < 4.5 * math.sqrt(2.0 / 3.0) / math.sqrt(m)
+
+
+# --------------------------------------------------------------------------
+# pair lists
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3s", "c4"])
+def test_pairlist_bit_exact(P, orc, name):
+    s = cfg(name)
+    log(f"pairlist {name} n={s.n_res}")
+    c = ctx_for(P, s)
+    c.build_pairlist()
+    got = c.get_pairlist()
+    ref = orc.OracleSystem(s, RunParams()).pairlist(s.x)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_pairlist_all_lane_layouts(P, orc, lanes):
+    s = cfg("c1")
+    x = perturbed(s, 0.5, seed=lanes)   # the list build evaluates no bond terms
+    c = ctx_for(P, s, x=x, lanes=lanes)
+    c.build_pairlist()
+    ref = orc.OracleSystem(s, RunParams()).pairlist(x)
+    assert np.array_equal(c.get_pairlist(), ref)
+
+
+def test_pairlist_after_dynamics(P, orc):
+    s = cfg("c1")
+    c = ctx_for(P, s)
+    c.step(137)
+    x = c.get_coordinates()
+    c.build_pairlist()
+    ref = orc.OracleSystem(s, RunParams()).pairlist(x)
+    assert np.array_equal(c.get_pairlist(), ref)
+
+
+# --------------------------------------------------------------------------
+# forces and energies
+# --------------------------------------------------------------------------
+
+def _energy_close(Eg, Eo, n_res, kBT=RunParams().kBT):
+    """Each recorded term within FORCE_TOL of the oracle, relative to the term
+    or to the thermal scale N kBT, whichever is larger: a sum with heavy
+    cancellation (the virial of a strained configuration) carries the single-
+    precision rounding of its O(N) contributions, not of its net value."""
+    floor = n_res * kBT
+    for k in range(5):
+        assert abs(Eg[k] - Eo[k]) <= FORCE_TOL * max(abs(Eo[k]), floor), (k, Eg[k], Eo[k])
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3s", "c4"])
+def test_forces_and_energies(P, orc, name):
+    s = cfg(name)
+    x = perturbed(s)
+    log(f"forces {name} n={s.n_res}")
+    c = ctx_for(P, s, x=x)
+    c.set_step(1234)
+    F, E, fe = c.compute_forces()
+    o = orc.OracleSystem(s, RunParams())
+    Fo, Eo, feo, st = o.forces(x, step=1234)
+    assert st == 0
+    err = rel_l2(F, Fo)
+    log(f"  force rel err {err:.3e}")
+    assert err <= FORCE_TOL
+    for t in range(s.n_traj):
+        _energy_close(E[t], Eo[t], s.res_offsets[t + 1] - s.res_offsets[t])
+    assert np.allclose(fe, feo, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_forces_all_lane_counts(P, orc, lanes):
+    s = cfg("c1")
+    x = perturbed(s, seed=2)
+    c = ctx_for(P, s, x=x, lanes=lanes)
+    F, E, _ = c.compute_forces()
+    Fo, Eo, _, _ = orc.OracleSystem(s, RunParams()).forces(x)
+    assert rel_l2(F, Fo) <= FORCE_TOL
+    _energy_close(E[0], Eo[0], s.n_res)
+
+
+def test_newton_third_law_on_gpu(P):
+    s = cfg("c2")
+    s2 = cap_of(s, s.n_res)
+    s2.tip = None
+    s2.fixed = None
+    c = ctx_for(P, s2, x=perturbed(s2))
+    F, _, _ = c.compute_forces()
+    assert np.abs(F.sum(0)).max() < 2e-5 * np.abs(F).sum()
+
+
+# --------------------------------------------------------------------------
+# trajectories
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2cap"])
+def test_trajectory_200_steps(P, orc, name):
+    s = cfg(name)
+    p = RunParams()
+    log(f"trajectory {name} n={s.n_res}")
+    c = ctx_for(P, s, p, energy_every=10)
+    c.step(200)
+    xg = c.get_coordinates()
+    Eg, estep = c.get_energies()
+    o = orc.OracleSystem(s, p)
+    xo, Eo, _, st = o.run(s.x, 200, energy_every=10)
+    assert st == 0
+    d = np.linalg.norm(xg - xo, axis=1).max()
+    log(f"  max |dx| {d:.3e} A")
+    assert d <= TRAJ_TOL
+    assert estep == 190
+    _energy_close(Eg[0], Eo[-1][0], s.n_res)
+
+
+def test_graph_replay_equals_direct_launches(P):
+    s = cfg("c1")
+    a = ctx_for(P, s, graph_steps=1, energy_every=20)
+    b = ctx_for(P, s, graph_steps=0, energy_every=20)
+    for n in [3, 7, 40, 5]:     # crosses period boundaries in both orders
+        a.step(n)
+        b.step(n)
+    assert np.array_equal(a.get_coordinates(), b.get_coordinates())
+    Ea, sa = a.get_energies()
+    Eb, sb = b.get_energies()
+    assert sa == sb == 40
+    assert np.array_equal(Ea, Eb)
+
+
+def test_runs_are_bit_reproducible(P):
+    s = cfg("c2cap")
+    xs = []
+    for _ in range(2):
+        c = ctx_for(P, s)
+        c.step(60)
+        xs.append(c.get_coordinates())
+        c.close()
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_resume_at_period_boundary_is_exact(P):
+    s = cfg("c1")
+    a = ctx_for(P, s)
+    a.step(40)
+    xa = a.get_coordinates()
+    b = ctx_for(P, s)
+    b.step(20)
+    mid = b.get_coordinates()
+    c = ctx_for(P, s, x=mid)
+    c.set_step(20)
+    c.step(20)
+    assert np.array_equal(c.get_coordinates(), xa)
+
+
+def test_fixed_residue_and_cantilever(P, orc):
+    s = cfg("c1")
+    c = ctx_for(P, s, energy_every=10)
+    x0 = c.get_coordinates()
+    c.step(30)
+    x = c.get_coordinates()
+    assert np.array_equal(x[0], x0[0])
+    assert not np.array_equal(x[1], x0[1])
+    fe = c.get_external_force()
+    _, _, feo, _ = orc.OracleSystem(s, RunParams()).run(s.x, 30, energy_every=10)
+    assert np.allclose(fe, feo[-1], rtol=1e-4, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# error paths, forced from the host
+# --------------------------------------------------------------------------
+
+def test_stretched_bond_is_reported(P):
+    s = cfg("c0")
+    x = s.x.copy()
+    b = x[10] - x[9]
+    x[10:] += 2.5 * b / np.linalg.norm(b)   # bond 9-10 stretched past R0
+    c = ctx_for(P, s, x=x)
+    with pytest.raises(P.SopError) as e:
+        c.compute_forces()
+    assert e.value.name == "SOP_E_FENE"
+    c.set_coordinates(s.x)            # clears the sticky error
+    c.compute_forces()
+
+
+def test_list_overflow_is_reported(P):
+    s = cfg("c1")
+    c = ctx_for(P, s, RunParams(list_capacity=16))
+    c.build_pairlist()
+    with pytest.raises(P.SopError) as e:
+        c.synchronize()
+    assert e.value.name == "SOP_E_LIST_OVERFLOW"
+
+
+def test_tip_contact_is_reported(P):
+    s = make_config("c0")
+    s.tip = Tip(5.0, 1.0, 1.0, s.x[3].copy(), np.zeros(3))
+    c = ctx_for(P, s)
+    with pytest.raises(P.SopError) as e:
+        c.compute_forces()
+    assert e.value.name == "SOP_E_TIP"
+
+
+def test_coincident_residues_are_reported(P):
+    from synth.structures import System
+    x = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [5.0, 0.0, 0.0]])
+    s = System("coincident", x, np.array([0, 3], np.int64), np.zeros(1, np.uint32),
+               np.zeros(3, np.int32), np.zeros((0, 2), np.int32), np.zeros(0),
+               np.zeros((0, 2), np.int32), np.zeros(0))
+    c = ctx_for(P, s)
+    c.step(1)
+    with pytest.raises(P.SopError) as e:
+        c.synchronize()
+    assert e.value.name == "SOP_E_NONFINITE"
+    with pytest.raises(P.SopError):
+        c.set_coordinates(np.full_like(x, np.nan))   # rejected on the host
