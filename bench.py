@@ -119,7 +119,7 @@ def main():
     value = N * L * args.steps / dt
     note(f"timed {args.steps} periods in {dt:.3f} s: {value:.4e} residue-steps/s")
 
-    k_ms, rb_ms = ctx.step_timed(args.timing_steps)
+    k_ms, rb_ms, _ = ctx.step_timed(args.timing_steps)
     note(f"fused step kernel {k_ms * 1e3:.2f} us, list rebuild {rb_ms * 1e3:.2f} us")
     bytes_step = N * (64 + 12 + 8 * b + 8 * c + 4 * pp)
     achieved = bytes_step / (k_ms * 1e-3) / 1e9

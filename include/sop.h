@@ -138,6 +138,42 @@ sop_status sop_set_tip(sop_ctx *ctx, double radius, double eps, double sigma, co
 
 /* ---- schedule ------------------------------------------------------------ */
 
+enum {
+    SOP_SCHEDULE_PLAIN = 0,   /* one fused kernel per step over a cell-grid list */
+    SOP_SCHEDULE_BATCHED = 1  /* one persistent launch per many steps; each workgroup
+                                 keeps whole trajectories (<= 1024 residues each)
+                                 resident in LDS */
+};
+
+/*
+ * Execution schedule (call before sop_bind_workspace).  Both schedules compute
+ * the same dynamics from the same noise stream; they differ in how work maps
+ * to the GPU.  The batched schedule is for ensembles of many independent
+ * trajectories (the paper's many-runs-per-GPU mode, Section IV.D); it returns
+ * SOP_E_ARG when a trajectory has more than 1024 residues.
+ */
+sop_status sop_set_schedule(sop_ctx *ctx, int32_t schedule);
+
+/*
+ * Batched schedule: residues per workgroup (256, 512 or 1024; 0 = the
+ * smallest that holds the longest trajectory) and steps per launch (>= 1).
+ * Consecutive trajectories are packed greedily into workgroups.  May be
+ * changed after binding; the list is rebuilt at the next step.
+ */
+sop_status sop_set_batch(sop_ctx *ctx, int32_t wg_residues, int32_t steps_per_launch);
+sop_status sop_get_batch(const sop_ctx *ctx, int32_t *wg_residues, int32_t *steps_per_launch,
+                         int32_t *n_packs);
+
+/*
+ * Choose the schedule parameters by timing: lanes per residue (plain) or
+ * workgroup size and steps per launch (batched).  Each candidate runs from
+ * the current state, which is restored afterwards, for about budget_ms in
+ * total.  With a cache_path, a matching entry (device, schedule, topology
+ * digest) is used without timing and new results are appended; the choice
+ * is therefore deterministic given the cache.  Needs bound coordinates.
+ */
+sop_status sop_autotune(sop_ctx *ctx, double budget_ms, const char *cache_path);
+
 /*
  * Lanes of a 64-wide wavefront that cooperate on one residue's pair loops
  * (1, 2, 4, 8 or 16; 0 selects a default from the system size).  Changes
@@ -197,10 +233,12 @@ sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
 
 /*
  * Same as sop_step, launched kernel by kernel with HIP events on the
- * context's stream around each list rebuild and each fused step kernel;
- * waits after every step.  ms_out[0] = mean duration of the fused step
- * kernel, ms_out[1] = mean duration of one list rebuild (all its kernels),
- * ms_out[2] is reserved (0).  For measurement only.
+ * context's stream around each kernel group; waits after every launch.
+ * Plain schedule: ms_out[0] = mean duration of the fused step kernel,
+ * ms_out[1] = mean duration of one list rebuild (all its kernels),
+ * ms_out[2] = 1.  Batched schedule: ms_out[0] = mean duration of one
+ * persistent launch, ms_out[1] = 0, ms_out[2] = steps per launch.
+ * For measurement only.
  */
 sop_status sop_step_timed(sop_ctx *ctx, int64_t n_steps, double *ms_out);
 
@@ -220,7 +258,8 @@ sop_status sop_get_pairlist(sop_ctx *ctx, int64_t cap, int32_t *ij_host, int64_t
 
 /*
  * Forces and energies at the current positions and step without moving
- * anything (the list is rebuilt first only if stale).  f_host: double[3*n_res]
+ * anything; the list is rebuilt first when a step would rebuild it (stale,
+ * or step % list_every == 0).  f_host: double[3*n_res]
  * or NULL; energies_host: double[n_traj*SOP_NTERMS] or NULL; f_ext_host:
  * double[n_traj] or NULL (reported external force).  Synchronizes.
  */

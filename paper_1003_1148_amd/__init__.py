@@ -8,6 +8,8 @@ from ._sop import (  # noqa: F401
     Context,
     SopError,
     NTERMS,
+    SCHEDULE_BATCHED,
+    SCHEDULE_PLAIN,
     TERM_NAMES,
     LIB_PATH,
     declared_functions,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libsop.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "sop.h")
 
 NTERMS = 5
+SCHEDULE_PLAIN, SCHEDULE_BATCHED = 0, 1
 TERM_NAMES = ("fene", "native", "repulsive", "external", "virial")
 STATUS = {0: "SOP_OK", -1: "SOP_E_ARG", -2: "SOP_E_STATE", -3: "SOP_E_WORKSPACE",
           -4: "SOP_E_HIP", -5: "SOP_E_FENE", -6: "SOP_E_LIST_OVERFLOW",
@@ -62,6 +63,10 @@ def lib():
             "sop_set_pulling": [vp, i32, i64, dbl, vp, vp],
             "sop_set_tip": [vp, dbl, dbl, dbl, vp, vp],
             "sop_set_lanes": [vp, i32],
+            "sop_set_schedule": [vp, i32],
+            "sop_set_batch": [vp, i32, i32],
+            "sop_get_batch": [vp, vp, vp, vp],
+            "sop_autotune": [vp, dbl, C.c_char_p],
             "sop_get_lanes": [vp, vp],
             "sop_set_graph_steps": [vp, i32],
             "sop_set_energy_interval": [vp, i64],
@@ -170,6 +175,24 @@ class Context:
     def set_lanes(self, lanes):
         self._check(lib().sop_set_lanes(self.h, int(lanes)))
 
+    def set_schedule(self, schedule):
+        if isinstance(schedule, str):
+            schedule = {"plain": SCHEDULE_PLAIN, "batched": SCHEDULE_BATCHED}[schedule]
+        self._check(lib().sop_set_schedule(self.h, int(schedule)))
+
+    def set_batch(self, wg_residues=0, steps_per_launch=100):
+        self._check(lib().sop_set_batch(self.h, int(wg_residues), int(steps_per_launch)))
+
+    def get_batch(self):
+        """(residues per workgroup, steps per launch, number of packs)."""
+        a, b, c = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        self._check(lib().sop_get_batch(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, budget_ms=200.0, cache_path=None):
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        self._check(lib().sop_autotune(self.h, float(budget_ms), cp))
+
     def get_lanes(self):
         v = C.c_int32(0)
         self._check(lib().sop_get_lanes(self.h, C.byref(v)))
@@ -220,10 +243,13 @@ class Context:
         self._check(lib().sop_step(self.h, int(n)))
 
     def step_timed(self, n):
-        """Advance n steps kernel by kernel; returns (mean step-kernel ms, mean rebuild ms)."""
+        """Advance n steps launch by launch with events around each kernel group.
+
+        Plain schedule: (mean step-kernel ms, mean rebuild ms, 1); batched:
+        (mean persistent-launch ms, 0, steps per launch)."""
         ms = np.zeros(3)
         self._check(lib().sop_step_timed(self.h, int(n), _p(ms)))
-        return float(ms[0]), float(ms[1])
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def synchronize(self):
         self._check(lib().sop_synchronize(self.h))
@@ -272,10 +298,11 @@ def status_string(st):
 
 
 def from_system(system, params, stream=None, lanes=0, graph_steps=1, energy_every=0,
-                coordinates=None):
+                coordinates=None, schedule="plain", batch=None):
     """Load a system description (duck-typed: x, res_offsets, stream_ids, bonds,
-    bond_r0, natives, native_r0, fixed, pulls, tip), bind a torch workspace
-    and set the coordinates."""
+    bond_r0, natives, native_r0, fixed, pulls, tip), choose the schedule
+    ("plain" or "batched", batch = (residues per workgroup, steps per launch)),
+    bind a torch workspace and set the coordinates."""
     ctx = Context(params, stream)
     ctx.load_topology(system.res_offsets, system.bonds, system.bond_r0, system.natives,
                       system.native_r0, stream_ids=system.stream_ids, fixed=system.fixed)
@@ -284,6 +311,9 @@ def from_system(system, params, stream=None, lanes=0, graph_steps=1, energy_ever
     tip = getattr(system, "tip", None)
     if tip is not None:
         ctx.set_tip(tip.radius, tip.eps, tip.sigma, tip.c0, tip.v)
+    ctx.set_schedule(schedule)
+    if batch is not None:
+        ctx.set_batch(*batch)
     ctx.set_lanes(lanes)
     ctx.set_graph_steps(graph_steps)
     ctx.set_energy_interval(energy_every)

@@ -30,12 +30,18 @@ struct sop_ctx {
     std::vector<unsigned char> fixed;
     std::vector<PullDev> pulls;
     std::vector<int> pull_slot;
+    std::vector<int4> traj_cell;
     TipDev tip{};
 
-    // schedule
+    // schedule: plain (kernel per step) or batched (persistent packs)
+    int schedule = SOP_SCHEDULE_PLAIN;
     int lanes_req = 0, lanes = 1, cap = 256;
     int graph_steps = 1;
     long long energy_every = 0;
+    int batch_wg_req = 0, batch_wg = 1024, batch_steps = 100;
+    long long max_len = 0;           // longest trajectory
+    std::vector<int> pack_res;       // batched: first residue of each pack
+    hipGraphExec_t bgraphs[2] = {nullptr, nullptr};  // batched launch graphs by layer parity
 
     // device state
     bool topo = false, bound = false, coords = false, list_valid = false;
@@ -80,7 +86,7 @@ sop_status status_from_bits(unsigned bits)
 {
     if (bits & ERR_FENE)
         return SOP_E_FENE;
-    if (bits & ERR_OVERFLOW)
+    if (bits & (ERR_OVERFLOW | ERR_CELL))
         return SOP_E_LIST_OVERFLOW;
     if (bits & ERR_TIP)
         return SOP_E_TIP;
@@ -95,6 +101,8 @@ const char *bits_message(unsigned bits)
         return "a FENE bond reached |r - r0| >= R0";
     if (bits & ERR_OVERFLOW)
         return "a residue has more list partners than the list capacity";
+    if (bits & ERR_CELL)
+        return "more than 128 residues fell into one cell of the list-rebuild grid";
     if (bits & ERR_TIP)
         return "a residue reached the tip surface";
     if (bits & ERR_NONFINITE)
@@ -109,9 +117,11 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
 {
     const size_t n = (size_t)c->n_res;
     const size_t T = (size_t)c->n_traj;
-    const int G = 64 / c->lanes;
-    const size_t list_elems = ((n + G - 1) / G) * (size_t)G * (size_t)c->cap;
-    const size_t ncell = (size_t)c->n_cells_cap;
+    const bool plain = c->schedule == SOP_SCHEDULE_PLAIN;
+    // padded for 64 residues per slice so that any lane count fits
+    const size_t list_elems = plain ? ((n + 63) / 64) * 64 * (size_t)c->cap : 0;
+    const size_t list16_elems = plain ? 0 : n * (size_t)c->cap;
+    const size_t ncell = plain ? (size_t)c->n_cells_cap : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base ? base + off : nullptr;
@@ -119,19 +129,18 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
         return p;
     };
     DevBufs d{};
-    d.hi[0] = (float4 *)take(n * sizeof(float4));
-    d.hi[1] = (float4 *)take(n * sizeof(float4));
-    d.lo[0] = (float4 *)take(n * sizeof(float4));
-    d.lo[1] = (float4 *)take(n * sizeof(float4));
+    d.pos[0] = (float4 *)take(2 * n * sizeof(float4));
+    d.pos[1] = (float4 *)take(2 * n * sizeof(float4));
     d.trow = (int2 *)take(n * sizeof(int2));
     d.tent = (float2 *)take(c->tent.size() * sizeof(float2));
     d.list = (int *)take(list_elems * sizeof(int));
     d.list_cnt = (int *)take(n * sizeof(int));
-    d.cell_of = (int *)take(n * sizeof(int));
-    d.cell_slot = (int *)take(n * sizeof(int));
+    d.list16 = (unsigned short *)take(list16_elems * sizeof(unsigned short));
+    d.pack_res = (int *)take((T + 1) * sizeof(int));
+    d.pos_save = (float4 *)take(2 * n * sizeof(float4));
     d.cell_count = (int *)take(ncell * sizeof(int));
-    d.cell_start = (int *)take((ncell + 1) * sizeof(int));
-    d.cpos = (float4 *)take(n * sizeof(float4));
+    d.cells = (float4 *)take(ncell * CELL_CAP * sizeof(float4));
+    d.traj_cell = (int4 *)take(T * sizeof(int4));
     d.traj_lo = (int *)take(n * sizeof(int));
     d.traj_hi = (int *)take(n * sizeof(int));
     d.pull_slot = (int *)take(n * sizeof(int));
@@ -142,6 +151,7 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.energy = (double *)take(T * SOP_NTERMS * sizeof(double));
     d.f_ext = (double *)take(T * sizeof(double));
     d.fout = (float4 *)take(n * sizeof(float4));
+    d.words = (uint4 *)take(n * sizeof(uint4));
     d.step_base = (long long *)take(sizeof(long long));
     d.step_next = (long long *)take(sizeof(long long));
     d.err = (unsigned *)take(sizeof(unsigned));
@@ -170,13 +180,44 @@ void destroy_graphs(sop_ctx *c)
                 (void)hipGraphExecDestroy(g);
                 g = nullptr;
             }
+    for (auto &g : c->bgraphs)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
 }
+
+// Greedy packing of consecutive trajectories into workgroups of `wg` residues.
+void make_packs(sop_ctx *c)
+{
+    c->pack_res.assign(1, 0);
+    long long fill = 0;
+    for (int t = 0; t < c->n_traj; ++t) {
+        const long long len = c->res_offsets[t + 1] - c->res_offsets[t];
+        if (fill > 0 && fill + len > c->batch_wg) {
+            c->pack_res.push_back((int)c->res_offsets[t]);
+            fill = 0;
+        }
+        fill += len;
+    }
+    c->pack_res.push_back((int)c->n_res);
+}
+
+int pick_batch_wg(const sop_ctx *c)
+{
+    if (c->batch_wg_req)
+        return c->batch_wg_req;
+    return c->max_len <= 256 ? 256 : (c->max_len <= 512 ? 512 : 1024);
+}
+
+int n_packs(const sop_ctx *c) { return (int)c->pack_res.size() - 1; }
 
 StepConsts step_consts(const sop_ctx *c)
 {
     StepConsts k{};
     k.k_fene = (float)c->p.k_fene;
     k.R0sq = (float)(c->p.R0 * c->p.R0);
+    k.inv_R0sq = (float)(1.0 / (c->p.R0 * c->p.R0));
     k.eps_h = (float)c->p.eps_h;
     k.eps_l = (float)c->p.eps_l;
     k.sigma2 = (float)(c->p.sigma * c->p.sigma);
@@ -195,19 +236,47 @@ float list_rc2(const sop_ctx *c) { return (float)(c->p.r_list * c->p.r_list); }
 // cell index.
 float cell_edge(const sop_ctx *c) { return (float)(c->p.r_list * 1.002 + 0.05); }
 
+// Grid for the list rebuild.  Each trajectory's cells are shifted to its own
+// block of a lattice of trajectory boxes so that independent trajectories
+// that overlap in space do not share cells; the grid wraps, so positions
+// outside the initial boxes still map to valid (shared) cells.
 void set_grid(sop_ctx *c, const double *xyz)
 {
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (long long i = 0; i < c->n_res; ++i)
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = std::min(lo[a], xyz[3 * i + a]);
-            hi[a] = std::max(hi[a], xyz[3 * i + a]);
-        }
     const double e = cell_edge(c);
-    long long g[3];
-    for (int a = 0; a < 3; ++a) {
-        double ext = c->n_res ? hi[a] - lo[a] : 0.0;
-        g[a] = std::max<long long>(3, (long long)std::ceil(ext / e) + 2);
+    const int T = c->n_traj;
+    std::vector<long long> lo(3 * (size_t)T), ext(3 * (size_t)T);
+    long long span[3] = {1, 1, 1};
+    for (int t = 0; t < T; ++t) {
+        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        for (long long i = c->res_offsets[t]; i < c->res_offsets[t + 1]; ++i)
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = std::min(mn[a], xyz[3 * i + a]);
+                mx[a] = std::max(mx[a], xyz[3 * i + a]);
+            }
+        for (int a = 0; a < 3; ++a) {
+            if (c->res_offsets[t + 1] == c->res_offsets[t]) {
+                mn[a] = mx[a] = 0.0;
+            }
+            lo[3 * t + a] = (long long)std::floor(mn[a] / e);
+            ext[3 * t + a] = (long long)std::floor(mx[a] / e) - lo[3 * t + a] + 1;
+            span[a] = std::max(span[a], ext[3 * t + a] + 1);  // one empty cell between boxes
+        }
+    }
+    // lattice of trajectory boxes, about as many along each axis
+    long long A = 1;
+    while (A * A * A < T)
+        ++A;
+    c->traj_cell.assign(T, int4{0, 0, 0, 0});
+    long long g[3] = {3, 3, 3};
+    for (int t = 0; t < T; ++t) {
+        const long long ix = t % A, iy = (t / A) % A, iz = t / (A * A);
+        const long long org[3] = {ix * span[0], iy * span[1], iz * span[2]};
+        long long off[3];
+        for (int a = 0; a < 3; ++a) {
+            off[a] = org[a] - lo[3 * t + a];
+            g[a] = std::max(g[a], org[a] + ext[3 * t + a] + 1);
+        }
+        c->traj_cell[t] = int4{(int)off[0], (int)off[1], (int)off[2], 0};
     }
     while (g[0] * g[1] * g[2] > c->n_cells_cap) {
         int m = 0;
@@ -263,6 +332,50 @@ void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, b
                 c->pulls.empty() ? 0 : 1, energy, 0, base, off, s);
     if (energy)
         launch_reduce_energy(c->b, c->n_traj, s);
+}
+
+void batch_launch(sop_ctx *c, hipStream_t s, int n_steps, int stale, int mode, const long long *base,
+                  long long off)
+{
+    launch_batch(c->b, c->cur, n_packs(c), c->batch_wg, c->cap, step_consts(c), c->tip,
+                 c->pulls.empty() ? 0 : 1, list_rc2(c), c->p.list_every, c->energy_every, n_steps,
+                 stale, mode, base, off, s);
+}
+
+// Last step in [first, first + n) whose energies are recorded, or -1.
+long long last_record(const sop_ctx *c, long long first, long long n)
+{
+    const long long E = c->energy_every;
+    if (E <= 0 || n <= 0)
+        return -1;
+    const long long last = first + n - 1;
+    const long long r = last - last % E;
+    return r >= first ? r : -1;
+}
+
+// Batched schedule: a graph of one persistent launch of batch_steps steps plus
+// the device step-counter advance, for layer parity `par`.
+sop_status capture_batch_graph(sop_ctx *c, int par)
+{
+    if (!c->cap_stream)
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int saved = c->cur;
+    c->cur = par;
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    batch_launch(c, c->cap_stream, c->batch_steps, 0, 0, c->b.step_base, 0);
+    launch_add_step(c->b.step_base, c->batch_steps, c->cap_stream);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->cur = saved;
+    if (e != hipSuccess)
+        return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return hip_fail(c, e, "hipGraphInstantiate");
+    c->bgraphs[par] = ex;
+    return SOP_OK;
 }
 
 // Capture `periods` list periods (rebuild + list_every steps each) starting at
@@ -465,7 +578,10 @@ sop_status sop_load_topology(sop_ctx *c, int32_t n_traj, const int64_t *res_offs
     c->pull_slot.assign(n, -1);
     c->tip = TipDev{};
     c->lanes = c->lanes_req ? c->lanes_req : default_lanes(n);
-    c->n_cells_cap = (int)std::min<long long>(std::max<long long>(4 * n, 4096), 1LL << 22);
+    c->max_len = 0;
+    for (int t = 0; t < n_traj; ++t)
+        c->max_len = std::max<long long>(c->max_len, res_offsets[t + 1] - res_offsets[t]);
+    c->n_cells_cap = (int)std::min<long long>(std::max<long long>(n / 2, 4096), 1LL << 21);
     c->topo = true;
     return SOP_OK;
 }
@@ -540,11 +656,15 @@ sop_status sop_set_lanes(sop_ctx *c, int32_t lanes)
         return SOP_E_ARG;
     if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
         return fail(c, SOP_E_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
-    if (c->bound)
-        return fail(c, SOP_E_STATE, "set lanes before binding the workspace");
     c->lanes_req = lanes;
-    if (c->topo)
-        c->lanes = lanes ? lanes : default_lanes(c->n_res);
+    if (c->topo) {
+        const int nl = lanes ? lanes : default_lanes(c->n_res);
+        if (nl != c->lanes) {
+            c->lanes = nl;
+            c->list_valid = false;  // the list layout follows the lane count
+            destroy_graphs(c);
+        }
+    }
     return SOP_OK;
 }
 
@@ -555,6 +675,56 @@ sop_status sop_get_lanes(const sop_ctx *c, int32_t *lanes)
     if (!c->topo)
         return SOP_E_STATE;
     *lanes = c->lanes;
+    return SOP_OK;
+}
+
+sop_status sop_set_schedule(sop_ctx *c, int32_t schedule)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (schedule != SOP_SCHEDULE_PLAIN && schedule != SOP_SCHEDULE_BATCHED)
+        return fail(c, SOP_E_ARG, "unknown schedule");
+    if (c->bound)
+        return fail(c, SOP_E_STATE, "set the schedule before binding the workspace");
+    c->schedule = schedule;
+    return SOP_OK;
+}
+
+sop_status sop_set_batch(sop_ctx *c, int32_t wg, int32_t steps)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (!(wg == 0 || wg == 256 || wg == 512 || wg == 1024) || steps < 1)
+        return fail(c, SOP_E_ARG, "workgroup residues must be 0, 256, 512 or 1024 and steps >= 1");
+    if (c->topo && wg && wg < c->max_len)
+        return fail(c, SOP_E_ARG, "workgroup smaller than the longest trajectory");
+    c->batch_wg_req = wg;
+    c->batch_steps = steps;
+    for (auto &g : c->bgraphs)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    if (c->bound && c->schedule == SOP_SCHEDULE_BATCHED) {
+        c->batch_wg = pick_batch_wg(c);
+        make_packs(c);
+        HIP_TRY(c, hipMemcpyAsync(c->b.pack_res, c->pack_res.data(), c->pack_res.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, c->stream));
+        c->list_valid = false;  // the list layout follows the packs
+    }
+    return SOP_OK;
+}
+
+sop_status sop_get_batch(const sop_ctx *c, int32_t *wg, int32_t *steps, int32_t *np)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (wg)
+        *wg = c->bound ? c->batch_wg : pick_batch_wg(c);
+    if (steps)
+        *steps = c->batch_steps;
+    if (np)
+        *np = c->bound ? n_packs(c) : 0;
     return SOP_OK;
 }
 
@@ -594,6 +764,8 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
     if (!dev || ((uintptr_t)dev & 255) || bytes < need)
         return fail(c, SOP_E_WORKSPACE, "workspace null, not 256-byte aligned, or smaller than " +
                                             std::to_string(need) + " bytes");
+    if (c->schedule == SOP_SCHEDULE_BATCHED && c->max_len > 1024)
+        return fail(c, SOP_E_ARG, "the batched schedule holds trajectories of at most 1024 residues");
     destroy_graphs(c);
     c->bound = false;
     c->coords = false;
@@ -601,6 +773,14 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
     c->ws = dev;
     c->ws_bytes = bytes;
     layout(c, (char *)dev, &c->b);
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        c->batch_wg = pick_batch_wg(c);
+        if (c->batch_wg < c->max_len)
+            return fail(c, SOP_E_ARG, "batch workgroup smaller than the longest trajectory");
+        make_packs(c);
+        HIP_TRY(c, hipMemcpyAsync(c->b.pack_res, c->pack_res.data(), c->pack_res.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
     const DevBufs &b = c->b;
     const size_t n = (size_t)c->n_res;
     hipStream_t s = c->stream;
@@ -640,7 +820,7 @@ sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
     for (long long k = 0; k < 3 * n; ++k)
         if (!std::isfinite(xyz[k]))
             return fail(c, SOP_E_ARG, "non-finite coordinate");
-    std::vector<float4> hi(n), lo(n);
+    std::vector<float4> pv(2 * n);
     for (long long i = 0; i < n; ++i) {
         float h[3], l[3];
         for (int a = 0; a < 3; ++a) {
@@ -652,16 +832,16 @@ sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
         int tr = c->traj_of[i];
         std::memcpy(&tw, &tag, 4);
         std::memcpy(&lw, &tr, 4);
-        hi[i] = float4{h[0], h[1], h[2], tw};
-        lo[i] = float4{l[0], l[1], l[2], lw};
+        pv[2 * i] = float4{h[0], h[1], h[2], tw};
+        pv[2 * i + 1] = float4{l[0], l[1], l[2], lw};
     }
     set_grid(c, xyz);
     destroy_graphs(c);  // the grid is a kernel argument of captured rebuilds
     hipStream_t s = c->stream;
-    for (int k = 0; k < 2; ++k) {
-        HIP_TRY(c, hipMemcpyAsync(c->b.hi[k], hi.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
-        HIP_TRY(c, hipMemcpyAsync(c->b.lo[k], lo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
-    }
+    for (int k = 0; k < 2; ++k)
+        HIP_TRY(c, hipMemcpyAsync(c->b.pos[k], pv.data(), 2 * n * sizeof(float4), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->b.traj_cell, c->traj_cell.data(), c->n_traj * sizeof(int4),
+                              hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(c->b.err, 0, sizeof(unsigned), s));
     HIP_TRY(c, hipStreamSynchronize(s));
     c->cur = 0;
@@ -681,13 +861,12 @@ sop_status sop_get_coordinates(sop_ctx *c, double *xyz)
         return fail(c, SOP_E_ARG, "null output");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const long long n = c->n_res;
-    std::vector<float4> hi(n), lo(n);
-    HIP_TRY(c, hipMemcpy(hi.data(), c->b.hi[c->cur], n * sizeof(float4), hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(lo.data(), c->b.lo[c->cur], n * sizeof(float4), hipMemcpyDeviceToHost));
+    std::vector<float4> pv(2 * n);
+    HIP_TRY(c, hipMemcpy(pv.data(), c->b.pos[c->cur], 2 * n * sizeof(float4), hipMemcpyDeviceToHost));
     for (long long i = 0; i < n; ++i) {
-        xyz[3 * i + 0] = (double)hi[i].x + (double)lo[i].x;
-        xyz[3 * i + 1] = (double)hi[i].y + (double)lo[i].y;
-        xyz[3 * i + 2] = (double)hi[i].z + (double)lo[i].z;
+        xyz[3 * i + 0] = (double)pv[2 * i].x + (double)pv[2 * i + 1].x;
+        xyz[3 * i + 1] = (double)pv[2 * i].y + (double)pv[2 * i + 1].y;
+        xyz[3 * i + 2] = (double)pv[2 * i].z + (double)pv[2 * i + 1].z;
     }
     return check_device_errors(c);
 }
@@ -714,7 +893,10 @@ sop_status sop_build_pairlist(sop_ctx *c)
     sop_status st = need_ready(c);
     if (st != SOP_OK)
         return st;
-    rebuild(c, c->stream, false);
+    if (c->schedule == SOP_SCHEDULE_BATCHED)
+        batch_launch(c, c->stream, 1, 1, 1, nullptr, c->step);  // rebuild + one force evaluation
+    else
+        rebuild(c, c->stream, false);
     HIP_TRY(c, hipGetLastError());
     c->list_valid = true;
     return SOP_OK;
@@ -733,18 +915,33 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
     if (st != SOP_OK)
         return st;
     const long long n = c->n_res;
-    const int G = 64 / c->lanes;
     std::vector<int> cnt(n);
-    std::vector<int> list(((n + G - 1) / G) * (size_t)G * c->cap);
     HIP_TRY(c, hipMemcpy(cnt.data(), c->b.list_cnt, n * sizeof(int), hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(list.data(), c->b.list, list.size() * sizeof(int), hipMemcpyDeviceToHost));
     std::vector<std::pair<int, int>> pairs;
-    for (long long i = 0; i < n; ++i)
-        for (int p = 0; p < std::min(cnt[i], c->cap); ++p) {
-            int j = list[list_index_host((int)i, p, c->cap, c->lanes)];
-            if (i < j)
-                pairs.push_back({(int)i, j});
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        std::vector<unsigned short> list((size_t)n * c->cap);
+        HIP_TRY(c, hipMemcpy(list.data(), c->b.list16, list.size() * sizeof(unsigned short),
+                             hipMemcpyDeviceToHost));
+        for (int pk = 0; pk < n_packs(c); ++pk) {
+            const long long base = c->pack_res[pk], m = c->pack_res[pk + 1] - base;
+            for (long long t = 0; t < m; ++t)
+                for (int k = 0; k < std::min(cnt[base + t], c->cap); ++k) {
+                    const int j = (int)(base + list[(size_t)base * c->cap + (size_t)k * m + t]);
+                    if (base + t < j)
+                        pairs.push_back({(int)(base + t), j});
+                }
         }
+    } else {
+        const int G = 64 / c->lanes;
+        std::vector<int> list(((n + G - 1) / G) * (size_t)G * c->cap);
+        HIP_TRY(c, hipMemcpy(list.data(), c->b.list, list.size() * sizeof(int), hipMemcpyDeviceToHost));
+        for (long long i = 0; i < n; ++i)
+            for (int p = 0; p < std::min(cnt[i], c->cap); ++p) {
+                int j = list[list_index_host((int)i, p, c->cap, c->lanes)];
+                if (i < j)
+                    pairs.push_back({(int)i, j});
+            }
+    }
     std::sort(pairs.begin(), pairs.end());
     *n_pairs = (int64_t)pairs.size();
     if ((int64_t)pairs.size() > cap)
@@ -761,13 +958,17 @@ sop_status sop_compute_forces(sop_ctx *c, double *f, double *energies, double *f
     sop_status st = need_ready(c);
     if (st != SOP_OK)
         return st;
-    if (!c->list_valid) {
-        rebuild(c, c->stream, false);
-        c->list_valid = true;
+    const bool stale = !c->list_valid || c->step % c->p.list_every == 0;
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        batch_launch(c, c->stream, 1, stale ? 1 : 0, 1, nullptr, c->step);
+    } else {
+        if (stale)
+            rebuild(c, c->stream, false);
+        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+                    c->pulls.empty() ? 0 : 1, true, 1, nullptr, c->step, c->stream);
+        launch_reduce_energy(c->b, c->n_traj, c->stream);
     }
-    launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
-                c->pulls.empty() ? 0 : 1, true, 1, nullptr, c->step, c->stream);
-    launch_reduce_energy(c->b, c->n_traj, c->stream);
+    c->list_valid = true;
     HIP_TRY(c, hipGetLastError());
     st = check_device_errors(c);
     if (st != SOP_OK)
@@ -800,6 +1001,38 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
         return fail(c, SOP_E_ARG, "negative step count");
     if (c->sticky)
         return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        const long long K = c->batch_steps;
+        bool base_set = false;
+        long long q = 0;
+        while (q < n_steps) {
+            const long long k = std::min<long long>(K, n_steps - q);
+            const long long rec = last_record(c, c->step, k);
+            if (c->graph_steps > 0 && c->list_valid && k == K) {
+                if (!c->bgraphs[c->cur]) {
+                    st = capture_batch_graph(c, c->cur);
+                    if (st != SOP_OK)
+                        return st;
+                }
+                if (!base_set) {
+                    launch_set_step(c->b.step_base, c->step, c->stream);
+                    base_set = true;
+                }
+                HIP_TRY(c, hipGraphLaunch(c->bgraphs[c->cur], c->stream));
+            } else {
+                batch_launch(c, c->stream, (int)k, c->list_valid ? 0 : 1, 0, nullptr, c->step);
+                base_set = false;
+            }
+            if (rec >= 0)
+                c->energy_step = rec;
+            c->list_valid = true;
+            c->cur ^= 1;
+            c->step += k;
+            q += k;
+        }
+        HIP_TRY(c, hipGetLastError());
+        return SOP_OK;
+    }
     const int L = c->p.list_every;
     const long long E = c->energy_every;
     const long long span = (long long)L * std::max(c->graph_steps, 1);
@@ -860,6 +1093,42 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
     hipEvent_t ev[4];
     for (auto &e : ev)
         HIP_TRY(c, hipEventCreate(&e));
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        double sum = 0.0;
+        long long cnt = 0, q = 0;
+        sop_status out = SOP_OK;
+        while (q < n_steps) {
+            const long long k = std::min<long long>(c->batch_steps, n_steps - q);
+            const long long rec = last_record(c, c->step, k);
+            (void)hipEventRecord(ev[0], c->stream);
+            batch_launch(c, c->stream, (int)k, c->list_valid ? 0 : 1, 0, nullptr, c->step);
+            (void)hipEventRecord(ev[1], c->stream);
+            hipError_t e = hipEventSynchronize(ev[1]);
+            if (e != hipSuccess) {
+                out = hip_fail(c, e, "hipEventSynchronize");
+                break;
+            }
+            float ms = 0.0f;
+            if (k == c->batch_steps && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) {
+                sum += ms;
+                ++cnt;
+            }
+            if (rec >= 0)
+                c->energy_step = rec;
+            c->list_valid = true;
+            c->cur ^= 1;
+            c->step += k;
+            q += k;
+        }
+        for (auto &e : ev)
+            (void)hipEventDestroy(e);
+        ms_out[0] = cnt ? sum / (double)cnt : 0.0;
+        ms_out[1] = 0.0;
+        ms_out[2] = (double)c->batch_steps;
+        if (out == SOP_OK)
+            HIP_TRY(c, hipGetLastError());
+        return out;
+    }
     double sum[3] = {0, 0, 0};
     long long cnt[3] = {0, 0, 0};
     sop_status out = SOP_OK;
@@ -900,8 +1169,9 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
     }
     for (auto &e : ev)
         (void)hipEventDestroy(e);
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
         ms_out[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    ms_out[2] = 1.0;
     if (out == SOP_OK)
         HIP_TRY(c, hipGetLastError());
     return out;
@@ -944,14 +1214,13 @@ sop_status sop_sample_noise(sop_ctx *c, int64_t step, uint32_t *words, double *g
         return st;
     if (step < 0)
         return fail(c, SOP_E_ARG, "negative step");
-    // cpos and fout are scratch outside a list rebuild or a force evaluation
-    launch_noise(c->b, c->cur, (int)c->n_res, step_consts(c), step, (uint4 *)c->b.cpos, c->b.fout,
-                 c->stream);
+    // fout is scratch outside a force evaluation
+    launch_noise(c->b, c->cur, (int)c->n_res, step_consts(c), step, c->b.words, c->b.fout, c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const long long n = c->n_res;
     if (words)
-        HIP_TRY(c, hipMemcpy(words, c->b.cpos, n * sizeof(uint4), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(words, c->b.words, n * sizeof(uint4), hipMemcpyDeviceToHost));
     if (g) {
         std::vector<float4> gv(n);
         HIP_TRY(c, hipMemcpy(gv.data(), c->b.fout, n * sizeof(float4), hipMemcpyDeviceToHost));
@@ -962,6 +1231,173 @@ sop_status sop_sample_noise(sop_ctx *c, int64_t step, uint32_t *words, double *g
         }
     }
     return SOP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// FNV-1a digest of what the schedule's speed depends on.
+unsigned long long topology_digest(const sop_ctx *c)
+{
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((unsigned long long)c->n_res);
+    mix((unsigned long long)c->n_traj);
+    for (long long v : c->res_offsets)
+        mix((unsigned long long)v);
+    for (const int2 &r : c->trow)
+        mix((unsigned long long)(unsigned)r.y);
+    mix((unsigned long long)c->cap);
+    mix((unsigned long long)c->p.list_every);
+    return h;
+}
+
+std::string cache_key(const sop_ctx *c)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s|%d|%016llx", arch.c_str(), c->schedule, topology_digest(c));
+    return buf;
+}
+
+// Cache lines: <key> <a> <b>   (lanes 0 for the plain schedule: a = lanes)
+bool cache_lookup(const char *path, const std::string &key, int *a, int *b)
+{
+    if (!path)
+        return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    char k[200];
+    int x, y;
+    bool found = false;
+    while (std::fscanf(f, "%199s %d %d", k, &x, &y) == 3)
+        if (key == k) {
+            *a = x;
+            *b = y;
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int a, int b)
+{
+    if (!path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f, "%s %d %d\n", key.c_str(), a, b);
+    std::fclose(f);
+}
+
+// Residue-steps per second of `steps` steps from the saved state.
+sop_status trial(sop_ctx *c, long long steps, double *rate)
+{
+    const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
+    HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
+    const long long step0 = c->step;
+    c->list_valid = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    sop_status st = sop_step(c, 2 * c->p.list_every);  // warm up: capture graphs, touch caches
+    if (st == SOP_OK) {
+        (void)hipEventRecord(e0, c->stream);
+        st = sop_step(c, steps);
+        (void)hipEventRecord(e1, c->stream);
+    }
+    float ms = 0.0f;
+    if (st == SOP_OK && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        *rate = ms > 0 ? (double)c->n_res * (double)steps / (1e-3 * ms) : 0.0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // back to the saved state (the trial advanced the layer parity too)
+    HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->step = step0;
+    c->list_valid = false;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (c->sticky)
+        return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
+    const std::string key = cache_key(c);
+    int a = 0, b = 0;
+    if (cache_lookup(cache_path, key, &a, &b)) {
+        if (c->schedule == SOP_SCHEDULE_BATCHED)
+            return sop_set_batch(c, a, b);
+        return sop_set_lanes(c, a);
+    }
+    const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
+    HIP_TRY(c, hipMemcpyAsync(c->b.pos_save, c->b.pos[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+    const long long saved_energy_step = c->energy_step;
+    std::vector<std::pair<int, int>> cand;
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        for (int wg : {256, 512, 1024})
+            if (wg >= c->max_len)
+                for (int k : {20, 50, 100, 200})
+                    cand.push_back({wg, k});
+    } else {
+        for (int l : {1, 2, 4, 8, 16})
+            cand.push_back({l, 0});
+    }
+    // steps per trial from the budget, using the current schedule's speed as a guide
+    double rate0 = 0.0;
+    st = trial(c, 4 * c->p.list_every, &rate0);
+    if (st != SOP_OK)
+        return st;
+    const double per_trial_ms = std::max(1.0, budget_ms / (double)cand.size());
+    long long steps = (long long)(rate0 * 1e-3 * per_trial_ms / (double)c->n_res);
+    steps = std::max<long long>(2 * c->p.list_every, (steps / (2 * c->p.list_every)) * 2 * c->p.list_every);
+    if (c->schedule == SOP_SCHEDULE_BATCHED)
+        steps = std::max<long long>(steps, 400);
+    double best = -1.0;
+    std::pair<int, int> pick = cand.front();
+    for (const auto &cd : cand) {
+        if (c->schedule == SOP_SCHEDULE_BATCHED)
+            st = sop_set_batch(c, cd.first, cd.second);
+        else
+            st = sop_set_lanes(c, cd.first);
+        if (st != SOP_OK)
+            return st;
+        double rate = 0.0;
+        st = trial(c, steps, &rate);
+        if (st != SOP_OK)
+            return st;
+        if (rate > best) {
+            best = rate;
+            pick = cd;
+        }
+    }
+    st = c->schedule == SOP_SCHEDULE_BATCHED ? sop_set_batch(c, pick.first, pick.second)
+                                             : sop_set_lanes(c, pick.first);
+    if (st != SOP_OK)
+        return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->energy_step = saved_energy_step;
+    cache_store(cache_path, key, pick.first, pick.second);
+    return check_device_errors(c);
 }
 
 sop_status sop_synchronize(sop_ctx *c)

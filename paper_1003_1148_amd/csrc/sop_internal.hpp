@@ -17,6 +17,7 @@ enum : unsigned {
     ERR_OVERFLOW = 1u << 1,
     ERR_NONFINITE = 1u << 2,
     ERR_TIP = 1u << 3,
+    ERR_CELL = 1u << 4,  // a rebuild cell holds more than CELL_CAP residues
 };
 
 // Per-residue energy record written on energy steps:
@@ -51,36 +52,44 @@ struct GridDev {
     int n_cells;
 };
 
+// Residues per cell of the list-rebuild grid (fixed capacity; more is the
+// list-overflow error).
+constexpr int CELL_CAP = 128;
+
 // Device buffers carved out of the caller's workspace.
 struct DevBufs {
-    float4 *hi[2];
-    float4 *lo[2];
+    // positions, two time layers; residue i is pos[l][2i] = {hi.xyz, tag},
+    // pos[l][2i+1] = {lo.xyz, trajectory}; tag = index inside the
+    // trajectory | fixed << 31.  x = hi + lo.
+    float4 *pos[2];
     int2 *trow;       // per residue: {first entry, n_bond | n_native << 12}
     float2 *tent;     // {partner id bits, r0}: bonds first, then natives
-    int *list;        // lane-sliced list (see list_index)
+    int *list;        // lane-sliced list (see list_index_host)
     int *list_cnt;    // partners per residue
-    int *cell_of;     // cell of each residue
-    int *cell_slot;   // arrival slot of each residue in its cell
+    unsigned short *list16;  // batched form: per-pack list of local indices
+    int *pack_res;    // batched form: first residue of each pack (n_packs + 1)
+    float4 *pos_save; // one saved layer (autotuning restores the state it found)
     int *cell_count;  // residues per cell
-    int *cell_start;  // exclusive scan of cell_count (n_cells + 1)
-    float4 *cpos;     // positions in cell order, w = residue id bits
+    float4 *cells;    // CELL_CAP slots per cell: {hi.xyz, residue id bits}
+    int4 *traj_cell;  // per trajectory: cell-index offset that keeps trajectories apart
     int *traj_lo;     // per residue: first residue of its trajectory
     int *traj_hi;     // per residue: one past the last residue of its trajectory
     int *pull_slot;   // per residue: cantilever index or -1
     PullDev *pulls;
-    unsigned *stream_ids;  // per trajectory
+    unsigned *stream_ids;    // per trajectory
     long long *res_offsets;  // n_traj + 1
-    double *res_energy;    // n_res * RES_E
-    double *energy;        // n_traj * SOP_NTERMS, last record
-    double *f_ext;         // n_traj, last record
-    float4 *fout;          // forces (compute_forces)
-    long long *step_base;  // graph replays: step of the period's first step
+    double *res_energy;      // n_res * RES_E
+    double *energy;          // n_traj * SOP_NTERMS, last record
+    double *f_ext;           // n_traj, last record
+    float4 *fout;            // forces (compute_forces), noise samples
+    uint4 *words;            // Philox words (noise samples)
+    long long *step_base;    // graph replays: step of the period's first step
     long long *step_next;
     unsigned *err;
 };
 
 struct StepConsts {
-    float k_fene, R0sq, eps_h, eps_l, sigma2;
+    float k_fene, R0sq, inv_R0sq, eps_h, eps_l, sigma2;
     float c_drift, c_noise;
     unsigned key0, key1;
     double h;
@@ -94,6 +103,13 @@ void launch_step(const DevBufs &b, int cur, int n_res, int cap, int lanes, const
                  const TipDev &tip, int has_pull, bool energy, int mode,
                  const long long *step_base, long long step_off, hipStream_t s);
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
+// Batched ensemble: n_steps steps of every pack in one launch (mode 1: one
+// force evaluation, no update).
+void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const StepConsts &c,
+                  const TipDev &tip, int has_pull, float rc2, int list_every, long long energy_every,
+                  int n_steps, int stale, int mode, const long long *step_base, long long step_off,
+                  hipStream_t s);
+void launch_add_step(long long *base, long long k, hipStream_t s);
 void launch_set_step(long long *dst, long long value, hipStream_t s);
 void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long long step, uint4 *words,
                   float4 *g, hipStream_t s);

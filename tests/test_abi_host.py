@@ -104,3 +104,25 @@ def test_protocol_and_schedule_validation(lib):
     c.set_tip(-1.0, 0.0, 1.0, np.zeros(3), np.zeros(3))          # removes the tip
     for k in [1, 2, 4, 8, 16, 0]:
         c.set_lanes(k)
+
+
+def test_batched_schedule_validation(lib):
+    s = make_config("c3", n_traj=8)
+    c = _ctx(s)
+    longest = int(np.diff(s.res_offsets).max())
+    assert longest > 256
+    with pytest.raises(P.SopError):
+        c.set_batch(256, 50)                      # smaller than the longest trajectory
+    with pytest.raises(P.SopError):
+        c.set_batch(300, 50)                      # not a supported workgroup size
+    with pytest.raises(P.SopError):
+        c.set_batch(0, 0)                         # steps per launch >= 1
+    with pytest.raises(P.SopError):
+        c.set_schedule(7)
+    c.set_schedule("batched")
+    c.set_batch(1024, 40)
+    assert c.get_batch()[:2] == (1024, 40)
+    c.set_batch(0, 40)
+    assert c.get_batch()[0] == 512                # smallest that holds the longest chain
+    n_batched = c.workspace_size()
+    assert n_batched > 0

@@ -1,0 +1,168 @@
+"""The batched ensemble schedule (one persistent launch over packs of whole
+trajectories) against the FP64 oracle, plus its schedule invariances."""
+import sys
+
+import numpy as np
+import pytest
+
+from synth import RunParams, make_config
+
+pytestmark = pytest.mark.gpu
+
+FORCE_TOL = 1e-5
+TRAJ_TOL = 1e-4
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1003_1148_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ens():
+    """48 trajectories of 50-500 residues (the ensemble's first 48 chains),
+    with a cantilever on the last residue of trajectory 3 and residue 0 of
+    trajectory 5 fixed."""
+    from synth.structures import Pull
+    s = make_config("c3", n_traj=48)
+    t = 3
+    last = int(s.res_offsets[t + 1] - 1)
+    s.pulls = [Pull(t, last, 0.5, s.x[last] + np.array([0.5, 0.0, 0.0]), np.array([0.01, 0.0, 0.0]))]
+    fixed = np.zeros(s.n_res, np.uint8)
+    fixed[s.res_offsets[5]] = 1
+    s.fixed = fixed
+    return s
+
+
+def ctx(P, s, x=None, wg=0, steps=50, energy_every=0, graph=1, p=None):
+    return P.from_system(s, p or RunParams(), coordinates=x, schedule="batched",
+                         batch=(wg, steps), energy_every=energy_every, graph_steps=graph)
+
+
+def perturbed(s, sd=0.15, seed=1):
+    rng = np.random.default_rng(seed)
+    return s.x + sd * rng.standard_normal(s.x.shape)
+
+
+def test_batched_pairlist_bit_exact(P, orc, ens):
+    x = perturbed(ens)
+    c = ctx(P, ens, x=x)
+    c.build_pairlist()
+    ref = orc.OracleSystem(ens, RunParams()).pairlist(x)
+    assert np.array_equal(c.get_pairlist(), ref)
+
+
+def test_batched_forces_and_energies(P, orc, ens):
+    x = perturbed(ens)
+    c = ctx(P, ens, x=x)
+    c.set_step(77)
+    F, E, fe = c.compute_forces()
+    Fo, Eo, feo, st = orc.OracleSystem(ens, RunParams()).forces(x, step=77)
+    assert st == 0
+    err = float(np.linalg.norm(F - Fo) / np.linalg.norm(Fo))
+    log(f"batched force rel err {err:.3e}")
+    assert err <= FORCE_TOL
+    kBT = RunParams().kBT
+    for t in range(ens.n_traj):
+        n = ens.res_offsets[t + 1] - ens.res_offsets[t]
+        for k in range(5):
+            assert abs(E[t, k] - Eo[t, k]) <= FORCE_TOL * max(abs(Eo[t, k]), n * kBT), (t, k)
+    assert np.allclose(fe, feo, rtol=1e-5, atol=1e-6)
+
+
+def test_batched_trajectory_200_steps(P, orc, ens):
+    p = RunParams()
+    c = ctx(P, ens, energy_every=10, steps=30)    # launches that straddle list periods
+    c.step(200)
+    xg = c.get_coordinates()
+    Eg, estep = c.get_energies()
+    xo, Eo, feo, st = orc.OracleSystem(ens, p).run(ens.x, 200, energy_every=10)
+    assert st == 0
+    d = float(np.linalg.norm(xg - xo, axis=1).max())
+    log(f"batched 200-step max |dx| {d:.3e} A")
+    assert d <= TRAJ_TOL
+    assert estep == 190
+    for t in range(ens.n_traj):
+        n = ens.res_offsets[t + 1] - ens.res_offsets[t]
+        for k in range(5):
+            assert abs(Eg[t, k] - Eo[-1][t, k]) <= FORCE_TOL * max(abs(Eo[-1][t, k]), n * p.kBT)
+    assert np.allclose(c.get_external_force(), feo[-1], rtol=1e-4, atol=1e-6)
+    assert np.array_equal(xg[ens.res_offsets[5]], c_first(P, ens)[ens.res_offsets[5]])
+
+
+def c_first(P, ens):
+    return ctx(P, ens).get_coordinates()
+
+
+def test_batched_results_do_not_depend_on_the_schedule(P, ens):
+    """Packing and steps per launch change only how work maps to the GPU."""
+    runs = []
+    for wg, k, graph in [(512, 100, 1), (1024, 20, 1), (1024, 7, 0)]:
+        c = ctx(P, ens, wg=wg, steps=k, graph=graph, energy_every=20)
+        c.step(140)
+        runs.append((c.get_coordinates(), c.get_energies()[0]))
+        c.close()
+    for x, E in runs[1:]:
+        assert np.array_equal(x, runs[0][0])
+        assert np.array_equal(E, runs[0][1])
+
+
+def test_batched_resume_is_exact(P, ens):
+    a = ctx(P, ens)
+    a.step(60)
+    b = ctx(P, ens)
+    b.step(30)
+    c = ctx(P, ens, x=b.get_coordinates())
+    c.set_step(30)
+    c.step(30)
+    assert np.array_equal(a.get_coordinates(), c.get_coordinates())
+
+
+def test_autotune_keeps_state_and_uses_cache(P, ens, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    a = ctx(P, ens)
+    x0 = a.get_coordinates()
+    a.autotune(budget_ms=100.0, cache_path=cache)
+    assert np.array_equal(a.get_coordinates(), x0)
+    assert a.get_step() == 0
+    choice = a.get_batch()
+    a.step(40)
+    b = ctx(P, ens)
+    b.step(40)
+    assert np.array_equal(a.get_coordinates(), b.get_coordinates())
+    # a second context picks the cached choice without timing
+    c = ctx(P, ens, wg=1024, steps=7)
+    c.autotune(budget_ms=100.0, cache_path=cache)
+    assert c.get_batch() == choice
+    with open(cache) as f:
+        assert len(f.read().strip().splitlines()) == 1
+
+
+def test_plain_autotune_keeps_state(P):
+    s = make_config("c1")
+    c = P.from_system(s, RunParams())
+    x0 = c.get_coordinates()
+    c.autotune(budget_ms=50.0)
+    assert np.array_equal(c.get_coordinates(), x0)
+    assert c.get_lanes() in (1, 2, 4, 8, 16)
+    c.step(20)
+    c.synchronize()
+
+
+def test_batched_matches_plain_to_tolerance(P, ens):
+    a = ctx(P, ens)
+    b = P.from_system(ens, RunParams())
+    a.step(100)
+    b.step(100)
+    d = float(np.linalg.norm(a.get_coordinates() - b.get_coordinates(), axis=1).max())
+    assert d <= TRAJ_TOL
