@@ -65,6 +65,56 @@ def cpu_baseline(system, params, n_steps):
             "seconds": dt}
 
 
+def batched_leg(P, make_config, RunParams, np, energy_every, steps, n_seq, seq_steps):
+    """The ensemble of 4,096 trajectories of 50-500 residues in the batched
+    schedule, against the same library run one trajectory at a time (plain
+    schedule) on a random sample of the ensemble's trajectories."""
+    note("generating the 4,096-trajectory ensemble")
+    s = make_config("c3")
+    p = RunParams()
+    ctx = P.from_system(s, p, schedule="batched", energy_every=energy_every)
+    ctx.autotune(budget_ms=400.0)
+    wg, K, n_packs = ctx.get_batch()
+    ctx.step(2 * K)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.synchronize()
+    dt = time.perf_counter() - t0
+    rate = s.n_res * steps / dt
+    launch_ms, _, _ = ctx.step_timed(3 * K)
+    note(f"batched: {s.n_res} residues, {n_packs} packs of <= {wg}, {K} steps/launch: "
+         f"{rate:.4e} residue-steps/s ({launch_ms * 1e3:.1f} us per launch)")
+    ctx.close()
+    rng = np.random.default_rng(5)
+    pick = rng.choice(s.n_traj, size=n_seq, replace=False)
+    work = tsum = 0.0
+    for t in pick:
+        sub = s.subset([int(t)])
+        c = P.from_system(sub, p, energy_every=energy_every)
+        c.step(100)
+        c.synchronize()
+        t0 = time.perf_counter()
+        c.step(seq_steps)
+        c.synchronize()
+        tsum += time.perf_counter() - t0
+        work += sub.n_res * seq_steps
+        c.close()
+    seq = work / tsum
+    note(f"sequential single-trajectory launches: {seq:.4e} residue-steps/s; "
+         f"batched speedup {rate / seq:.1f}x")
+    return {
+        "workload": f"{s.n_traj} independent trajectories, chain lengths U[50, 500], "
+                    f"{s.n_res} residues",
+        "value": rate, "unit": "residue-steps/s", "steps": steps,
+        "wg_residues": wg, "steps_per_launch": K, "n_packs": n_packs,
+        "launch_us": launch_ms * 1e3,
+        "sequential": {"value": seq, "trajectories": int(n_seq), "steps_each": seq_steps,
+                       "schedule": "plain, one trajectory per context"},
+        "speedup_vs_sequential": rate / seq,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +126,23 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=2000)
+    ap.add_argument("--seq-trajectories", type=int, default=16)
+    ap.add_argument("--seq-steps", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (for memory counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        note(f"copied {args.calibrate_copy} MiB 5 times")
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -163,6 +229,9 @@ def main():
             "rebuild_us": rb_ms * 1e3,
         },
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(P, make_config, RunParams, np, args.energy_every,
+                                     args.batched_steps, args.seq_trajectories, args.seq_steps)
     if not args.no_cpu_baseline:
         note(f"oracle CPU baseline: {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(s, p, args.cpu_steps)

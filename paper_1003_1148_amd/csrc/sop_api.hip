@@ -140,6 +140,8 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.pos_save = (float4 *)take(2 * n * sizeof(float4));
     d.cell_count = (int *)take(ncell * sizeof(int));
     d.cells = (float4 *)take(ncell * CELL_CAP * sizeof(float4));
+    d.occupied = (int *)take(ncell * sizeof(int));
+    d.n_occupied = (int *)take(sizeof(int));
     d.traj_cell = (int4 *)take(T * sizeof(int4));
     d.traj_lo = (int *)take(n * sizeof(int));
     d.traj_hi = (int *)take(n * sizeof(int));

@@ -71,6 +71,8 @@ struct DevBufs {
     float4 *pos_save; // one saved layer (autotuning restores the state it found)
     int *cell_count;  // residues per cell
     float4 *cells;    // CELL_CAP slots per cell: {hi.xyz, residue id bits}
+    int *occupied;    // ids of the occupied cells (unordered)
+    int *n_occupied;
     int4 *traj_cell;  // per trajectory: cell-index offset that keeps trajectories apart
     int *traj_lo;     // per residue: first residue of its trajectory
     int *traj_hi;     // per residue: one past the last residue of its trajectory

@@ -3,6 +3,8 @@
 // list; Philox4x32-10 Box-Muller noise; first-order overdamped update of
 // Eq. 2 / Algorithm 7 with compensated single-precision positions), and the
 // double-precision energy reduction.
+#include <algorithm>
+
 #include "sop_internal.hpp"
 
 namespace sop {
@@ -93,17 +95,20 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // Verlet-list rebuild: clear cell counts -> bin into fixed-capacity cells ->
 // one workgroup per cell fills the rows of its residues
 // ---------------------------------------------------------------------------
-__global__ void k_clear(int *__restrict__ a, int n)
+__global__ void k_clear(int *__restrict__ a, int n, int *__restrict__ n_occupied)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         a[i] = 0;
+    if (i == 0)
+        *n_occupied = 0;
 }
 
 // Also advances the step counter of graph replays (once per rebuild) when
 // step_base is given.
 __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const int4 *__restrict__ traj_cell,
-                      int *__restrict__ count, float4 *__restrict__ cells, unsigned *__restrict__ err,
+                      int *__restrict__ count, float4 *__restrict__ cells, int *__restrict__ occupied,
+                      int *__restrict__ n_occupied, unsigned *__restrict__ err,
                       long long *step_base, long long *step_next, int period)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,6 +128,8 @@ __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const in
     const int cz = wrap_cell(p.z, g.inv_cell, off.z, g.gz);
     const int c = cx + g.gx * (cy + g.gy * cz);
     const int slot = atomicAdd(&count[c], 1);
+    if (slot == 0)
+        occupied[atomicAdd(n_occupied, 1)] = c;  // order varies; each cell is filled on its own
     if (slot < CELL_CAP)
         cells[(size_t)c * CELL_CAP + slot] = make_float4(p.x, p.y, p.z, __int_as_float(i));
     else
@@ -130,6 +137,8 @@ __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const in
 }
 
 struct FillArgs {
+    const int *occupied;
+    const int *n_occupied;
     const int *count;
     const float4 *cells;
     const int *traj_lo;
@@ -160,13 +169,13 @@ __global__ __launch_bounds__(WG) void k_fill(FillArgs a)
     __shared__ int seg_n[27];
     __shared__ int seg_off[28];
 
-    const int c = blockIdx.x;
-    const int m = min(a.count[c], CELL_CAP);
-    if (m == 0)
-        return;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const GridDev g = a.g;
+    const int n_occ = *a.n_occupied;
+    for (int oc = blockIdx.x; oc < n_occ; oc += gridDim.x) {
+    const int c = a.occupied[oc];
+    const int m = min(a.count[c], CELL_CAP);
     if (t < 27) {
         const int cx = c % g.gx, cy = (c / g.gx) % g.gy, cz = c / (g.gx * g.gy);
         const int xx = (cx + (t % 3) - 1 + g.gx) % g.gx;
@@ -230,6 +239,8 @@ __global__ __launch_bounds__(WG) void k_fill(FillArgs a)
             const int tlo = a.traj_lo[i], thi = a.traj_hi[i];
             const int2 row = a.trow[i];
             const int nex = (row.y & 4095) + (row.y >> 12);
+            // bonded and native partners of i, one per lane (the first 64)
+            const int pv = lane < nex ? __float_as_int(a.tent[row.x + lane].x) : -1;
             int *rowp = a.list + (size_t)(i / G) * a.cap * G + (i % G) * LANES;
             int cnt = own_cnt[mi];
             for (int q0 = 0; q0 < tot; q0 += 64) {
@@ -242,7 +253,10 @@ __global__ __launch_bounds__(WG) void k_fill(FillArgs a)
                     ok = j != i && j >= tlo && j < thi && within_cutoff(p, cq, a.rc2);
                 }
                 if (__ballot(ok)) {
-                    for (int e = 0; e < nex; ++e)
+                    const int ne = min(nex, 64);
+                    for (int e = 0; e < ne; ++e)
+                        ok = ok && (j != __builtin_amdgcn_readlane(pv, e));
+                    for (int e = 64; e < nex; ++e)
                         ok = ok && (__float_as_int(a.tent[row.x + e].x) != j);
                 }
                 const unsigned long long mask = __ballot(ok);
@@ -264,6 +278,8 @@ __global__ __launch_bounds__(WG) void k_fill(FillArgs a)
         a.list_cnt[i] = own_cnt[mi];
         if (own_cnt[mi] > a.cap)
             atomicOr(a.err, ERR_OVERFLOW);
+    }
+    __syncthreads();  // LDS is reused by the next cell
     }
 }
 
@@ -871,7 +887,8 @@ inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per);
 template <int LANES>
 void fill_lanes(const FillArgs &f, int n_cells, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill<LANES>, dim3(n_cells), dim3(WG), 0, s, f);
+    // occupied cells are spread over a bounded grid of workgroups
+    hipLaunchKernelGGL(k_fill<LANES>, dim3(std::min(n_cells, 2048)), dim3(WG), 0, s, f);
 }
 
 template <int LANES, bool ENERGY, int MODE>
@@ -902,11 +919,14 @@ void step_dispatch(int lanes, const StepArgs &a, hipStream_t s)
 void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int lanes, const GridDev &g, float rc2,
                     hipStream_t s, bool advance_step_base, int list_every)
 {
-    hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells);
+    hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells,
+                       b.n_occupied);
     hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, WG)), dim3(WG), 0, s, b.pos[cur], n, g, b.traj_cell,
-                       b.cell_count, b.cells, b.err, advance_step_base ? b.step_base : nullptr, b.step_next,
+                       b.cell_count, b.cells, b.occupied, b.n_occupied, b.err, advance_step_base ? b.step_base : nullptr, b.step_next,
                        list_every);
     FillArgs f{};
+    f.occupied = b.occupied;
+    f.n_occupied = b.n_occupied;
     f.count = b.cell_count;
     f.cells = b.cells;
     f.traj_lo = b.traj_lo;
