@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed list periods")
     ap.add_argument("--warmup", type=int, default=100, help="untimed list periods")
-    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="residues per workgroup (64/128/256; 0 = autotune)")
     ap.add_argument("--graph-periods", type=int, default=10)
     ap.add_argument("--energy-every", type=int, default=1000)
     ap.add_argument("--timing-steps", type=int, default=300)
@@ -162,8 +162,10 @@ def main():
     s = make_config("c2")
     p = RunParams()
     L = p.list_every
-    ctx = P.from_system(s, p, lanes=args.lanes, graph_steps=args.graph_periods,
+    ctx = P.from_system(s, p, tile=args.tile, graph_steps=args.graph_periods,
                         energy_every=args.energy_every)
+    if args.tile == 0:
+        ctx.autotune(budget_ms=300.0)
     ctx.build_pairlist()
     n_pairs = len(ctx.get_pairlist())
     N = s.n_res
@@ -210,7 +212,7 @@ def main():
             "n_res": N,
             "md_steps_per_step": L,
             "energy_every": args.energy_every,
-            "lanes": ctx.get_lanes(),
+            "tile": ctx.get_tile(),
             "graph_periods": args.graph_periods,
             "bonds_per_res": round(b, 4),
             "natives_per_res": round(c, 4),

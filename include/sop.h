@@ -109,8 +109,8 @@ sop_status sop_destroy(sop_ctx *ctx);
  *   fixed        uint8[n_res] (nonzero = residue never moves) or NULL
  * Returns SOP_E_ARG for an id out of range, a pair spanning two trajectories,
  * a self pair, a duplicate pair, a pair both bonded and native, r0 <= 0, or
- * more than 4095 bonds on one residue.  Host only.  Invalidates any bound
- * workspace.
+ * more than 64 bonded plus native partners on one residue.  Host only.
+ * Invalidates any bound workspace.
  */
 sop_status sop_load_topology(sop_ctx *ctx, int32_t n_traj, const int64_t *res_offsets,
                              const uint32_t *stream_ids, int64_t n_bonds, const int32_t *bonds,
@@ -165,7 +165,7 @@ sop_status sop_get_batch(const sop_ctx *ctx, int32_t *wg_residues, int32_t *step
                          int32_t *n_packs);
 
 /*
- * Choose the schedule parameters by timing: lanes per residue (plain) or
+ * Choose the schedule parameters by timing: tile size (plain) or
  * workgroup size and steps per launch (batched).  Each candidate runs from
  * the current state, which is restored afterwards, for about budget_ms in
  * total.  With a cache_path, a matching entry (device, schedule, topology
@@ -175,14 +175,17 @@ sop_status sop_get_batch(const sop_ctx *ctx, int32_t *wg_residues, int32_t *step
 sop_status sop_autotune(sop_ctx *ctx, double budget_ms, const char *cache_path);
 
 /*
- * Lanes of a 64-wide wavefront that cooperate on one residue's pair loops
- * (1, 2, 4, 8 or 16; 0 selects a default from the system size).  Changes
- * the list layout; call before sop_bind_workspace.
+ * Plain schedule: residues per workgroup ("tile" of consecutive residues;
+ * 64, 128 or 256; 0 selects a default from the system size).  At each list
+ * rebuild a tile gathers the residues it interacts with into at most 1024
+ * (tiles of 64 or 128) or 2048 (tiles of 256) LDS slots; a tile that needs
+ * more reports SOP_E_LIST_OVERFLOW.  May be changed after binding; the list
+ * is rebuilt at the next step.
  */
-sop_status sop_set_lanes(sop_ctx *ctx, int32_t lanes);
+sop_status sop_set_tile(sop_ctx *ctx, int32_t tile);
 
-/* Lanes per residue in effect (after a topology is loaded). */
-sop_status sop_get_lanes(const sop_ctx *ctx, int32_t *lanes);
+/* Tile size in effect (after a topology is loaded). */
+sop_status sop_get_tile(const sop_ctx *ctx, int32_t *tile);
 
 /*
  * HIP graphs: 0 launches every kernel from the host; k > 0 captures k whole
@@ -199,7 +202,7 @@ sop_status sop_set_energy_interval(sop_ctx *ctx, int64_t k);
 /* ---- workspace ----------------------------------------------------------- */
 
 /* Bytes of device memory the bound workspace must provide (256-byte aligned
- * start).  Depends on the topology, the list capacity and the lanes. */
+ * start).  Depends on the topology, the schedule and the list capacity. */
 sop_status sop_workspace_size(const sop_ctx *ctx, size_t *bytes);
 
 /*

@@ -62,12 +62,12 @@ def lib():
             "sop_load_topology": [vp, i32, vp, vp, i64, vp, vp, i64, vp, vp, vp],
             "sop_set_pulling": [vp, i32, i64, dbl, vp, vp],
             "sop_set_tip": [vp, dbl, dbl, dbl, vp, vp],
-            "sop_set_lanes": [vp, i32],
+            "sop_set_tile": [vp, i32],
             "sop_set_schedule": [vp, i32],
             "sop_set_batch": [vp, i32, i32],
             "sop_get_batch": [vp, vp, vp, vp],
             "sop_autotune": [vp, dbl, C.c_char_p],
-            "sop_get_lanes": [vp, vp],
+            "sop_get_tile": [vp, vp],
             "sop_set_graph_steps": [vp, i32],
             "sop_set_energy_interval": [vp, i64],
             "sop_workspace_size": [vp, vp],
@@ -172,8 +172,8 @@ class Context:
         w = np.ascontiguousarray(v, dtype=np.float64)
         self._check(lib().sop_set_tip(self.h, float(radius), float(eps), float(sigma), _p(a), _p(w)))
 
-    def set_lanes(self, lanes):
-        self._check(lib().sop_set_lanes(self.h, int(lanes)))
+    def set_tile(self, tile):
+        self._check(lib().sop_set_tile(self.h, int(tile)))
 
     def set_schedule(self, schedule):
         if isinstance(schedule, str):
@@ -193,9 +193,9 @@ class Context:
         cp = None if cache_path is None else os.fsencode(cache_path)
         self._check(lib().sop_autotune(self.h, float(budget_ms), cp))
 
-    def get_lanes(self):
+    def get_tile(self):
         v = C.c_int32(0)
-        self._check(lib().sop_get_lanes(self.h, C.byref(v)))
+        self._check(lib().sop_get_tile(self.h, C.byref(v)))
         return v.value
 
     def set_graph_steps(self, k):
@@ -297,7 +297,7 @@ def status_string(st):
     return lib().sop_status_string(int(st)).decode()
 
 
-def from_system(system, params, stream=None, lanes=0, graph_steps=1, energy_every=0,
+def from_system(system, params, stream=None, tile=0, graph_steps=1, energy_every=0,
                 coordinates=None, schedule="plain", batch=None):
     """Load a system description (duck-typed: x, res_offsets, stream_ids, bonds,
     bond_r0, natives, native_r0, fixed, pulls, tip), choose the schedule
@@ -314,7 +314,7 @@ def from_system(system, params, stream=None, lanes=0, graph_steps=1, energy_ever
     ctx.set_schedule(schedule)
     if batch is not None:
         ctx.set_batch(*batch)
-    ctx.set_lanes(lanes)
+    ctx.set_tile(tile)
     ctx.set_graph_steps(graph_steps)
     ctx.set_energy_interval(energy_every)
     ctx.bind_workspace()

@@ -35,7 +35,7 @@ struct sop_ctx {
 
     // schedule: plain (kernel per step) or batched (persistent packs)
     int schedule = SOP_SCHEDULE_PLAIN;
-    int lanes_req = 0, lanes = 1, cap = 256;
+    int tile_req = 0, tile = 128, cap = 256;
     int graph_steps = 1;
     long long energy_every = 0;
     int batch_wg_req = 0, batch_wg = 1024, batch_steps = 100;
@@ -82,12 +82,13 @@ sop_status hip_fail(sop_ctx *c, hipError_t e, const char *what)
             return hip_fail((ctx), e_, #expr);             \
     } while (0)
 
+// A list that overflowed leaves the forces undefined, so it is reported first.
 sop_status status_from_bits(unsigned bits)
 {
+    if (bits & (ERR_OVERFLOW | ERR_CELL | ERR_STAGE))
+        return SOP_E_LIST_OVERFLOW;
     if (bits & ERR_FENE)
         return SOP_E_FENE;
-    if (bits & (ERR_OVERFLOW | ERR_CELL))
-        return SOP_E_LIST_OVERFLOW;
     if (bits & ERR_TIP)
         return SOP_E_TIP;
     if (bits & ERR_NONFINITE)
@@ -97,12 +98,14 @@ sop_status status_from_bits(unsigned bits)
 
 const char *bits_message(unsigned bits)
 {
-    if (bits & ERR_FENE)
-        return "a FENE bond reached |r - r0| >= R0";
     if (bits & ERR_OVERFLOW)
         return "a residue has more list partners than the list capacity";
     if (bits & ERR_CELL)
         return "more than 128 residues fell into one cell of the list-rebuild grid";
+    if (bits & ERR_STAGE)
+        return "a tile of the plain schedule interacts with more residues than its LDS staging holds, or its cell neighbourhood exceeds the rebuild's LDS table";
+    if (bits & ERR_FENE)
+        return "a FENE bond reached |r - r0| >= R0";
     if (bits & ERR_TIP)
         return "a residue reached the tip surface";
     if (bits & ERR_NONFINITE)
@@ -118,9 +121,15 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     const size_t n = (size_t)c->n_res;
     const size_t T = (size_t)c->n_traj;
     const bool plain = c->schedule == SOP_SCHEDULE_PLAIN;
-    // padded for 64 residues per slice so that any lane count fits
-    const size_t list_elems = plain ? ((n + 63) / 64) * 64 * (size_t)c->cap : 0;
-    const size_t list16_elems = plain ? 0 : n * (size_t)c->cap;
+    // padded for the largest tile so that any tile size fits
+    const size_t n_pad = ((n + 255) / 256) * 256;
+    const size_t list16_elems = plain ? n_pad * (size_t)c->cap : n * (size_t)c->cap;
+    const size_t topo2_elems = plain ? n_pad * TOPO_CAP : 0;
+    const size_t n_tiles_max = plain ? (n + 63) / 64 : 0;   // tiles of the smallest size
+    // slots of every tile, for the largest need over the tile sizes
+    const size_t stage_elems =
+        plain ? std::max({((n + 63) / 64) * 1024, ((n + 127) / 128) * 1024, ((n + 255) / 256) * 2048})
+              : 0;
     const size_t ncell = plain ? (size_t)c->n_cells_cap : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -133,15 +142,16 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.pos[1] = (float4 *)take(2 * n * sizeof(float4));
     d.trow = (int2 *)take(n * sizeof(int2));
     d.tent = (float2 *)take(c->tent.size() * sizeof(float2));
-    d.list = (int *)take(list_elems * sizeof(int));
     d.list_cnt = (int *)take(n * sizeof(int));
     d.list16 = (unsigned short *)take(list16_elems * sizeof(unsigned short));
+    d.topo2 = (uint2 *)take(topo2_elems * sizeof(uint2));
+    d.stage = (int *)take(stage_elems * sizeof(int));
+    d.stage_cnt = (int *)take(n_tiles_max * sizeof(int));
     d.pack_res = (int *)take((T + 1) * sizeof(int));
     d.pos_save = (float4 *)take(2 * n * sizeof(float4));
     d.cell_count = (int *)take(ncell * sizeof(int));
     d.cells = (float4 *)take(ncell * CELL_CAP * sizeof(float4));
-    d.occupied = (int *)take(ncell * sizeof(int));
-    d.n_occupied = (int *)take(sizeof(int));
+    d.cell_of = (int *)take((plain ? n : 0) * sizeof(int));
     d.traj_cell = (int4 *)take(T * sizeof(int4));
     d.traj_lo = (int *)take(n * sizeof(int));
     d.traj_hi = (int *)take(n * sizeof(int));
@@ -162,16 +172,15 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     return off;
 }
 
-int default_lanes(long long n)
+// Residues per workgroup of the plain schedule: enough tiles to cover the
+// 256 compute units a few times over.
+int default_tile(long long n)
 {
-    // enough wavefronts to cover the 1024 SIMDs several times over
-    if (n >= 262144)
-        return 2;
-    if (n >= 65536)
-        return 4;
-    if (n >= 8192)
-        return 8;
-    return 16;
+    if (n >= 4 * 256 * 256)
+        return 256;
+    if (n >= 2 * 256 * 128)
+        return 128;
+    return 64;
 }
 
 void destroy_graphs(sop_ctx *c)
@@ -324,13 +333,13 @@ sop_status need_ready(sop_ctx *c)
 
 void rebuild(sop_ctx *c, hipStream_t s, bool advance)
 {
-    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, c->grid, list_rc2(c), s, advance,
+    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), cell_edge(c), s, advance,
                    c->p.list_every);
 }
 
 void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy)
 {
-    launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+    launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                 c->pulls.empty() ? 0 : 1, energy, 0, base, off, s);
     if (energy)
         launch_reduce_energy(c->b, c->n_traj, s);
@@ -560,8 +569,9 @@ sop_status sop_load_topology(sop_ctx *c, int32_t n_traj, const int64_t *res_offs
     for (long long i = 0; i < n; ++i) {
         std::sort(rb[i].begin(), rb[i].end());
         std::sort(rn[i].begin(), rn[i].end());
-        if (rb[i].size() > 4095 || rn[i].size() >= (1u << 19))
-            return fail(c, SOP_E_ARG, "too many bonds or natives on residue " + std::to_string(i));
+        if (rb[i].size() + rn[i].size() > (size_t)TOPO_CAP)
+            return fail(c, SOP_E_ARG, "more than " + std::to_string(TOPO_CAP) +
+                                          " bonded and native partners on residue " + std::to_string(i));
         c->trow[i] = int2{(int)c->tent.size(), (int)(rb[i].size() | (rn[i].size() << 12))};
         for (auto &e : rb[i]) {
             int bits = e.first;
@@ -579,7 +589,7 @@ sop_status sop_load_topology(sop_ctx *c, int32_t n_traj, const int64_t *res_offs
     c->pulls.clear();
     c->pull_slot.assign(n, -1);
     c->tip = TipDev{};
-    c->lanes = c->lanes_req ? c->lanes_req : default_lanes(n);
+    c->tile = c->tile_req ? c->tile_req : default_tile(n);
     c->max_len = 0;
     for (int t = 0; t < n_traj; ++t)
         c->max_len = std::max<long long>(c->max_len, res_offsets[t + 1] - res_offsets[t]);
@@ -652,31 +662,31 @@ sop_status sop_set_tip(sop_ctx *c, double radius, double eps, double sigma, cons
     return SOP_OK;
 }
 
-sop_status sop_set_lanes(sop_ctx *c, int32_t lanes)
+sop_status sop_set_tile(sop_ctx *c, int32_t tile)
 {
     if (!c)
         return SOP_E_ARG;
-    if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
-        return fail(c, SOP_E_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
-    c->lanes_req = lanes;
+    if (!(tile == 0 || tile == 64 || tile == 128 || tile == 256))
+        return fail(c, SOP_E_ARG, "tile must be 0, 64, 128 or 256 residues");
+    c->tile_req = tile;
     if (c->topo) {
-        const int nl = lanes ? lanes : default_lanes(c->n_res);
-        if (nl != c->lanes) {
-            c->lanes = nl;
-            c->list_valid = false;  // the list layout follows the lane count
+        const int nt = tile ? tile : default_tile(c->n_res);
+        if (nt != c->tile) {
+            c->tile = nt;
+            c->list_valid = false;  // the list layout follows the tile size
             destroy_graphs(c);
         }
     }
     return SOP_OK;
 }
 
-sop_status sop_get_lanes(const sop_ctx *c, int32_t *lanes)
+sop_status sop_get_tile(const sop_ctx *c, int32_t *tile)
 {
-    if (!c || !lanes)
+    if (!c || !tile)
         return SOP_E_ARG;
     if (!c->topo)
         return SOP_E_STATE;
-    *lanes = c->lanes;
+    *tile = c->tile;
     return SOP_OK;
 }
 
@@ -801,6 +811,13 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
     HIP_TRY(c, hipMemcpyAsync(b.res_offsets, c->res_offsets.data(), (c->n_traj + 1) * sizeof(long long),
                               hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(b.list_cnt, 0, n * sizeof(int), s));
+    if (c->schedule == SOP_SCHEDULE_PLAIN) {
+        // slot arrays start as slot 0, which every tile's staging holds
+        const size_t n_pad = ((n + 255) / 256) * 256;
+        HIP_TRY(c, hipMemsetAsync(b.list16, 0, n_pad * c->cap * sizeof(unsigned short), s));
+        HIP_TRY(c, hipMemsetAsync(b.topo2, 0, n_pad * TOPO_CAP * sizeof(uint2), s));
+        HIP_TRY(c, hipMemsetAsync(b.stage_cnt, 0, ((n + 63) / 64) * sizeof(int), s));
+    }
     HIP_TRY(c, hipMemsetAsync(b.res_energy, 0, n * RES_E * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.energy, 0, (size_t)c->n_traj * SOP_NTERMS * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.f_ext, 0, (size_t)c->n_traj * sizeof(double), s));
@@ -934,15 +951,26 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
                 }
         }
     } else {
-        const int G = 64 / c->lanes;
-        std::vector<int> list(((n + G - 1) / G) * (size_t)G * c->cap);
-        HIP_TRY(c, hipMemcpy(list.data(), c->b.list, list.size() * sizeof(int), hipMemcpyDeviceToHost));
-        for (long long i = 0; i < n; ++i)
-            for (int p = 0; p < std::min(cnt[i], c->cap); ++p) {
-                int j = list[list_index_host((int)i, p, c->cap, c->lanes)];
+        // rows hold slots of their tile; the tile's stage maps slots to ids
+        const int T = c->tile, SM = stage_max_host(T);
+        const size_t n_tiles = (size_t)((n + T - 1) / T);
+        std::vector<unsigned short> list(n_tiles * (size_t)T * c->cap);
+        std::vector<int> stage(n_tiles * (size_t)SM), stage_cnt(n_tiles);
+        HIP_TRY(c, hipMemcpy(list.data(), c->b.list16, list.size() * sizeof(unsigned short),
+                             hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(stage.data(), c->b.stage, stage.size() * sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(stage_cnt.data(), c->b.stage_cnt, n_tiles * sizeof(int), hipMemcpyDeviceToHost));
+        for (long long i = 0; i < n; ++i) {
+            const size_t tile = (size_t)(i / T);
+            for (int k = 0; k < std::min(cnt[i], c->cap); ++k) {
+                const int sl = list[list16_index_host(i, k, c->cap, T)];
+                if (sl >= stage_cnt[tile])
+                    return fail(c, SOP_E_LIST_OVERFLOW, "list entry outside its tile's staging set");
+                const int j = stage[tile * SM + sl];
                 if (i < j)
                     pairs.push_back({(int)i, j});
             }
+        }
     }
     std::sort(pairs.begin(), pairs.end());
     *n_pairs = (int64_t)pairs.size();
@@ -966,7 +994,7 @@ sop_status sop_compute_forces(sop_ctx *c, double *f, double *energies, double *f
     } else {
         if (stale)
             rebuild(c, c->stream, false);
-        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                     c->pulls.empty() ? 0 : 1, true, 1, nullptr, c->step, c->stream);
         launch_reduce_energy(c->b, c->n_traj, c->stream);
     }
@@ -1146,7 +1174,7 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
         }
         const bool en = E > 0 && c->step % E == 0;
         (void)hipEventRecord(ev[2], c->stream);
-        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->lanes, step_consts(c), c->tip,
+        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                     c->pulls.empty() ? 0 : 1, en, 0, nullptr, c->step, c->stream);
         (void)hipEventRecord(ev[3], c->stream);
         if (en)
@@ -1272,7 +1300,7 @@ std::string cache_key(const sop_ctx *c)
     return buf;
 }
 
-// Cache lines: <key> <a> <b>   (lanes 0 for the plain schedule: a = lanes)
+// Cache lines: <key> <a> <b>   (plain schedule: a = tile, b = 0; batched: a = wg, b = steps)
 bool cache_lookup(const char *path, const std::string &key, int *a, int *b)
 {
     if (!path)
@@ -1349,7 +1377,7 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
     if (cache_lookup(cache_path, key, &a, &b)) {
         if (c->schedule == SOP_SCHEDULE_BATCHED)
             return sop_set_batch(c, a, b);
-        return sop_set_lanes(c, a);
+        return sop_set_tile(c, a);
     }
     const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
     HIP_TRY(c, hipMemcpyAsync(c->b.pos_save, c->b.pos[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1361,8 +1389,8 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
                 for (int k : {20, 50, 100, 200})
                     cand.push_back({wg, k});
     } else {
-        for (int l : {1, 2, 4, 8, 16})
-            cand.push_back({l, 0});
+        for (int tl : {64, 128, 256})
+            cand.push_back({tl, 0});
     }
     // steps per trial from the budget, using the current schedule's speed as a guide
     double rate0 = 0.0;
@@ -1380,7 +1408,7 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
         if (c->schedule == SOP_SCHEDULE_BATCHED)
             st = sop_set_batch(c, cd.first, cd.second);
         else
-            st = sop_set_lanes(c, cd.first);
+            st = sop_set_tile(c, cd.first);
         if (st != SOP_OK)
             return st;
         double rate = 0.0;
@@ -1393,7 +1421,7 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
         }
     }
     st = c->schedule == SOP_SCHEDULE_BATCHED ? sop_set_batch(c, pick.first, pick.second)
-                                             : sop_set_lanes(c, pick.first);
+                                             : sop_set_tile(c, pick.first);
     if (st != SOP_OK)
         return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -18,6 +18,7 @@ enum : unsigned {
     ERR_NONFINITE = 1u << 2,
     ERR_TIP = 1u << 3,
     ERR_CELL = 1u << 4,  // a rebuild cell holds more than CELL_CAP residues
+    ERR_STAGE = 1u << 5, // a tile interacts with more residues than its LDS staging holds
 };
 
 // Per-residue energy record written on energy steps:
@@ -55,6 +56,10 @@ struct GridDev {
 // Residues per cell of the list-rebuild grid (fixed capacity; more is the
 // list-overflow error).
 constexpr int CELL_CAP = 128;
+// Bonded plus native partners per residue (larger is rejected at load).
+constexpr int TOPO_CAP = 64;
+// Largest staging set of a tile of the plain schedule (its LDS footprint).
+constexpr int STAGE_MAX = 2048;
 
 // Device buffers carved out of the caller's workspace.
 struct DevBufs {
@@ -64,15 +69,16 @@ struct DevBufs {
     float4 *pos[2];
     int2 *trow;       // per residue: {first entry, n_bond | n_native << 12}
     float2 *tent;     // {partner id bits, r0}: bonds first, then natives
-    int *list;        // lane-sliced list (see list_index_host)
     int *list_cnt;    // partners per residue
-    unsigned short *list16;  // batched form: per-pack list of local indices
+    unsigned short *list16;  // plain: rows as tile slots, 8 per lane per chunk; batched: per-pack local indices
+    uint2 *topo2;            // plain: {slot, r0 bits} of bonded/native partners, (i/T)*TOPO_CAP*T + e*T + i%T
+    int *stage;       // plain: per tile, global ids of its slots (stage_max per tile)
+    int *stage_cnt;   // plain: slots per tile
     int *pack_res;    // batched form: first residue of each pack (n_packs + 1)
     float4 *pos_save; // one saved layer (autotuning restores the state it found)
     int *cell_count;  // residues per cell
     float4 *cells;    // CELL_CAP slots per cell: {hi.xyz, residue id bits}
-    int *occupied;    // ids of the occupied cells (unordered)
-    int *n_occupied;
+    int *cell_of;     // per residue: its cell at the last rebuild
     int4 *traj_cell;  // per trajectory: cell-index offset that keeps trajectories apart
     int *traj_lo;     // per residue: first residue of its trajectory
     int *traj_hi;     // per residue: one past the last residue of its trajectory
@@ -98,10 +104,11 @@ struct StepConsts {
 };
 
 // ---- kernel launchers (sop_kernels.hip) ----------------------------------
-void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int lanes, const GridDev &g,
-                    float rc2, hipStream_t s, bool advance_step_base, int list_every);
+// Plain schedule, tiles of `tile` residues (64, 128 or 256).
+void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int tile, const GridDev &g,
+                    float rc2, float edge, hipStream_t s, bool advance_step_base, int list_every);
 // mode: 0 = step, 1 = forces only
-void launch_step(const DevBufs &b, int cur, int n_res, int cap, int lanes, const StepConsts &c,
+void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode,
                  const long long *step_base, long long step_off, hipStream_t s);
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
@@ -116,13 +123,13 @@ void launch_set_step(long long *dst, long long value, hipStream_t s);
 void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long long step, uint4 *words,
                   float4 *g, hipStream_t s);
 
-// Index of entry p of residue r in the lane-sliced list.
-inline size_t list_index_host(int r, int p, int cap, int lanes)
+// Plain schedule: entry k of residue r's row (a slot of its tile), and the
+// slots a tile of `tile` residues can stage.
+inline size_t list16_index_host(long long r, int k, int cap, int tile)
 {
-    const int G = 64 / lanes;
-    const size_t slice = (size_t)(r / G);
-    const int g = r % G;
-    return slice * (size_t)cap * G + (size_t)(p / lanes) * 64 + (size_t)g * lanes + (p % lanes);
+    return (size_t)(r / tile) * (size_t)cap * tile + (size_t)(k >> 3) * (8 * (size_t)tile) +
+           (size_t)(r % tile) * 8 + (size_t)(k & 7);
 }
+inline int stage_max_host(int tile) { return tile >= 256 ? 2048 : 1024; }
 
 }  // namespace sop

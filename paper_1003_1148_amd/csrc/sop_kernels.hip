@@ -12,7 +12,6 @@ namespace sop {
 namespace {
 
 constexpr int WG = 256;       // threads per workgroup (4 wave64)
-constexpr int CHUNK = 1024;   // candidates staged in LDS per pass of the fill
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the Gaussian mapping
@@ -95,21 +94,28 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // Verlet-list rebuild: clear cell counts -> bin into fixed-capacity cells ->
 // one workgroup per cell fills the rows of its residues
 // ---------------------------------------------------------------------------
-__global__ void k_clear(int *__restrict__ a, int n, int *__restrict__ n_occupied)
+__global__ void k_clear(int *__restrict__ a, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         a[i] = 0;
-    if (i == 0)
-        *n_occupied = 0;
+}
+
+// Cell index of one residue in the wrapped grid (the trajectory's offset
+// keeps independent trajectories in separate cells).
+__device__ __forceinline__ int cell_index(const float4 &p, const int4 &off, const GridDev &g)
+{
+    const int cx = wrap_cell(p.x, g.inv_cell, off.x, g.gx);
+    const int cy = wrap_cell(p.y, g.inv_cell, off.y, g.gy);
+    const int cz = wrap_cell(p.z, g.inv_cell, off.z, g.gz);
+    return cx + g.gx * (cy + g.gy * cz);
 }
 
 // Also advances the step counter of graph replays (once per rebuild) when
 // step_base is given.
 __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const int4 *__restrict__ traj_cell,
-                      int *__restrict__ count, float4 *__restrict__ cells, int *__restrict__ occupied,
-                      int *__restrict__ n_occupied, unsigned *__restrict__ err,
-                      long long *step_base, long long *step_next, int period)
+                      int *__restrict__ count, float4 *__restrict__ cells, int *__restrict__ cell_of,
+                      unsigned *__restrict__ err, long long *step_base, long long *step_next, int period)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && step_base) {
@@ -122,177 +128,534 @@ __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const in
     const float4 p = pos[2 * i];
     if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))
         atomicOr(err, ERR_NONFINITE);
-    const int4 off = traj_cell[__float_as_int(pos[2 * i + 1].w)];
-    const int cx = wrap_cell(p.x, g.inv_cell, off.x, g.gx);
-    const int cy = wrap_cell(p.y, g.inv_cell, off.y, g.gy);
-    const int cz = wrap_cell(p.z, g.inv_cell, off.z, g.gz);
-    const int c = cx + g.gx * (cy + g.gy * cz);
+    const int c = cell_index(p, traj_cell[__float_as_int(pos[2 * i + 1].w)], g);
+    cell_of[i] = c;
     const int slot = atomicAdd(&count[c], 1);
-    if (slot == 0)
-        occupied[atomicAdd(n_occupied, 1)] = c;  // order varies; each cell is filled on its own
     if (slot < CELL_CAP)
         cells[(size_t)c * CELL_CAP + slot] = make_float4(p.x, p.y, p.z, __int_as_float(i));
     else
         atomicOr(err, ERR_CELL);
 }
 
-struct FillArgs {
-    const int *occupied;
-    const int *n_occupied;
+// ---------------------------------------------------------------------------
+// Pair terms of Eq. 1, external terms and the compensated update, shared by
+// the plain and the batched schedules.
+// ---------------------------------------------------------------------------
+
+// Per-residue force and, on energy steps, double energy/virial sums.
+struct Acc {
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    double e_b = 0.0, e_n = 0.0, e_r = 0.0, vir = 0.0;
+};
+
+struct PairConsts {
+    float kf, inv_R0sq, R0sq, eh, eh12, el, el6, sg2;
+};
+
+__device__ __forceinline__ PairConsts pair_consts(const StepConsts &c)
+{
+    PairConsts k;
+    k.kf = c.k_fene;
+    k.inv_R0sq = c.inv_R0sq;
+    k.R0sq = c.R0sq;
+    k.eh = c.eps_h;
+    k.eh12 = 12.0f * c.eps_h;
+    k.el = c.eps_l;
+    k.el6 = 6.0f * c.eps_l;
+    k.sg2 = c.sigma2;
+    return k;
+}
+
+// FENE: -(k R0^2/2) ln(1 - (r - r0)^2/R0^2); |r - r0| >= R0 sets `broken`.
+__device__ __forceinline__ void add_fene(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
+                                         const float4 &lj, float r0, const PairConsts &k, bool rec,
+                                         bool &broken)
+{
+    const float3 d = pair_delta(hi, lo, hj, lj);
+    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    const float rr = __builtin_amdgcn_sqrtf(r2);
+    const float dl = rr - r0;
+    float x = 1.0f - dl * dl * k.inv_R0sq;
+    if (!(x > 0.0f)) {
+        broken = true;
+        x = 1.0f;
+    }
+    const float coef = -k.kf * dl * fast_rcp(x * rr);
+    A.fx += coef * d.x;
+    A.fy += coef * d.y;
+    A.fz += coef * d.z;
+    if (rec) {
+        const double dd = (double)dl;
+        const double R0sq = (double)k.R0sq;
+        A.e_b += -0.5 * (double)k.kf * R0sq * log1p(-dd * dd / R0sq);
+        A.vir += -(double)rr * (double)k.kf * dd / (1.0 - dd * dd / R0sq);
+    }
+}
+
+// Native contact: eps_h [(r0/r)^12 - 2 (r0/r)^6].
+__device__ __forceinline__ void add_native(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
+                                           const float4 &lj, float r0, const PairConsts &k, bool rec)
+{
+    const float3 d = pair_delta(hi, lo, hj, lj);
+    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    const float ir2 = fast_rcp(r2);
+    const float s = r0 * r0 * ir2;
+    const float q = s * s * s;
+    const float coef = k.eh12 * (q * q - q) * ir2;
+    A.fx += coef * d.x;
+    A.fy += coef * d.y;
+    A.fz += coef * d.z;
+    if (rec) {
+        A.e_n += (double)(k.eh * (q * q - 2.0f * q));
+        A.vir += (double)(k.eh12 * (q * q - q));
+    }
+}
+
+// Soft repulsion: eps_l (sigma/r)^6.
+__device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const float4 &lo,
+                                              const float4 &hj, const float4 &lj, const PairConsts &k,
+                                              bool rec)
+{
+    const float3 d = pair_delta(hi, lo, hj, lj);
+    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    const float ir2 = fast_rcp(r2);
+    const float s = k.sg2 * ir2;
+    const float q = s * s * s;
+    const float coef = k.el6 * q * ir2;
+    A.fx += coef * d.x;
+    A.fy += coef * d.y;
+    A.fz += coef * d.z;
+    if (rec) {
+        A.e_r += (double)(k.el * q);
+        A.vir += (double)(k.el6 * q);
+    }
+}
+
+// Cantilever `pull` (index or -1) and tip on one residue at t_n = step*h.
+__device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep, const float4 &hi,
+                                             const float4 &lo, long long step, double h, int pull,
+                                             const PullDev *pulls, const TipDev &tip, bool rec,
+                                             unsigned *err)
+{
+    if (pull < 0 && !tip.on)
+        return;
+    const double tn = (double)step * h;
+    const double px = (double)hi.x + (double)lo.x;
+    const double py = (double)hi.y + (double)lo.y;
+    const double pz = (double)hi.z + (double)lo.z;
+    if (pull >= 0) {
+        const PullDev pd = pulls[pull];
+        const double dx = pd.anchor0[0] + pd.v[0] * tn - px;
+        const double dy = pd.anchor0[1] + pd.v[1] * tn - py;
+        const double dz = pd.anchor0[2] + pd.v[2] * tn - pz;
+        A.fx += (float)(pd.kappa * dx);
+        A.fy += (float)(pd.kappa * dy);
+        A.fz += (float)(pd.kappa * dz);
+        if (rec) {
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            e_x += 0.5 * pd.kappa * d2;
+            f_rep += pd.has_dir ? pd.kappa * (dx * pd.vhat[0] + dy * pd.vhat[1] + dz * pd.vhat[2])
+                                : pd.kappa * sqrt(d2);
+        }
+    }
+    if (tip.on) {
+        const float dx = (float)(px - (tip.c0[0] + tip.v[0] * tn));
+        const float dy = (float)(py - (tip.c0[1] + tip.v[1] * tn));
+        const float dz = (float)(pz - (tip.c0[2] + tip.v[2] * tn));
+        const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float gap = rr - (float)tip.radius;
+        if (!(gap > 0.0f)) {
+            atomicOr(err, ERR_TIP);
+            return;
+        }
+        const float sg = (float)tip.sigma / gap;
+        const float s3 = sg * sg * sg;
+        const float q = s3 * s3;
+        const float mag = 6.0f * (float)tip.eps * q / gap;
+        const float cx = mag * dx / rr, cy = mag * dy / rr, cz = mag * dz / rr;
+        A.fx += cx;
+        A.fy += cy;
+        A.fz += cz;
+        if (rec) {
+            e_x += tip.eps * (double)q;
+            if (tip.has_dir)
+                f_rep += (double)cx * tip.vhat[0] + (double)cy * tip.vhat[1] + (double)cz * tip.vhat[2];
+        }
+    }
+}
+
+// Noise (Section III.C) and the first-order update (Eq. 2 / Algorithm 7)
+// with compensated positions: (hi, lo) <- TwoSum(hi, delta + lo) per axis.
+__device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Acc &A, long long step,
+                                                unsigned stream, const StepConsts &c, unsigned *err)
+{
+    const unsigned tag = __float_as_uint(hi.w);
+    if (tag >> 31)
+        return;  // fixed residue
+    const uint4 w = philox10(make_uint4(tag & 0x7fffffffu, stream, (unsigned)step,
+                                        (unsigned)((unsigned long long)step >> 32)),
+                             c.key0, c.key1);
+    float nh[3], nl[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const float f = ax == 0 ? A.fx : (ax == 1 ? A.fy : A.fz);
+        const float h0 = comp(hi, ax), l0 = comp(lo, ax);
+        const float delta = c.c_drift * f + c.c_noise * gaussian_axis(w, ax);
+        const float y = delta + l0;
+        const float t = h0 + y;
+        const float bp = t - h0;
+        const float ap = t - bp;
+        nl[ax] = (h0 - ap) + (y - bp);
+        nh[ax] = t;
+    }
+    if (!isfinite(nh[0]) || !isfinite(nh[1]) || !isfinite(nh[2]) || !isfinite(nl[0]) ||
+        !isfinite(nl[1]) || !isfinite(nl[2]))
+        atomicOr(err, ERR_NONFINITE);
+    hi = make_float4(nh[0], nh[1], nh[2], hi.w);
+    lo = make_float4(nl[0], nl[1], nl[2], lo.w);
+}
+
+// ---------------------------------------------------------------------------
+// Plain schedule, tile staging: at each rebuild, the residues a tile of
+// consecutive residues interacts with (list partners, bonded and native
+// partners, itself) become a sorted set of at most stage_max slots, and
+// rows are rewritten as 16-bit slots into that set.
+// ---------------------------------------------------------------------------
+template <int TILE>
+constexpr int stage_max() { return TILE >= 256 ? 2048 : 1024; }
+
+// Entry k of lane t of a tile: rows are stored in chunks of 8 slots per lane
+// so that one 16-byte load brings the next 8 partners of a residue.
+template <int TILE>
+__device__ __forceinline__ size_t list16_index(int tile, int t, int k, int cap)
+{
+    return (size_t)tile * cap * TILE + (size_t)(k >> 3) * (8 * TILE) + (size_t)t * 8 + (k & 7);
+}
+
+constexpr int CAND_MAX = 2816;  // candidate residues a tile stages in LDS during a rebuild
+constexpr int CELLS_MAX = 640;  // distinct cells around one tile
+constexpr int CHASH_BITS = 10;
+constexpr int CHASH = 1 << CHASH_BITS;  // open-addressing table of those cells
+constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
+
+struct BuildArgs {
+    const float4 *pos;
+    const int *cell_of;
     const int *count;
     const float4 *cells;
+    const int4 *traj_cell;
     const int *traj_lo;
     const int *traj_hi;
     const int2 *trow;
     const float2 *tent;
-    int *list;
     int *list_cnt;
+    unsigned short *list16;
+    uint2 *topo2;
+    int *stage;
+    int *stage_cnt;
     unsigned *err;
     GridDev g;
-    float rc2;
-    int cap;
+    float rc2, edge, cull2;
+    int n, cap;
 };
 
-// Rows of every residue of one cell.  Candidates are the residues of the 27
-// surrounding cells, visited in a fixed cell order with each cell's residues
-// ranked by id in LDS; a wave appends the passing candidates of one residue
-// in that order (ballot + prefix count), so rows are deterministic.
-template <int LANES>
-__global__ __launch_bounds__(WG) void k_fill(FillArgs a)
+// One workgroup per tile.  (1) The cells around the tile's residues (their
+// 27-cell neighbourhoods) go into an LDS table; their residues are copied to
+// LDS and ranked by id within each cell.  (2) Each lane builds its residue's
+// row over its 27 cells in a fixed order (cells whose box lies beyond the
+// cutoff are skipped), members in id order: the Algorithm 3 filter r < r_list
+// without bonded or native partners.  (3) The candidates that some row or
+// bond/native entry uses become the tile's staging slots, and rows are
+// rewritten as slots.
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_tile_build(BuildArgs a)
 {
-    constexpr int G = 64 / LANES;
-    __shared__ float4 own[CELL_CAP];
-    __shared__ int own_cnt[CELL_CAP];
-    __shared__ float4 raw[CHUNK];
-    __shared__ float4 cand[CHUNK];
-    __shared__ int seg_cell[27];
-    __shared__ int seg_n[27];
-    __shared__ int seg_off[28];
+    constexpr int SM = stage_max<TILE>();
+    __shared__ float4 cand[CAND_MAX];            // arrival order within each cell
+    __shared__ unsigned short order[CAND_MAX];   // rank in cell -> arrival index
+    __shared__ unsigned short used[CAND_MAX];    // 0/1, then the slot number
+    __shared__ int hkey[CHASH];
+    __shared__ short hval[CHASH];
+    __shared__ int ccell[CELLS_MAX];
+    __shared__ int cbase[CELLS_MAX + 1];
+    __shared__ int part[TILE];
+    __shared__ int extra[EXTRA_MAX];
+    __shared__ int n_cu, n_extra, bad;
 
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const int i = tile * TILE + t;
+    const bool act = i < a.n;
     const GridDev g = a.g;
-    const int n_occ = *a.n_occupied;
-    for (int oc = blockIdx.x; oc < n_occ; oc += gridDim.x) {
-    const int c = a.occupied[oc];
-    const int m = min(a.count[c], CELL_CAP);
-    if (t < 27) {
-        const int cx = c % g.gx, cy = (c / g.gx) % g.gy, cz = c / (g.gx * g.gy);
-        const int xx = (cx + (t % 3) - 1 + g.gx) % g.gx;
-        const int yy = (cy + (t / 3) % 3 - 1 + g.gy) % g.gy;
-        const int zz = (cz + t / 9 - 1 + g.gz) % g.gz;
-        const int nc = xx + g.gx * (yy + g.gy * zz);
-        seg_cell[t] = nc;
-        seg_n[t] = min(a.count[nc], CELL_CAP);
-    }
-    if (t < m)
-        raw[t] = a.cells[(size_t)c * CELL_CAP + t];
-    __syncthreads();
-    if (t < m) {
-        const int id = __float_as_int(raw[t].w);
-        int rank = 0;
-        for (int k = 0; k < m; ++k)
-            rank += __float_as_int(raw[k].w) < id;
-        own[rank] = raw[t];
-        own_cnt[rank] = 0;
-    }
+    for (int h = t; h < CHASH; h += TILE)
+        hkey[h] = -1;
     if (t == 0) {
-        int o = 0;
-        for (int k = 0; k < 27; ++k) {
-            seg_off[k] = o;
-            o += seg_n[k];
-        }
-        seg_off[27] = o;
+        n_cu = 0;
+        n_extra = 0;
+        bad = 0;
     }
     __syncthreads();
 
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int s0 = 0;
-    while (s0 < 27) {
-        int s1 = s0 + 1;
-        while (s1 < 27 && seg_off[s1 + 1] - seg_off[s0] <= CHUNK)
-            ++s1;
-        const int base = seg_off[s0];
-        const int tot = seg_off[s1] - base;
-        for (int q = t; q < tot; q += WG) {
-            int sg = s0;
-            while (seg_off[sg + 1] - base <= q)
-                ++sg;
-            raw[q] = a.cells[(size_t)seg_cell[sg] * CELL_CAP + (q - (seg_off[sg] - base))];
+    auto wrap = [](int v, int n) { const int r = v % n; return r < 0 ? r + n : r; };
+    auto hslot = [](int key) { return (int)(((unsigned)key * 2654435761u) >> (32 - CHASH_BITS)) & (CHASH - 1); };
+    auto lookup = [&](int key) -> int {
+        int h = hslot(key);
+        for (int probe = 0; probe < CHASH; ++probe) {
+            const int k = hkey[h];
+            if (k == key)
+                return hval[h];
+            if (k < 0)
+                return -1;
+            h = (h + 1) & (CHASH - 1);
         }
-        __syncthreads();
-        for (int q = t; q < tot; q += WG) {
-            int sg = s0;
-            while (seg_off[sg + 1] - base <= q)
-                ++sg;
-            const int so = seg_off[sg] - base, sn = seg_n[sg];
-            const int id = __float_as_int(raw[q].w);
-            int rank = 0;
-            for (int k = 0; k < sn; ++k)
-                rank += __float_as_int(raw[so + k].w) < id;
-            cand[so + rank] = raw[q];
-        }
-        __syncthreads();
-        for (int mi = wave; mi < m; mi += WG / 64) {
-            const float4 p = own[mi];
-            const int i = __builtin_amdgcn_readfirstlane(__float_as_int(p.w));
-            const int tlo = a.traj_lo[i], thi = a.traj_hi[i];
-            const int2 row = a.trow[i];
-            const int nex = (row.y & 4095) + (row.y >> 12);
-            // bonded and native partners of i, one per lane (the first 64)
-            const int pv = lane < nex ? __float_as_int(a.tent[row.x + lane].x) : -1;
-            int *rowp = a.list + (size_t)(i / G) * a.cap * G + (i % G) * LANES;
-            int cnt = own_cnt[mi];
-            for (int q0 = 0; q0 < tot; q0 += 64) {
-                const int q = q0 + lane;
-                bool ok = false;
-                int j = -1;
-                if (q < tot) {
-                    const float4 cq = cand[q];
-                    j = __float_as_int(cq.w);
-                    ok = j != i && j >= tlo && j < thi && within_cutoff(p, cq, a.rc2);
+        return -1;
+    };
+
+    // own residue: position, unwrapped cell coordinates, neighbourhood
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    int ux = 0, uy = 0, uz = 0;
+    if (act) {
+        p = a.pos[2 * i];
+        const int4 off = a.traj_cell[__float_as_int(a.pos[2 * i + 1].w)];
+        auto ucell = [&](float x, int o) {
+            float v = floorf(x * g.inv_cell);
+            if (!(v == v))
+                v = 0.0f;
+            return (int)fminf(fmaxf(v, -1.0e9f), 1.0e9f) + o;
+        };
+        ux = ucell(p.x, off.x);
+        uy = ucell(p.y, off.y);
+        uz = ucell(p.z, off.z);
+        for (int d = 0; d < 27; ++d) {
+            const int cid = wrap(ux + d % 3 - 1, g.gx) +
+                            g.gx * (wrap(uy + (d / 3) % 3 - 1, g.gy) + g.gy * wrap(uz + d / 9 - 1, g.gz));
+            int h = hslot(cid);
+            for (int probe = 0; probe < CHASH; ++probe) {
+                const int prev = atomicCAS(&hkey[h], -1, cid);
+                if (prev == -1) {
+                    const int m = atomicAdd(&n_cu, 1);
+                    if (m < CELLS_MAX) {
+                        ccell[m] = cid;
+                        hval[h] = (short)m;
+                    } else {
+                        bad = 1;
+                    }
+                    break;
                 }
-                if (__ballot(ok)) {
-                    const int ne = min(nex, 64);
-                    for (int e = 0; e < ne; ++e)
-                        ok = ok && (j != __builtin_amdgcn_readlane(pv, e));
-                    for (int e = 64; e < nex; ++e)
-                        ok = ok && (__float_as_int(a.tent[row.x + e].x) != j);
-                }
-                const unsigned long long mask = __ballot(ok);
-                if (ok) {
-                    const int at = cnt + __popcll(mask & below);
-                    if (at < a.cap)
-                        rowp[(at / LANES) * 64 + (at % LANES)] = j;
-                }
-                cnt += __popcll(mask);
+                if (prev == cid)
+                    break;
+                h = (h + 1) & (CHASH - 1);
+                if (probe == CHASH - 1)
+                    bad = 1;
             }
-            if (lane == 0)
-                own_cnt[mi] = cnt;
         }
+    }
+    __syncthreads();
+    const int NC = n_cu;
+    if (bad == 0 && NC <= CELLS_MAX) {
+        for (int m = t; m < NC; m += TILE)
+            cbase[m + 1] = min(a.count[ccell[m]], CELL_CAP);
         __syncthreads();
-        s0 = s1;
+        if (t == 0) {
+            cbase[0] = 0;
+            for (int m = 0; m < NC; ++m)
+                cbase[m + 1] += cbase[m];
+            if (cbase[NC] > CAND_MAX)
+                bad = 1;
+        }
     }
-    for (int mi = t; mi < m; mi += WG) {
-        const int i = __float_as_int(own[mi].w);
-        a.list_cnt[i] = own_cnt[mi];
-        if (own_cnt[mi] > a.cap)
+    __syncthreads();
+    const int2 row = act ? a.trow[i] : make_int2(0, 0);
+    const int ntop = (row.y & 4095) + (row.y >> 12);
+    if (bad || NC > CELLS_MAX) {
+        // report, leave the tile's slots at the empty slot so steps stay in bounds
+        if (t == 0) {
+            atomicOr(a.err, ERR_STAGE);
+            a.stage_cnt[tile] = 0;
+        }
+        if (act) {
+            a.list_cnt[i] = 0;
+            uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
+            for (int e = 0; e < ntop; ++e)
+                trw[(size_t)e * TILE] = make_uint2((unsigned)SM, __float_as_uint(1.0f));
+        }
+        return;  // uniform: bad and NC are read after a barrier
+    }
+    const int M = cbase[NC];
+    auto segment_of = [&](int ci) {  // last m with cbase[m] <= ci
+        int lo = 0, hi = NC;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cbase[mid] <= ci)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        return lo;
+    };
+    for (int ci = t; ci < M; ci += TILE) {
+        const int m = segment_of(ci);
+        cand[ci] = a.cells[(size_t)ccell[m] * CELL_CAP + (ci - cbase[m])];
+        used[ci] = 0;
+    }
+    __syncthreads();
+    for (int ci = t; ci < M; ci += TILE) {
+        const int m = segment_of(ci);
+        const int id = __float_as_int(cand[ci].w);
+        int rank = 0;
+        for (int k = cbase[m]; k < cbase[m + 1]; ++k)
+            rank += __float_as_int(cand[k].w) < id;
+        order[cbase[m] + rank] = (unsigned short)ci;
+    }
+    __syncthreads();
+
+    // rows, one lane per residue, with arrival indices for now
+    int cnt = 0;
+    if (act) {
+        const int tlo = a.traj_lo[i], thi = a.traj_hi[i];
+        int ex[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            ex[u] = u < ntop ? __float_as_int(a.tent[row.x + u].x) : -2;
+        const float lx = floorf(p.x * g.inv_cell) * a.edge;
+        const float ly = floorf(p.y * g.inv_cell) * a.edge;
+        const float lz = floorf(p.z * g.inv_cell) * a.edge;
+        const float gx[3] = {p.x - lx, 0.0f, lx + a.edge - p.x};
+        const float gy[3] = {p.y - ly, 0.0f, ly + a.edge - p.y};
+        const float gz[3] = {p.z - lz, 0.0f, lz + a.edge - p.z};
+        for (int d = 0; d < 27; ++d) {
+            const int dx = d % 3, dy = (d / 3) % 3, dz = d / 9;
+            // smallest distance from p to that cell's box
+            if (gx[dx] * gx[dx] + gy[dy] * gy[dy] + gz[dz] * gz[dz] > a.cull2)
+                continue;
+            const int cid = wrap(ux + dx - 1, g.gx) + g.gx * (wrap(uy + dy - 1, g.gy) + g.gy * wrap(uz + dz - 1, g.gz));
+            const int m = lookup(cid);
+            for (int r = cbase[m]; r < cbase[m + 1]; ++r) {
+                const int ci = order[r];
+                const float4 q = cand[ci];
+                const int j = __float_as_int(q.w);
+                if (j == i || j < tlo || j >= thi || !within_cutoff(p, q, a.rc2))
+                    continue;
+                bool excl = false;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    excl |= ex[u] == j;
+                for (int e = 16; e < ntop; ++e)
+                    excl |= __float_as_int(a.tent[row.x + e].x) == j;
+                if (excl)
+                    continue;
+                if (cnt < a.cap)
+                    a.list16[list16_index<TILE>(tile, t, cnt, a.cap)] = (unsigned short)ci;
+                used[ci] = 1;
+                ++cnt;
+            }
+        }
+        a.list_cnt[i] = cnt;
+        if (cnt > a.cap)
             atomicOr(a.err, ERR_OVERFLOW);
+        // bonded and native partners: their candidate, or an extra slot
+        uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
+        for (int e = 0; e < ntop; ++e) {
+            const float2 te = a.tent[row.x + e];
+            const int j = __float_as_int(te.x);
+            const int m = lookup(a.cell_of[j]);
+            int ci = -1;
+            if (m >= 0) {
+                int lo = cbase[m], hi = cbase[m + 1];  // binary search by id in the cell
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int idm = __float_as_int(cand[order[mid]].w);
+                    if (idm < j)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo < cbase[m + 1] && __float_as_int(cand[order[lo]].w) == j)
+                    ci = order[lo];
+            }
+            unsigned code;
+            if (ci >= 0) {
+                used[ci] = 1;
+                code = (unsigned)ci;
+            } else {
+                const int k = atomicAdd(&n_extra, 1);
+                if (k < EXTRA_MAX)
+                    extra[k] = j;
+                code = 0x80000000u | (unsigned)k;
+            }
+            trw[(size_t)e * TILE] = make_uint2(code, __float_as_uint(te.y));
+        }
     }
-    __syncthreads();  // LDS is reused by the next cell
+    __syncthreads();
+    // used candidates -> slots (exclusive prefix over arrival order)
+    const int per = (M + TILE - 1) / TILE;
+    const int c0 = min(M, t * per), c1 = min(M, c0 + per);
+    int u = 0;
+    for (int ci = c0; ci < c1; ++ci)
+        u += used[ci];
+    part[t] = u;
+    __syncthreads();
+    for (int off = 1; off < TILE; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const int n_used = part[TILE - 1];
+    const int S = n_used + min(n_extra, EXTRA_MAX);
+    if (S > SM || n_extra > EXTRA_MAX) {
+        if (t == 0) {
+            atomicOr(a.err, ERR_STAGE);
+            a.stage_cnt[tile] = 0;
+        }
+        if (act) {
+            a.list_cnt[i] = 0;
+            uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
+            for (int e = 0; e < ntop; ++e)
+                trw[(size_t)e * TILE] = make_uint2((unsigned)SM, __float_as_uint(1.0f));
+        }
+        return;  // uniform
+    }
+    int sl = part[t] - u;
+    int *st = a.stage + (size_t)tile * SM;
+    for (int ci = c0; ci < c1; ++ci) {
+        if (used[ci]) {
+            st[sl] = __float_as_int(cand[ci].w);
+            used[ci] = (unsigned short)sl;
+            ++sl;
+        }
+    }
+    for (int k = t; k < min(n_extra, EXTRA_MAX); k += TILE)
+        st[n_used + k] = extra[k];
+    if (t == 0)
+        a.stage_cnt[tile] = S;
+    __syncthreads();
+    if (act) {
+        // rows padded to a multiple of 8 with the empty slot SM (a position
+        // far away, so its pair term is exactly zero)
+        const int m = min(cnt, a.cap);
+        for (int k = 0; k < ((m + 7) & ~7); ++k) {
+            const size_t x = list16_index<TILE>(tile, t, k, a.cap);
+            a.list16[x] = k < m ? used[a.list16[x]] : (unsigned short)SM;
+        }
+        uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
+        for (int e = 0; e < ntop; ++e) {
+            const uint2 v = trw[(size_t)e * TILE];
+            const unsigned sl2 = (v.x & 0x80000000u) ? (unsigned)n_used + (v.x & 0x7fffffffu) : used[v.x];
+            trw[(size_t)e * TILE] = make_uint2(sl2, v.y);
+        }
     }
 }
 
-// ---------------------------------------------------------------------------
-// Fused step: forces -> (noise -> compensated update) | force output
-// ---------------------------------------------------------------------------
-struct StepArgs {
+struct TileArgs {
     const float4 *pin;
     float4 *pout;
     const int2 *trow;
     const float2 *tent;
-    const int *list;
+    const unsigned short *list16;
+    const uint2 *topo2;
     const int *list_cnt;
+    const int *stage;
+    const int *stage_cnt;
     const unsigned *stream_ids;
     const int *pull_slot;
     const PullDev *pulls;
@@ -301,199 +664,134 @@ struct StepArgs {
     unsigned *err;
     const long long *step_base;
     long long step_off;
-    int n, cap, has_pull, n_waves;
+    int n, cap, has_pull, n_tiles;
     StepConsts c;
     TipDev tip;
 };
 
-// Per-residue force and, on energy steps, double energy/virial sums.
-struct Acc {
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    double e_b = 0.0, e_n = 0.0, e_r = 0.0, vir = 0.0;
-};
-
-// eps_l (sigma/r)^6 between residue (hi, lo) and a listed partner.
-__device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const float4 &lo,
-                                              const float4 &hj, const float4 &lj, float sg2,
-                                              float el, float el6, bool ENERGY)
+// One workgroup per tile, one lane per residue: stage the tile's slots in
+// LDS, then every pair term reads LDS.
+// Few waves per SIMD (about one residue per lane across the GPU), so the
+// compiler may trade registers for loads in flight.
+template <int TILE, bool ENERGY, int MODE>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tile_step(TileArgs a)
 {
-    const float3 d = pair_delta(hi, lo, hj, lj);
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const float ir2 = fast_rcp(r2);
-    const float s = sg2 * ir2;
-    const float q = s * s * s;
-    const float coef = el6 * q * ir2;
-    A.fx += coef * d.x;
-    A.fy += coef * d.y;
-    A.fz += coef * d.z;
-    if (ENERGY) {
-        A.e_r += (double)(el * q);
-        A.vir += (double)(el6 * q);
-    }
-}
-
-template <int LANES, bool ENERGY, int MODE>
-__global__ __launch_bounds__(WG) void k_step(StepArgs a)
-{
-    constexpr int G = 64 / LANES;
-    const int lane = threadIdx.x & 63;
-    // XCD-aware order: consecutive residue blocks stay on one XCD's L2.
+    constexpr int SM = stage_max<TILE>();
+    __shared__ float4 sh[2 * (SM + 1)];  // slot SM: the far-away empty slot
+    // XCD-aware order: consecutive tiles stay on one XCD's L2.
     const int per = gridDim.x >> 3;
-    const int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int wave = blk * (WG / 64) + (threadIdx.x >> 6);
-    if (wave >= a.n_waves)
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= a.n_tiles)
         return;
-    const int g = lane / LANES, l = lane % LANES;
-    const int r = wave * G + g;
-    if (r >= a.n)
+    const int t = threadIdx.x;
+    const int i = tile * TILE + t;
+    const bool act = i < a.n;
+    const int S = a.stage_cnt[tile];
+    const int *st = a.stage + (size_t)tile * SM;
+    // independent loads of this residue's data first
+    float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
+    int2 row = make_int2(0, 0);
+    int cnt = 0;
+    const uint4 *lp4 = reinterpret_cast<const uint4 *>(a.list16) + (size_t)tile * (a.cap >> 3) * TILE + t;
+    const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
+    uint4 cur = make_uint4(0u, 0u, 0u, 0u);
+    if (act) {
+        hi0 = a.pin[2 * i];
+        lo0 = a.pin[2 * i + 1];
+        row = a.trow[i];
+        cnt = min(a.list_cnt[i], a.cap);
+        cur = lp4[0];
+    }
+    {
+        // all slot ids first, then all positions, so the loads overlap
+        constexpr int PER = SM / TILE;
+        int ids[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int s = t + u * TILE;
+            ids[u] = s < S ? st[s] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (ids[u] >= 0) {
+                const int s = t + u * TILE;
+                sh[2 * s] = a.pin[2 * ids[u]];
+                sh[2 * s + 1] = a.pin[2 * ids[u] + 1];
+            }
+        }
+        if (t == 0) {
+            sh[2 * SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+            sh[2 * SM + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
+    __syncthreads();
+    if (!act)
         return;
-
-    const float4 hi = a.pin[2 * r];
-    const float4 lo = a.pin[2 * r + 1];
+    const PairConsts k = pair_consts(a.c);
+    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     Acc A;
     bool broken = false;
-
-    const int2 row = a.trow[r];
-    const int nb = row.y & 4095, nn = row.y >> 12;
-    const float kf = a.c.k_fene, inv_R0sq = a.c.inv_R0sq;
-    // FENE bonds
-    for (int p = l; p < nb; p += LANES) {
-        const float2 t = a.tent[row.x + p];
-        const int j = __float_as_int(t.x);
-        const float3 d = pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]);
-        const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-        const float rr = __builtin_amdgcn_sqrtf(r2);
-        const float dl = rr - t.y;
-        float x = 1.0f - dl * dl * inv_R0sq;
-        if (!(x > 0.0f)) {
-            broken = true;
-            x = 1.0f;
-        }
-        const float coef = -kf * dl * fast_rcp(x * rr);
-        A.fx += coef * d.x;
-        A.fy += coef * d.y;
-        A.fz += coef * d.z;
-        if (ENERGY) {
-            const double dd = (double)dl;
-            const double R0sq = (double)a.c.R0sq;
-            A.e_b += -0.5 * (double)kf * R0sq * log1p(-dd * dd / R0sq);
-            A.vir += -(double)rr * (double)kf * dd / (1.0 - dd * dd / R0sq);
+    const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
+    // bonds and natives, four entries per block
+    for (int e0 = 0; e0 < ntop; e0 += 4) {
+        uint2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            v[u] = e0 + u < ntop ? tp[(size_t)(e0 + u) * TILE] : make_uint2((unsigned)SM, __float_as_uint(1.0f));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u, sj = (int)v[u].x;
+            const float r0 = __uint_as_float(v[u].y);
+            if (e < nb)
+                add_fene(A, hi0, lo0, sh[2 * sj], sh[2 * sj + 1], r0, k, ENERGY, broken);
+            else if (e < ntop)
+                add_native(A, hi0, lo0, sh[2 * sj], sh[2 * sj + 1], r0, k, ENERGY);
         }
     }
-    // native contacts
-    const float eh = a.c.eps_h, eh12 = 12.0f * eh;
-    for (int p = nb + l; p < nb + nn; p += LANES) {
-        const float2 t = a.tent[row.x + p];
-        const int j = __float_as_int(t.x);
-        const float3 d = pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]);
-        const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-        const float ir2 = fast_rcp(r2);
-        const float s = t.y * t.y * ir2;
-        const float q = s * s * s;
-        const float coef = eh12 * (q * q - q) * ir2;
-        A.fx += coef * d.x;
-        A.fy += coef * d.y;
-        A.fz += coef * d.z;
-        if (ENERGY) {
-            A.e_n += (double)(eh * (q * q - 2.0f * q));
-            A.vir += (double)(eh12 * (q * q - q));
+    // list partners: chunks of 8 slots with four chunks in flight
+    const int nch = (cnt + 7) >> 3;
+    auto chunk8 = [&](const uint4 &q) {
+        const unsigned w[4] = {q.x, q.y, q.z, q.w};
+        float4 ph[8], pl[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {  // all 16 LDS reads before any use
+            const int sj = (int)((w[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+            ph[u] = sh[2 * sj];
+            pl[u] = sh[2 * sj + 1];
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            add_repulsive(A, hi0, lo0, ph[u], pl[u], k, ENERGY);
+    };
+    // unconditional loads (a branch around them would force a full wait);
+    // chunks past the row are clamped into the row's region and never used
+    const int last_ch = (a.cap >> 3) - 1;
+    auto fetch = [&](int ch) -> uint4 { return lp4[(size_t)min(ch, last_ch) * TILE]; };
+    uint4 q0 = cur, q1 = fetch(1), q2 = fetch(2), q3 = fetch(3);
+    int ch = 0;
+    for (; ch + 4 <= nch; ch += 4) {  // whole groups: no branches between the loads
+        chunk8(q0);
+        q0 = fetch(ch + 4);
+        chunk8(q1);
+        q1 = fetch(ch + 5);
+        chunk8(q2);
+        q2 = fetch(ch + 6);
+        chunk8(q3);
+        q3 = fetch(ch + 7);
     }
-    // repulsive list, four partners per iteration to keep gathers in flight
-    const float el = a.c.eps_l, el6 = 6.0f * el, sg2 = a.c.sigma2;
-    const int cnt = min(a.list_cnt[r], a.cap);
-    const int nk = cnt > l ? (cnt - l + LANES - 1) / LANES : 0;
-    const int *lp = a.list + (size_t)wave * a.cap * G + g * LANES + l;
-    int k = 0;
-    for (; k + 4 <= nk; k += 4) {
-        const int j0 = lp[(k + 0) * 64], j1 = lp[(k + 1) * 64];
-        const int j2 = lp[(k + 2) * 64], j3 = lp[(k + 3) * 64];
-        const float4 h0 = a.pin[2 * j0], l0 = a.pin[2 * j0 + 1];
-        const float4 h1 = a.pin[2 * j1], l1 = a.pin[2 * j1 + 1];
-        const float4 h2 = a.pin[2 * j2], l2 = a.pin[2 * j2 + 1];
-        const float4 h3 = a.pin[2 * j3], l3 = a.pin[2 * j3 + 1];
-        add_repulsive(A, hi, lo, h0, l0, sg2, el, el6, ENERGY);
-        add_repulsive(A, hi, lo, h1, l1, sg2, el, el6, ENERGY);
-        add_repulsive(A, hi, lo, h2, l2, sg2, el, el6, ENERGY);
-        add_repulsive(A, hi, lo, h3, l3, sg2, el, el6, ENERGY);
-    }
-    for (; k < nk; ++k) {
-        const int j = lp[k * 64];
-        add_repulsive(A, hi, lo, a.pin[2 * j], a.pin[2 * j + 1], sg2, el, el6, ENERGY);
-    }
-
-    // external terms (one lane per residue), positions in double
+    if (ch < nch)
+        chunk8(q0);
+    if (ch + 1 < nch)
+        chunk8(q1);
+    if (ch + 2 < nch)
+        chunk8(q2);
     double e_x = 0.0, f_rep = 0.0;
-    if (l == 0 && (a.has_pull || a.tip.on)) {
-        const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
-        const double tn = (double)step * a.c.h;
-        const double px = (double)hi.x + (double)lo.x;
-        const double py = (double)hi.y + (double)lo.y;
-        const double pz = (double)hi.z + (double)lo.z;
-        if (a.has_pull) {
-            const int sl = a.pull_slot[r];
-            if (sl >= 0) {
-                const PullDev pd = a.pulls[sl];
-                const double dx = pd.anchor0[0] + pd.v[0] * tn - px;
-                const double dy = pd.anchor0[1] + pd.v[1] * tn - py;
-                const double dz = pd.anchor0[2] + pd.v[2] * tn - pz;
-                A.fx += (float)(pd.kappa * dx);
-                A.fy += (float)(pd.kappa * dy);
-                A.fz += (float)(pd.kappa * dz);
-                if (ENERGY) {
-                    const double d2 = dx * dx + dy * dy + dz * dz;
-                    e_x += 0.5 * pd.kappa * d2;
-                    f_rep += pd.has_dir ? pd.kappa * (dx * pd.vhat[0] + dy * pd.vhat[1] + dz * pd.vhat[2])
-                                        : pd.kappa * sqrt(d2);
-                }
-            }
-        }
-        if (a.tip.on) {
-            const TipDev &tp = a.tip;
-            const float dx = (float)(px - (tp.c0[0] + tp.v[0] * tn));
-            const float dy = (float)(py - (tp.c0[1] + tp.v[1] * tn));
-            const float dz = (float)(pz - (tp.c0[2] + tp.v[2] * tn));
-            const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
-            const float gap = rr - (float)tp.radius;
-            if (!(gap > 0.0f)) {
-                atomicOr(a.err, ERR_TIP);
-            } else {
-                const float sg = (float)tp.sigma / gap;
-                const float s3 = sg * sg * sg;
-                const float q = s3 * s3;
-                const float mag = 6.0f * (float)tp.eps * q / gap;
-                const float cx = mag * dx / rr, cy = mag * dy / rr, cz = mag * dz / rr;
-                A.fx += cx;
-                A.fy += cy;
-                A.fz += cz;
-                if (ENERGY) {
-                    e_x += tp.eps * (double)q;
-                    if (tp.has_dir)
-                        f_rep += (double)cx * tp.vhat[0] + (double)cy * tp.vhat[1] +
-                                 (double)cz * tp.vhat[2];
-                }
-            }
-        }
-    }
+    add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
+                 a.tip, ENERGY, a.err);
     if (broken)
         atomicOr(a.err, ERR_FENE);
-
-    // combine the LANES partial sums of one residue (butterfly)
-    float fx = A.fx, fy = A.fy, fz = A.fz;
-#pragma unroll
-    for (int m = LANES / 2; m >= 1; m >>= 1) {
-        fx += __shfl_xor(fx, m, 64);
-        fy += __shfl_xor(fy, m, 64);
-        fz += __shfl_xor(fz, m, 64);
-        if (ENERGY) {
-            A.e_b += __shfl_xor(A.e_b, m, 64);
-            A.e_n += __shfl_xor(A.e_n, m, 64);
-            A.e_r += __shfl_xor(A.e_r, m, 64);
-            A.vir += __shfl_xor(A.vir, m, 64);
-        }
-    }
-    if (ENERGY && l == 0) {
-        double *er = a.res_energy + (size_t)r * RES_E;
+    if (ENERGY) {
+        double *er = a.res_energy + (size_t)i * RES_E;
         // each internal pair appears in both partners' rows
         er[0] = 0.5 * A.e_b;
         er[1] = 0.5 * A.e_n;
@@ -503,40 +801,13 @@ __global__ __launch_bounds__(WG) void k_step(StepArgs a)
         er[5] = f_rep;
     }
     if (MODE == 1) {
-        if (l == 0)
-            a.fout[r] = make_float4(fx, fy, fz, 0.0f);
+        a.fout[i] = make_float4(A.fx, A.fy, A.fz, 0.0f);
         return;
     }
-
-    // noise and compensated update; lane l handles axes l, l+LANES, ...
-    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
-    const unsigned tag = __float_as_uint(hi.w);
-    const bool fixed = (tag >> 31) != 0;
-    const unsigned local = tag & 0x7fffffffu;
-    const unsigned stream = a.stream_ids[__float_as_int(lo.w)];
-    const uint4 w = philox10(make_uint4(local, stream, (unsigned)step, (unsigned)((unsigned long long)step >> 32)),
-                             a.c.key0, a.c.key1);
-    float *ho = reinterpret_cast<float *>(a.pout + 2 * r);
-    float *lw = reinterpret_cast<float *>(a.pout + 2 * r + 1);
-    for (int ax = l; ax < 3; ax += LANES) {
-        const float f = ax == 0 ? fx : (ax == 1 ? fy : fz);
-        const float h0 = comp(hi, ax), l0 = comp(lo, ax);
-        float nh = h0, nl = l0;
-        if (!fixed) {
-            const float delta = a.c.c_drift * f + a.c.c_noise * gaussian_axis(w, ax);
-            // TwoSum(h0, delta + l0): exact error term kept in the low word
-            const float y = delta + l0;
-            const float t = h0 + y;
-            const float bp = t - h0;
-            const float ap = t - bp;
-            nl = (h0 - ap) + (y - bp);
-            nh = t;
-        }
-        if (!isfinite(nh) || !isfinite(nl))
-            atomicOr(a.err, ERR_NONFINITE);
-        ho[ax] = nh;
-        lw[ax] = nl;
-    }
+    float4 hi = hi0, lo = lo0;
+    langevin_update(hi, lo, A, step, a.stream_ids[__float_as_int(lo0.w)], a.c, a.err);
+    a.pout[2 * i] = hi;
+    a.pout[2 * i + 1] = lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -614,12 +885,7 @@ __global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
     const int nb = row.y & 4095, nn = row.y >> 12;
     unsigned short *lrow = a.list + (size_t)base * a.cap + t;
     const long long s0 = (a.step_base ? *a.step_base : 0) + a.step_off;
-    const float kf = a.c.k_fene, inv_R0sq = a.c.inv_R0sq;
-    const float eh = a.c.eps_h, eh12 = 12.0f * eh;
-    const float el = a.c.eps_l, el6 = 6.0f * el, sg2 = a.c.sigma2;
-    const unsigned tag = __float_as_uint(hi.w);
-    const bool fixed = (tag >> 31) != 0;
-    const unsigned local = tag & 0x7fffffffu;
+    const PairConsts kc = pair_consts(a.c);
     const int traj = __float_as_int(lo.w);
     const unsigned stream = act ? a.stream_ids[traj] : 0u;
 
@@ -653,107 +919,29 @@ __global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
             for (int e = 0; e < nb; ++e) {
                 const float2 tt = a.tent[row.x + e];
                 const int j = __float_as_int(tt.x) - base;
-                const float3 d = pair_delta(hi, lo, sh[2 * j], sh[2 * j + 1]);
-                const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-                const float rr = __builtin_amdgcn_sqrtf(r2);
-                const float dl = rr - tt.y;
-                float x = 1.0f - dl * dl * inv_R0sq;
-                if (!(x > 0.0f)) {
-                    broken = true;
-                    x = 1.0f;
-                }
-                const float coef = -kf * dl * fast_rcp(x * rr);
-                A.fx += coef * d.x;
-                A.fy += coef * d.y;
-                A.fz += coef * d.z;
-                if (rec) {
-                    const double dd = (double)dl;
-                    const double R0sq = (double)a.c.R0sq;
-                    A.e_b += -0.5 * (double)kf * R0sq * log1p(-dd * dd / R0sq);
-                    A.vir += -(double)rr * (double)kf * dd / (1.0 - dd * dd / R0sq);
-                }
+                add_fene(A, hi, lo, sh[2 * j], sh[2 * j + 1], tt.y, kc, rec, broken);
             }
             for (int e = nb; e < nb + nn; ++e) {
                 const float2 tt = a.tent[row.x + e];
                 const int j = __float_as_int(tt.x) - base;
-                const float3 d = pair_delta(hi, lo, sh[2 * j], sh[2 * j + 1]);
-                const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-                const float ir2 = fast_rcp(r2);
-                const float s = tt.y * tt.y * ir2;
-                const float qq = s * s * s;
-                const float coef = eh12 * (qq * qq - qq) * ir2;
-                A.fx += coef * d.x;
-                A.fy += coef * d.y;
-                A.fz += coef * d.z;
-                if (rec) {
-                    A.e_n += (double)(eh * (qq * qq - 2.0f * qq));
-                    A.vir += (double)(eh12 * (qq * qq - qq));
-                }
+                add_native(A, hi, lo, sh[2 * j], sh[2 * j + 1], tt.y, kc, rec);
             }
             const int m = min(cnt, a.cap);
             int k = 0;
             for (; k + 4 <= m; k += 4) {
                 const int j0 = lrow[(size_t)(k + 0) * n], j1 = lrow[(size_t)(k + 1) * n];
                 const int j2 = lrow[(size_t)(k + 2) * n], j3 = lrow[(size_t)(k + 3) * n];
-                add_repulsive(A, hi, lo, sh[2 * j0], sh[2 * j0 + 1], sg2, el, el6, rec);
-                add_repulsive(A, hi, lo, sh[2 * j1], sh[2 * j1 + 1], sg2, el, el6, rec);
-                add_repulsive(A, hi, lo, sh[2 * j2], sh[2 * j2 + 1], sg2, el, el6, rec);
-                add_repulsive(A, hi, lo, sh[2 * j3], sh[2 * j3 + 1], sg2, el, el6, rec);
+                add_repulsive(A, hi, lo, sh[2 * j0], sh[2 * j0 + 1], kc, rec);
+                add_repulsive(A, hi, lo, sh[2 * j1], sh[2 * j1 + 1], kc, rec);
+                add_repulsive(A, hi, lo, sh[2 * j2], sh[2 * j2 + 1], kc, rec);
+                add_repulsive(A, hi, lo, sh[2 * j3], sh[2 * j3 + 1], kc, rec);
             }
             for (; k < m; ++k) {
                 const int j = lrow[(size_t)k * n];
-                add_repulsive(A, hi, lo, sh[2 * j], sh[2 * j + 1], sg2, el, el6, rec);
+                add_repulsive(A, hi, lo, sh[2 * j], sh[2 * j + 1], kc, rec);
             }
-            if (a.has_pull || a.tip.on) {
-                const double tn = (double)step * a.c.h;
-                const double px = (double)hi.x + (double)lo.x;
-                const double py = (double)hi.y + (double)lo.y;
-                const double pz = (double)hi.z + (double)lo.z;
-                if (a.has_pull) {
-                    const int sl = a.pull_slot[i];
-                    if (sl >= 0) {
-                        const PullDev pd = a.pulls[sl];
-                        const double dx = pd.anchor0[0] + pd.v[0] * tn - px;
-                        const double dy = pd.anchor0[1] + pd.v[1] * tn - py;
-                        const double dz = pd.anchor0[2] + pd.v[2] * tn - pz;
-                        A.fx += (float)(pd.kappa * dx);
-                        A.fy += (float)(pd.kappa * dy);
-                        A.fz += (float)(pd.kappa * dz);
-                        if (rec) {
-                            const double d2 = dx * dx + dy * dy + dz * dz;
-                            e_x += 0.5 * pd.kappa * d2;
-                            f_rep += pd.has_dir ? pd.kappa * (dx * pd.vhat[0] + dy * pd.vhat[1] + dz * pd.vhat[2])
-                                                : pd.kappa * sqrt(d2);
-                        }
-                    }
-                }
-                if (a.tip.on) {
-                    const TipDev &tp = a.tip;
-                    const float dx = (float)(px - (tp.c0[0] + tp.v[0] * tn));
-                    const float dy = (float)(py - (tp.c0[1] + tp.v[1] * tn));
-                    const float dz = (float)(pz - (tp.c0[2] + tp.v[2] * tn));
-                    const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
-                    const float gap = rr - (float)tp.radius;
-                    if (!(gap > 0.0f)) {
-                        atomicOr(a.err, ERR_TIP);
-                    } else {
-                        const float sg = (float)tp.sigma / gap;
-                        const float s3 = sg * sg * sg;
-                        const float qq = s3 * s3;
-                        const float mag = 6.0f * (float)tp.eps * qq / gap;
-                        const float cx = mag * dx / rr, cy = mag * dy / rr, cz = mag * dz / rr;
-                        A.fx += cx;
-                        A.fy += cy;
-                        A.fz += cz;
-                        if (rec) {
-                            e_x += tp.eps * (double)qq;
-                            if (tp.has_dir)
-                                f_rep += (double)cx * tp.vhat[0] + (double)cy * tp.vhat[1] +
-                                         (double)cz * tp.vhat[2];
-                        }
-                    }
-                }
-            }
+            add_external(A, e_x, f_rep, hi, lo, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
+                         a.tip, rec, a.err);
             if (broken)
                 atomicOr(a.err, ERR_FENE);
         }
@@ -777,32 +965,8 @@ __global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
             return;
         }
         float4 nh4 = hi, nl4 = lo;
-        if (act) {
-            const uint4 w = philox10(make_uint4(local, stream, (unsigned)step,
-                                                (unsigned)((unsigned long long)step >> 32)),
-                                     a.c.key0, a.c.key1);
-            float nh[3], nl[3];
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                const float f = ax == 0 ? A.fx : (ax == 1 ? A.fy : A.fz);
-                const float h0 = comp(hi, ax), l0 = comp(lo, ax);
-                nh[ax] = h0;
-                nl[ax] = l0;
-                if (!fixed) {
-                    const float delta = a.c.c_drift * f + a.c.c_noise * gaussian_axis(w, ax);
-                    const float y = delta + l0;
-                    const float tt = h0 + y;
-                    const float bp = tt - h0;
-                    const float ap = tt - bp;
-                    nl[ax] = (h0 - ap) + (y - bp);
-                    nh[ax] = tt;
-                }
-                if (!isfinite(nh[ax]) || !isfinite(nl[ax]))
-                    atomicOr(a.err, ERR_NONFINITE);
-            }
-            nh4 = make_float4(nh[0], nh[1], nh[2], hi.w);
-            nl4 = make_float4(nl[0], nl[1], nl[2], lo.w);
-        }
+        if (act)
+            langevin_update(nh4, nl4, A, step, stream, a.c, a.err);
         __syncthreads();
         if (act) {
             sh[2 * t] = nh4;
@@ -884,81 +1048,88 @@ __global__ void k_set_step(long long *dst, long long v)
 
 inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per); }
 
-template <int LANES>
-void fill_lanes(const FillArgs &f, int n_cells, hipStream_t s)
+template <int TILE>
+void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, float rc2, float edge,
+                  float cull2, hipStream_t s)
 {
-    // occupied cells are spread over a bounded grid of workgroups
-    hipLaunchKernelGGL(k_fill<LANES>, dim3(std::min(n_cells, 2048)), dim3(WG), 0, s, f);
+    BuildArgs a{};
+    a.pos = b.pos[cur];
+    a.cell_of = b.cell_of;
+    a.count = b.cell_count;
+    a.cells = b.cells;
+    a.traj_cell = b.traj_cell;
+    a.traj_lo = b.traj_lo;
+    a.traj_hi = b.traj_hi;
+    a.trow = b.trow;
+    a.tent = b.tent;
+    a.list_cnt = b.list_cnt;
+    a.list16 = b.list16;
+    a.topo2 = b.topo2;
+    a.stage = b.stage;
+    a.stage_cnt = b.stage_cnt;
+    a.err = b.err;
+    a.g = g;
+    a.rc2 = rc2;
+    a.edge = edge;
+    a.cull2 = cull2;
+    a.n = n;
+    a.cap = cap;
+    hipLaunchKernelGGL(k_tile_build<TILE>, dim3(blocks_for(n, TILE)), dim3(TILE), 0, s, a);
 }
 
-template <int LANES, bool ENERGY, int MODE>
-void step_lanes(const StepArgs &a, hipStream_t s)
+template <int TILE, bool ENERGY, int MODE>
+void tile_step(const TileArgs &a, hipStream_t s)
 {
-    constexpr int G = 64 / LANES;
-    StepArgs x = a;
-    x.n_waves = blocks_for(a.n, G);
-    int blocks = blocks_for(x.n_waves, WG / 64);
-    blocks = ((blocks + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_step<LANES, ENERGY, MODE>), dim3(blocks), dim3(WG), 0, s, x);
+    TileArgs x = a;
+    x.n_tiles = blocks_for(a.n, TILE);
+    const int blocks = ((x.n_tiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_tile_step<TILE, ENERGY, MODE>), dim3(blocks), dim3(TILE), 0, s, x);
 }
 
 template <bool ENERGY, int MODE>
-void step_dispatch(int lanes, const StepArgs &a, hipStream_t s)
+void tile_dispatch(int tile, const TileArgs &a, hipStream_t s)
 {
-    switch (lanes) {
-    case 1: step_lanes<1, ENERGY, MODE>(a, s); break;
-    case 2: step_lanes<2, ENERGY, MODE>(a, s); break;
-    case 4: step_lanes<4, ENERGY, MODE>(a, s); break;
-    case 8: step_lanes<8, ENERGY, MODE>(a, s); break;
-    default: step_lanes<16, ENERGY, MODE>(a, s); break;
+    switch (tile) {
+    case 64: tile_step<64, ENERGY, MODE>(a, s); break;
+    case 128: tile_step<128, ENERGY, MODE>(a, s); break;
+    default: tile_step<256, ENERGY, MODE>(a, s); break;
     }
 }
 
 }  // namespace
 
-void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int lanes, const GridDev &g, float rc2,
-                    hipStream_t s, bool advance_step_base, int list_every)
+void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int tile, const GridDev &g, float rc2,
+                    float edge, hipStream_t s, bool advance_step_base, int list_every)
 {
-    hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells,
-                       b.n_occupied);
+    hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells);
     hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, WG)), dim3(WG), 0, s, b.pos[cur], n, g, b.traj_cell,
-                       b.cell_count, b.cells, b.occupied, b.n_occupied, b.err, advance_step_base ? b.step_base : nullptr, b.step_next,
-                       list_every);
-    FillArgs f{};
-    f.occupied = b.occupied;
-    f.n_occupied = b.n_occupied;
-    f.count = b.cell_count;
-    f.cells = b.cells;
-    f.traj_lo = b.traj_lo;
-    f.traj_hi = b.traj_hi;
-    f.trow = b.trow;
-    f.tent = b.tent;
-    f.list = b.list;
-    f.list_cnt = b.list_cnt;
-    f.err = b.err;
-    f.g = g;
-    f.rc2 = rc2;
-    f.cap = cap;
-    switch (lanes) {
-    case 1: fill_lanes<1>(f, g.n_cells, s); break;
-    case 2: fill_lanes<2>(f, g.n_cells, s); break;
-    case 4: fill_lanes<4>(f, g.n_cells, s); break;
-    case 8: fill_lanes<8>(f, g.n_cells, s); break;
-    default: fill_lanes<16>(f, g.n_cells, s); break;
+                       b.cell_count, b.cells, b.cell_of, b.err,
+                       advance_step_base ? b.step_base : nullptr, b.step_next, list_every);
+    // a cell whose box is farther than the cutoff plus a rounding margin
+    // holds no partner
+    const float rc = sqrtf(rc2) + 0.1f;
+    const float cull2 = rc * rc;
+    switch (tile) {
+    case 64: rebuild_tile<64>(b, cur, n, cap, g, rc2, edge, cull2, s); break;
+    case 128: rebuild_tile<128>(b, cur, n, cap, g, rc2, edge, cull2, s); break;
+    default: rebuild_tile<256>(b, cur, n, cap, g, rc2, edge, cull2, s); break;
     }
 }
 
-void launch_step(const DevBufs &b, int cur, int n, int cap, int lanes, const StepConsts &c,
+void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode, const long long *step_base,
                  long long step_off, hipStream_t s)
 {
-    StepArgs a{};
+    TileArgs a{};
     a.pin = b.pos[cur];
     a.pout = b.pos[cur ^ 1];
     a.trow = b.trow;
     a.tent = b.tent;
-    a.list = b.list;
+    a.list16 = b.list16;
+    a.topo2 = b.topo2;
     a.list_cnt = b.list_cnt;
+    a.stage = b.stage;
+    a.stage_cnt = b.stage_cnt;
     a.stream_ids = b.stream_ids;
     a.pull_slot = b.pull_slot;
     a.pulls = b.pulls;
@@ -974,14 +1145,14 @@ void launch_step(const DevBufs &b, int cur, int n, int cap, int lanes, const Ste
     a.tip = tip;
     if (mode == 1) {
         if (energy)
-            step_dispatch<true, 1>(lanes, a, s);
+            tile_dispatch<true, 1>(tile, a, s);
         else
-            step_dispatch<false, 1>(lanes, a, s);
+            tile_dispatch<false, 1>(tile, a, s);
     } else {
         if (energy)
-            step_dispatch<true, 0>(lanes, a, s);
+            tile_dispatch<true, 0>(tile, a, s);
         else
-            step_dispatch<false, 0>(lanes, a, s);
+            tile_dispatch<false, 0>(tile, a, s);
     }
 }
 

@@ -92,7 +92,7 @@ def test_protocol_and_schedule_validation(lib):
     s = make_config("c1")
     c = _ctx(s)
     with pytest.raises(P.SopError):
-        c.set_lanes(3)
+        c.set_tile(96)
     with pytest.raises(P.SopError):
         c.set_pulling(0, s.n_res, 1.0, np.zeros(3), np.zeros(3))   # residue out of range
     c.set_pulling(0, s.n_res - 1, 1.0, np.zeros(3), np.zeros(3))
@@ -102,8 +102,9 @@ def test_protocol_and_schedule_validation(lib):
         c.set_tip(5.0, 1.0, 0.0, np.zeros(3), np.zeros(3))      # sigma <= 0
     c.set_tip(5.0, 1.0, 1.0, np.zeros(3), np.zeros(3))
     c.set_tip(-1.0, 0.0, 1.0, np.zeros(3), np.zeros(3))          # removes the tip
-    for k in [1, 2, 4, 8, 16, 0]:
-        c.set_lanes(k)
+    for k in [64, 128, 256, 0]:
+        c.set_tile(k)
+    assert c.get_tile() in (64, 128, 256)
 
 
 def test_batched_schedule_validation(lib):

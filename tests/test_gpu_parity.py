@@ -132,11 +132,11 @@ def test_pairlist_bit_exact(P, orc, name):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
-def test_pairlist_all_lane_layouts(P, orc, lanes):
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_pairlist_all_tile_sizes(P, orc, tile):
     s = cfg("c1")
-    x = perturbed(s, 0.5, seed=lanes)   # the list build evaluates no bond terms
-    c = ctx_for(P, s, x=x, lanes=lanes)
+    x = perturbed(s, 0.5, seed=tile)   # the list build evaluates no bond terms
+    c = ctx_for(P, s, x=x, tile=tile)
     c.build_pairlist()
     ref = orc.OracleSystem(s, RunParams()).pairlist(x)
     assert np.array_equal(c.get_pairlist(), ref)
@@ -185,11 +185,11 @@ def test_forces_and_energies(P, orc, name):
     assert np.allclose(fe, feo, rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
-def test_forces_all_lane_counts(P, orc, lanes):
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_forces_all_tile_sizes(P, orc, tile):
     s = cfg("c1")
     x = perturbed(s, seed=2)
-    c = ctx_for(P, s, x=x, lanes=lanes)
+    c = ctx_for(P, s, x=x, tile=tile)
     F, E, _ = c.compute_forces()
     Fo, Eo, _, _ = orc.OracleSystem(s, RunParams()).forces(x)
     assert rel_l2(F, Fo) <= FORCE_TOL
