@@ -333,7 +333,7 @@ sop_status need_ready(sop_ctx *c)
 
 void rebuild(sop_ctx *c, hipStream_t s, bool advance)
 {
-    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), cell_edge(c), s, advance,
+    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), c->n_traj > 1 ? 1 : 0, s, advance,
                    c->p.list_every);
 }
 

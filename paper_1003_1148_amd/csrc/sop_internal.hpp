@@ -106,7 +106,7 @@ struct StepConsts {
 // ---- kernel launchers (sop_kernels.hip) ----------------------------------
 // Plain schedule, tiles of `tile` residues (64, 128 or 256).
 void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int tile, const GridDev &g,
-                    float rc2, float edge, hipStream_t s, bool advance_step_base, int list_every);
+                    float rc2, int multi, hipStream_t s, bool advance_step_base, int list_every);
 // mode: 0 = step, 1 = forces only
 void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode,
@@ -127,8 +127,8 @@ void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long lo
 // slots a tile of `tile` residues can stage.
 inline size_t list16_index_host(long long r, int k, int cap, int tile)
 {
-    return (size_t)(r / tile) * (size_t)cap * tile + (size_t)(k >> 3) * (8 * (size_t)tile) +
-           (size_t)(r % tile) * 8 + (size_t)(k & 7);
+    return (size_t)(r / tile) * (size_t)cap * tile + (size_t)(k >> 2) * (4 * (size_t)tile) +
+           (size_t)(r % tile) * 4 + (size_t)(k & 3);
 }
 inline int stage_max_host(int tile) { return tile >= 256 ? 2048 : 1024; }
 

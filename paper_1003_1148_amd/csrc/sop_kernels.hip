@@ -167,11 +167,9 @@ __device__ __forceinline__ PairConsts pair_consts(const StepConsts &c)
 }
 
 // FENE: -(k R0^2/2) ln(1 - (r - r0)^2/R0^2); |r - r0| >= R0 sets `broken`.
-__device__ __forceinline__ void add_fene(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
-                                         const float4 &lj, float r0, const PairConsts &k, bool rec,
-                                         bool &broken)
+__device__ __forceinline__ void add_fene_d(Acc &A, const float3 &d, float r0, const PairConsts &k, bool rec,
+                                           bool &broken)
 {
-    const float3 d = pair_delta(hi, lo, hj, lj);
     const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
     const float rr = __builtin_amdgcn_sqrtf(r2);
     const float dl = rr - r0;
@@ -193,10 +191,8 @@ __device__ __forceinline__ void add_fene(Acc &A, const float4 &hi, const float4 
 }
 
 // Native contact: eps_h [(r0/r)^12 - 2 (r0/r)^6].
-__device__ __forceinline__ void add_native(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
-                                           const float4 &lj, float r0, const PairConsts &k, bool rec)
+__device__ __forceinline__ void add_native_d(Acc &A, const float3 &d, float r0, const PairConsts &k, bool rec)
 {
-    const float3 d = pair_delta(hi, lo, hj, lj);
     const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
     const float ir2 = fast_rcp(r2);
     const float s = r0 * r0 * ir2;
@@ -212,11 +208,8 @@ __device__ __forceinline__ void add_native(Acc &A, const float4 &hi, const float
 }
 
 // Soft repulsion: eps_l (sigma/r)^6.
-__device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const float4 &lo,
-                                              const float4 &hj, const float4 &lj, const PairConsts &k,
-                                              bool rec)
+__device__ __forceinline__ void add_repulsive_d(Acc &A, const float3 &d, const PairConsts &k, bool rec)
 {
-    const float3 d = pair_delta(hi, lo, hj, lj);
     const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
     const float ir2 = fast_rcp(r2);
     const float s = k.sg2 * ir2;
@@ -229,6 +222,27 @@ __device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const fl
         A.e_r += (double)(k.el * q);
         A.vir += (double)(k.el6 * q);
     }
+}
+
+// The same terms from compensated positions (hi, lo) of both residues.
+__device__ __forceinline__ void add_fene(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
+                                         const float4 &lj, float r0, const PairConsts &k, bool rec,
+                                         bool &broken)
+{
+    add_fene_d(A, pair_delta(hi, lo, hj, lj), r0, k, rec, broken);
+}
+
+__device__ __forceinline__ void add_native(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
+                                           const float4 &lj, float r0, const PairConsts &k, bool rec)
+{
+    add_native_d(A, pair_delta(hi, lo, hj, lj), r0, k, rec);
+}
+
+__device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const float4 &lo,
+                                              const float4 &hj, const float4 &lj, const PairConsts &k,
+                                              bool rec)
+{
+    add_repulsive_d(A, pair_delta(hi, lo, hj, lj), k, rec);
 }
 
 // Cantilever `pull` (index or -1) and tip on one residue at t_n = step*h.
@@ -324,18 +338,14 @@ __device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Ac
 template <int TILE>
 constexpr int stage_max() { return TILE >= 256 ? 2048 : 1024; }
 
-// Entry k of lane t of a tile: rows are stored in chunks of 8 slots per lane
-// so that one 16-byte load brings the next 8 partners of a residue.
+// Candidate residues (the residues of the cells around a tile) held in LDS
+// at once during a rebuild; more are taken in windows of whole cells.
+constexpr int CAND_WIN = 1024;
+// Distinct cells around one tile, and the bits of its open-addressing table.
 template <int TILE>
-__device__ __forceinline__ size_t list16_index(int tile, int t, int k, int cap)
-{
-    return (size_t)tile * cap * TILE + (size_t)(k >> 3) * (8 * TILE) + (size_t)t * 8 + (k & 7);
-}
-
-constexpr int CAND_MAX = 2816;  // candidate residues a tile stages in LDS during a rebuild
-constexpr int CELLS_MAX = 640;  // distinct cells around one tile
-constexpr int CHASH_BITS = 10;
-constexpr int CHASH = 1 << CHASH_BITS;  // open-addressing table of those cells
+constexpr int cells_max() { return TILE >= 256 ? 512 : 1024; }
+template <int TILE>
+constexpr int chash_bits() { return TILE >= 256 ? 10 : 11; }
 constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
 
 struct BuildArgs {
@@ -355,48 +365,105 @@ struct BuildArgs {
     int *stage_cnt;
     unsigned *err;
     GridDev g;
-    float rc2, edge, cull2;
-    int n, cap;
+    float rc2;
+    int n, cap, multi;
 };
 
-// One workgroup per tile.  (1) The cells around the tile's residues (their
-// 27-cell neighbourhoods) go into an LDS table; their residues are copied to
-// LDS and ranked by id within each cell.  (2) Each lane builds its residue's
-// row over its 27 cells in a fixed order (cells whose box lies beyond the
-// cutoff are skipped), members in id order: the Algorithm 3 filter r < r_list
-// without bonded or native partners.  (3) The candidates that some row or
-// bond/native entry uses become the tile's staging slots, and rows are
-// rewritten as slots.
-template <int TILE>
-__global__ __launch_bounds__(TILE) void k_tile_build(BuildArgs a)
+// Exclusive prefix sum over the NT lanes of a workgroup (all lanes call it).
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int v, int *part, int &total)
 {
+    const int t = threadIdx.x;
+    part[t] = v;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        const int x = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    total = part[NT - 1];
+    const int r = part[t] - v;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int wrap_int(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Along one axis of the wrapped grid, cell c is u's own or an adjacent one.
+__device__ __forceinline__ bool adjacent_cell(int c, int u, int n)
+{
+    const int d = wrap_int(c - u, n);
+    return d <= 1 || d == n - 1;
+}
+
+// Bonded/native entry codes while a tile is built.
+constexpr unsigned CODE_NONE = 0xffffffffu;     // partner not found yet
+constexpr unsigned CODE_WINDOW = 0x80000000u;   // | candidate index in the current window
+constexpr unsigned CODE_EXTRA = 0x40000000u;    // | index among the extra slots
+
+// One workgroup of 256 lanes per tile of TILE consecutive residues; lane t
+// serves residue t % TILE and part t / TILE of its work.
+//  1. The cells around the tile's residues (each residue's own and adjacent
+//     cells) go into an LDS hash table and are sorted by cell index; their
+//     residues, sorted by (cell, residue index), are the tile's candidates.
+//  2. Per window of whole cells (at most CAND_WIN candidates, usually one
+//     window): candidates go to LDS; each residue is tested against them 32
+//     at a time with the single-precision predicate r < r_list of
+//     Algorithm 3, one bit per candidate (groups of 32 outside every
+//     neighbourhood of a wave are skipped); self, bonded and native partners
+//     are cleared; candidates some row or entry uses get the next staging
+//     slots in sorted order, and rows are appended as slots.
+//  3. Bonded/native partners outside the cells take extra slots at the end.
+// A row lists its partners in (cell, residue index) order whatever the tile
+// size or the order in which residues were binned.
+template <int TILE>
+__global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
+{
+    constexpr int NT = 256, NLB = NT / TILE;
     constexpr int SM = stage_max<TILE>();
-    __shared__ float4 cand[CAND_MAX];            // arrival order within each cell
-    __shared__ unsigned short order[CAND_MAX];   // rank in cell -> arrival index
-    __shared__ unsigned short used[CAND_MAX];    // 0/1, then the slot number
+    constexpr int CM = CAND_WIN;
+    constexpr int NW = CM / 32;
+    constexpr int CELLS_MAX = cells_max<TILE>();
+    constexpr int CHASH_BITS = chash_bits<TILE>();
+    constexpr int CHASH = 1 << CHASH_BITS;
+    static_assert(NW * TILE >= CM, "arrival ids alias the row bits");
+    __shared__ float4 cand[CM];           // the window's candidates, sorted
+    __shared__ unsigned bits[NW * TILE];  // row bits, word-major; first the arrival ids
     __shared__ int hkey[CHASH];
-    __shared__ short hval[CHASH];
-    __shared__ int ccell[CELLS_MAX];
+    __shared__ short hval[CHASH];         // cell number: arrival, then sorted
+    __shared__ int ccell[CELLS_MAX];      // arrival order
+    __shared__ short rank_of[CELLS_MAX];
+    __shared__ int scell[CELLS_MAX];      // sorted: cell index and its packed coordinates
+    __shared__ unsigned sxyz[CELLS_MAX];
     __shared__ int cbase[CELLS_MAX + 1];
-    __shared__ int part[TILE];
+    __shared__ unsigned used[NW];
+    __shared__ int wbase[NW];
+    __shared__ short wlo[NW], whi[NW];    // sorted cells spanned by each word
     __shared__ int extra[EXTRA_MAX];
-    __shared__ int n_cu, n_extra, bad;
+    __shared__ int part[NT];
+    __shared__ int n_cu, n_extra, bad_cells, n_used_w;
 
     const int tile = blockIdx.x, t = threadIdx.x;
-    const int i = tile * TILE + t;
+    const int rho = t % TILE, q = t / TILE;
+    const int i = tile * TILE + rho;
     const bool act = i < a.n;
+    const bool lead = act && q == 0;  // owns the residue's row and entries
     const GridDev g = a.g;
-    for (int h = t; h < CHASH; h += TILE)
+    for (int h = t; h < CHASH; h += NT)
         hkey[h] = -1;
     if (t == 0) {
         n_cu = 0;
         n_extra = 0;
-        bad = 0;
+        bad_cells = 0;
     }
     __syncthreads();
 
-    auto wrap = [](int v, int n) { const int r = v % n; return r < 0 ? r + n : r; };
-    auto hslot = [](int key) { return (int)(((unsigned)key * 2654435761u) >> (32 - CHASH_BITS)) & (CHASH - 1); };
+    auto hslot = [](int key) { return (int)(((unsigned)key * 2654435761u) >> (32 - CHASH_BITS)); };
     auto lookup = [&](int key) -> int {
         int h = hslot(key);
         for (int probe = 0; probe < CHASH; ++probe) {
@@ -410,24 +477,18 @@ __global__ __launch_bounds__(TILE) void k_tile_build(BuildArgs a)
         return -1;
     };
 
-    // own residue: position, unwrapped cell coordinates, neighbourhood
+    // ---- 1. cells around the tile ----
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-    int ux = 0, uy = 0, uz = 0;
+    int ux = 0, uy = 0, uz = 0;  // own wrapped cell coordinates
     if (act) {
         p = a.pos[2 * i];
         const int4 off = a.traj_cell[__float_as_int(a.pos[2 * i + 1].w)];
-        auto ucell = [&](float x, int o) {
-            float v = floorf(x * g.inv_cell);
-            if (!(v == v))
-                v = 0.0f;
-            return (int)fminf(fmaxf(v, -1.0e9f), 1.0e9f) + o;
-        };
-        ux = ucell(p.x, off.x);
-        uy = ucell(p.y, off.y);
-        uz = ucell(p.z, off.z);
-        for (int d = 0; d < 27; ++d) {
-            const int cid = wrap(ux + d % 3 - 1, g.gx) +
-                            g.gx * (wrap(uy + (d / 3) % 3 - 1, g.gy) + g.gy * wrap(uz + d / 9 - 1, g.gz));
+        ux = wrap_cell(p.x, g.inv_cell, off.x, g.gx);
+        uy = wrap_cell(p.y, g.inv_cell, off.y, g.gy);
+        uz = wrap_cell(p.z, g.inv_cell, off.z, g.gz);
+        for (int d = q; d < 27; d += NLB) {
+            const int cid = wrap_int(ux + d % 3 - 1, g.gx) +
+                            g.gx * (wrap_int(uy + (d / 3) % 3 - 1, g.gy) + g.gy * wrap_int(uz + d / 9 - 1, g.gz));
             int h = hslot(cid);
             for (int probe = 0; probe < CHASH; ++probe) {
                 const int prev = atomicCAS(&hkey[h], -1, cid);
@@ -437,7 +498,7 @@ __global__ __launch_bounds__(TILE) void k_tile_build(BuildArgs a)
                         ccell[m] = cid;
                         hval[h] = (short)m;
                     } else {
-                        bad = 1;
+                        bad_cells = 1;
                     }
                     break;
                 }
@@ -445,42 +506,69 @@ __global__ __launch_bounds__(TILE) void k_tile_build(BuildArgs a)
                     break;
                 h = (h + 1) & (CHASH - 1);
                 if (probe == CHASH - 1)
-                    bad = 1;
+                    bad_cells = 1;
             }
         }
     }
     __syncthreads();
-    const int NC = n_cu;
-    if (bad == 0 && NC <= CELLS_MAX) {
-        for (int m = t; m < NC; m += TILE)
-            cbase[m + 1] = min(a.count[ccell[m]], CELL_CAP);
-        __syncthreads();
-        if (t == 0) {
-            cbase[0] = 0;
-            for (int m = 0; m < NC; ++m)
-                cbase[m + 1] += cbase[m];
-            if (cbase[NC] > CAND_MAX)
-                bad = 1;
-        }
-    }
-    __syncthreads();
-    const int2 row = act ? a.trow[i] : make_int2(0, 0);
+    const int2 row = lead ? a.trow[i] : make_int2(0, 0);
     const int ntop = (row.y & 4095) + (row.y >> 12);
-    if (bad || NC > CELLS_MAX) {
-        // report, leave the tile's slots at the empty slot so steps stay in bounds
+    uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
+    auto fail_tile = [&]() {
+        // report; leave the tile pointing at the empty slot so steps stay in bounds
         if (t == 0) {
             atomicOr(a.err, ERR_STAGE);
             a.stage_cnt[tile] = 0;
         }
-        if (act) {
+        if (lead) {
             a.list_cnt[i] = 0;
-            uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
             for (int e = 0; e < ntop; ++e)
                 trw[(size_t)e * TILE] = make_uint2((unsigned)SM, __float_as_uint(1.0f));
         }
-        return;  // uniform: bad and NC are read after a barrier
+    };
+    if (bad_cells) {
+        fail_tile();
+        return;  // uniform: read after a barrier, written only before it
     }
-    const int M = cbase[NC];
+    const int NC = n_cu;
+    // coordinates packed in bx + by + bz <= 32 bits (the grid has at most 2^21 cells)
+    const int bx = 32 - __clz(g.gx), by = 32 - __clz(g.gy);
+    const unsigned mx = (1u << bx) - 1u, my = (1u << by) - 1u;
+    // sort the cells by index (rank by counting; indices are distinct)
+    for (int m = t; m < NC; m += NT) {
+        const int c = ccell[m];
+        int r = 0;
+        for (int m2 = 0; m2 < NC; ++m2)
+            r += ccell[m2] < c;
+        rank_of[m] = (short)r;
+        scell[r] = c;
+        sxyz[r] = (unsigned)(c % g.gx) | ((unsigned)((c / g.gx) % g.gy) << bx) |
+                  ((unsigned)(c / (g.gx * g.gy)) << (bx + by));
+    }
+    __syncthreads();
+    for (int h = t; h < CHASH; h += NT)
+        if (hkey[h] >= 0)
+            hval[h] = rank_of[hval[h]];
+    // candidate counts -> cbase (exclusive prefix in sorted cell order)
+    {
+        const int cper = (NC + NT - 1) / NT;
+        const int m0 = min(NC, t * cper), m1 = min(NC, m0 + cper);
+        int csum = 0;
+        for (int m = m0; m < m1; ++m)
+            csum += min(a.count[scell[m]], CELL_CAP);
+        int M = 0;
+        int cb = block_exclusive_scan<NT>(csum, part, M);
+        for (int m = m0; m < m1; ++m) {
+            cbase[m] = cb;
+            cb += min(a.count[scell[m]], CELL_CAP);
+        }
+        if (t == 0)
+            cbase[NC] = M;
+    }
+    if (lead)
+        for (int e = 0; e < ntop; ++e)
+            trw[(size_t)e * TILE] = make_uint2(CODE_NONE, __float_as_uint(a.tent[row.x + e].y));
+    __syncthreads();
     auto segment_of = [&](int ci) {  // last m with cbase[m] <= ci
         int lo = 0, hi = NC;
         while (hi - lo > 1) {
@@ -492,158 +580,214 @@ __global__ __launch_bounds__(TILE) void k_tile_build(BuildArgs a)
         }
         return lo;
     };
-    for (int ci = t; ci < M; ci += TILE) {
-        const int m = segment_of(ci);
-        cand[ci] = a.cells[(size_t)ccell[m] * CELL_CAP + (ci - cbase[m])];
-        used[ci] = 0;
-    }
-    __syncthreads();
-    for (int ci = t; ci < M; ci += TILE) {
-        const int m = segment_of(ci);
-        const int id = __float_as_int(cand[ci].w);
-        int rank = 0;
-        for (int k = cbase[m]; k < cbase[m + 1]; ++k)
-            rank += __float_as_int(cand[k].w) < id;
-        order[cbase[m] + rank] = (unsigned short)ci;
-    }
-    __syncthreads();
 
-    // rows, one lane per residue, with arrival indices for now
+    // ---- 2. windows of whole cells ----
+    const unsigned pad = (unsigned)SM | ((unsigned)SM << 16);
+    uint2 *lrow = reinterpret_cast<uint2 *>(a.list16) + (size_t)tile * (a.cap >> 2) * TILE + rho;
+    int *st = a.stage + (size_t)tile * SM;
     int cnt = 0;
-    if (act) {
-        const int tlo = a.traj_lo[i], thi = a.traj_hi[i];
-        int ex[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            ex[u] = u < ntop ? __float_as_int(a.tent[row.x + u].x) : -2;
-        const float lx = floorf(p.x * g.inv_cell) * a.edge;
-        const float ly = floorf(p.y * g.inv_cell) * a.edge;
-        const float lz = floorf(p.z * g.inv_cell) * a.edge;
-        const float gx[3] = {p.x - lx, 0.0f, lx + a.edge - p.x};
-        const float gy[3] = {p.y - ly, 0.0f, ly + a.edge - p.y};
-        const float gz[3] = {p.z - lz, 0.0f, lz + a.edge - p.z};
-        for (int d = 0; d < 27; ++d) {
-            const int dx = d % 3, dy = (d / 3) % 3, dz = d / 9;
-            // smallest distance from p to that cell's box
-            if (gx[dx] * gx[dx] + gy[dy] * gy[dy] + gz[dz] * gz[dz] > a.cull2)
-                continue;
-            const int cid = wrap(ux + dx - 1, g.gx) + g.gx * (wrap(uy + dy - 1, g.gy) + g.gy * wrap(uz + dz - 1, g.gz));
-            const int m = lookup(cid);
-            for (int r = cbase[m]; r < cbase[m + 1]; ++r) {
-                const int ci = order[r];
-                const float4 q = cand[ci];
-                const int j = __float_as_int(q.w);
-                if (j == i || j < tlo || j >= thi || !within_cutoff(p, q, a.rc2))
-                    continue;
-                bool excl = false;
-#pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    excl |= ex[u] == j;
-                for (int e = 16; e < ntop; ++e)
-                    excl |= __float_as_int(a.tent[row.x + e].x) == j;
-                if (excl)
-                    continue;
-                if (cnt < a.cap)
-                    a.list16[list16_index<TILE>(tile, t, cnt, a.cap)] = (unsigned short)ci;
-                used[ci] = 1;
-                ++cnt;
+    uint2 acc = make_uint2(pad, pad);
+    const int tlo = act ? a.traj_lo[i] : 0, thi = act ? a.traj_hi[i] : 0;
+    int slot_base = 0;
+    int *aid = reinterpret_cast<int *>(bits);
+    for (int mA = 0; mA < NC;) {
+        int mB = mA + 1;  // a cell holds at most CELL_CAP <= CM residues
+        {
+            int hi = NC;
+            while (mB < hi) {
+                const int mid = (mB + hi + 1) >> 1;
+                if (cbase[mid] - cbase[mA] <= CM)
+                    mB = mid;
+                else
+                    hi = mid - 1;
             }
         }
-        a.list_cnt[i] = cnt;
-        if (cnt > a.cap)
-            atomicOr(a.err, ERR_OVERFLOW);
-        // bonded and native partners: their candidate, or an extra slot
-        uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
-        for (int e = 0; e < ntop; ++e) {
-            const float2 te = a.tent[row.x + e];
-            const int j = __float_as_int(te.x);
-            const int m = lookup(a.cell_of[j]);
-            int ci = -1;
-            if (m >= 0) {
-                int lo = cbase[m], hi = cbase[m + 1];  // binary search by id in the cell
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const int idm = __float_as_int(cand[order[mid]].w);
-                    if (idm < j)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
+        const int base = cbase[mA], Mw = cbase[mB] - base;
+        for (int ci = t; ci < Mw; ci += NT) {
+            const int m = segment_of(base + ci);
+            aid[ci] = __float_as_int(a.cells[(size_t)scell[m] * CELL_CAP + (base + ci - cbase[m])].w);
+        }
+        for (int w = t; w < NW; w += NT)
+            used[w] = 0u;
+        __syncthreads();
+        for (int ci = t; ci < Mw; ci += NT) {
+            const int m = segment_of(base + ci);
+            const int id = aid[ci];
+            const int k0 = cbase[m] - base, k1 = cbase[m + 1] - base;
+            int r = k0;
+            for (int k = k0; k < k1; ++k)
+                r += aid[k] < id;
+            cand[r] = a.cells[(size_t)scell[m] * CELL_CAP + (base + ci - cbase[m])];
+        }
+        const int NWm = (Mw + 31) >> 5;
+        for (int w = t; w < NWm; w += NT) {
+            wlo[w] = (short)segment_of(base + 32 * w);
+            whi[w] = (short)segment_of(base + min(32 * w + 31, Mw - 1));
+        }
+        __syncthreads();
+        // row bits; part q takes words w = q mod NLB (uniform over a wave)
+        for (int w = q; w < NWm; w += NLB) {
+            bool reach = false;
+            if (act)
+                for (int m = wlo[w]; m <= whi[w]; ++m) {
+                    const unsigned v = sxyz[m];
+                    reach |= adjacent_cell((int)(v & mx), ux, g.gx) &&
+                             adjacent_cell((int)((v >> bx) & my), uy, g.gy) &&
+                             adjacent_cell((int)(v >> (bx + by)), uz, g.gz);
                 }
-                if (lo < cbase[m + 1] && __float_as_int(cand[order[lo]].w) == j)
-                    ci = order[lo];
+            unsigned word = 0u;
+            if (__any(reach)) {
+#pragma unroll 8
+                for (int k = 0; k < 32; ++k) {
+                    const int r = 32 * w + k;
+                    const float4 c = cand[r];
+                    const int j = __float_as_int(c.w);
+                    bool pass = act && r < Mw && within_cutoff(p, c, a.rc2);
+                    if (a.multi)
+                        pass = pass && j >= tlo && j < thi;
+                    word |= pass ? (1u << k) : 0u;
+                }
             }
-            unsigned code;
-            if (ci >= 0) {
-                used[ci] = 1;
-                code = (unsigned)ci;
-            } else {
+            bits[w * TILE + rho] = word;
+        }
+        __syncthreads();
+        // self, bonded and native partners in this window: clear their bits
+        auto find = [&](int j) -> int {  // window candidate of residue j, or -1
+            const int m = lookup(a.cell_of[j]);
+            if (m < mA || m >= mB)
+                return -1;
+            int lo = cbase[m] - base, hi = cbase[m + 1] - base;
+            const int end = hi;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (__float_as_int(cand[mid].w) < j)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            return (lo < end && __float_as_int(cand[lo].w) == j) ? lo : -1;
+        };
+        if (lead) {
+            const int rs = find(i);
+            if (rs >= 0)
+                bits[(rs >> 5) * TILE + rho] &= ~(1u << (rs & 31));
+            for (int e = 0; e < ntop; ++e) {
+                if (trw[(size_t)e * TILE].x != CODE_NONE)
+                    continue;
+                const int r = find(__float_as_int(a.tent[row.x + e].x));
+                if (r >= 0) {
+                    bits[(r >> 5) * TILE + rho] &= ~(1u << (r & 31));
+                    atomicOr(&used[r >> 5], 1u << (r & 31));
+                    trw[(size_t)e * TILE].x = CODE_WINDOW | (unsigned)r;
+                }
+            }
+        }
+        __syncthreads();
+        for (int w = t; w < NWm; w += NT) {
+            unsigned u = 0u;
+            for (int l = 0; l < TILE; ++l)
+                u |= bits[w * TILE + l];
+            used[w] |= u;  // this lane alone writes word w now
+        }
+        __syncthreads();
+        // slots of the used candidates: prefix over the window's words (<= 32)
+        if (t < 64) {
+            const int c = t < NWm ? __popc(used[t]) : 0;
+            int v = c;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(v, off, 64);
+                if (t >= off)
+                    v += y;
+            }
+            if (t < NWm)
+                wbase[t] = slot_base + v - c;
+            if (t == 63)
+                n_used_w = v;
+        }
+        __syncthreads();
+        const int nu = n_used_w;
+        if (slot_base + nu > SM) {
+            fail_tile();
+            return;  // uniform
+        }
+        if (t < NWm) {
+            int sl = wbase[t];
+            unsigned u = used[t];
+            while (u) {
+                const int b = __ffs(u) - 1;
+                u &= u - 1u;
+                st[sl++] = __float_as_int(cand[32 * t + b].w);
+            }
+        }
+        if (lead) {
+            // append this window's partners: chunks of 4 slots, the last one
+            // padded with the empty slot SM (far away: its term is exactly 0)
+            for (int w = 0; w < NWm; ++w) {
+                unsigned b = bits[w * TILE + rho];
+                while (b) {
+                    const int k = __ffs(b) - 1;
+                    b &= b - 1u;
+                    const unsigned sl = (unsigned)(wbase[w] + __popc(used[w] & ((1u << k) - 1u)));
+                    if (cnt < a.cap) {
+                        const int pos = cnt & 3, sh = (pos & 1) * 16;
+                        if (pos < 2)
+                            acc.x = (acc.x & ~(0xffffu << sh)) | (sl << sh);
+                        else
+                            acc.y = (acc.y & ~(0xffffu << sh)) | (sl << sh);
+                        if (pos == 3) {
+                            lrow[(size_t)(cnt >> 2) * TILE] = acc;
+                            acc = make_uint2(pad, pad);
+                        }
+                    }
+                    ++cnt;
+                }
+            }
+            for (int e = 0; e < ntop; ++e) {
+                const unsigned v = trw[(size_t)e * TILE].x;
+                if (v != CODE_NONE && (v & CODE_WINDOW)) {
+                    const int r = (int)(v & ~CODE_WINDOW), w = r >> 5;
+                    trw[(size_t)e * TILE].x =
+                        (unsigned)(wbase[w] + __popc(used[w] & ((1u << (r & 31)) - 1u)));
+                }
+            }
+        }
+        slot_base += nu;
+        mA = mB;
+        __syncthreads();  // the window's buffers are reused
+    }
+
+    // ---- 3. partners outside the cells ----
+    if (lead)
+        for (int e = 0; e < ntop; ++e)
+            if (trw[(size_t)e * TILE].x == CODE_NONE) {
                 const int k = atomicAdd(&n_extra, 1);
                 if (k < EXTRA_MAX)
-                    extra[k] = j;
-                code = 0x80000000u | (unsigned)k;
+                    extra[k] = __float_as_int(a.tent[row.x + e].x);
+                trw[(size_t)e * TILE].x = CODE_EXTRA | (unsigned)k;
             }
-            trw[(size_t)e * TILE] = make_uint2(code, __float_as_uint(te.y));
-        }
-    }
     __syncthreads();
-    // used candidates -> slots (exclusive prefix over arrival order)
-    const int per = (M + TILE - 1) / TILE;
-    const int c0 = min(M, t * per), c1 = min(M, c0 + per);
-    int u = 0;
-    for (int ci = c0; ci < c1; ++ci)
-        u += used[ci];
-    part[t] = u;
-    __syncthreads();
-    for (int off = 1; off < TILE; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    const int n_used = part[TILE - 1];
-    const int S = n_used + min(n_extra, EXTRA_MAX);
-    if (S > SM || n_extra > EXTRA_MAX) {
-        if (t == 0) {
-            atomicOr(a.err, ERR_STAGE);
-            a.stage_cnt[tile] = 0;
-        }
-        if (act) {
-            a.list_cnt[i] = 0;
-            uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
-            for (int e = 0; e < ntop; ++e)
-                trw[(size_t)e * TILE] = make_uint2((unsigned)SM, __float_as_uint(1.0f));
-        }
+    const int n_ex = n_extra;
+    const int S = slot_base + min(n_ex, EXTRA_MAX);
+    if (S > SM || n_ex > EXTRA_MAX) {
+        fail_tile();
         return;  // uniform
     }
-    int sl = part[t] - u;
-    int *st = a.stage + (size_t)tile * SM;
-    for (int ci = c0; ci < c1; ++ci) {
-        if (used[ci]) {
-            st[sl] = __float_as_int(cand[ci].w);
-            used[ci] = (unsigned short)sl;
-            ++sl;
-        }
-    }
-    for (int k = t; k < min(n_extra, EXTRA_MAX); k += TILE)
-        st[n_used + k] = extra[k];
+    for (int k = t; k < n_ex; k += NT)
+        st[slot_base + k] = extra[k];
     if (t == 0)
         a.stage_cnt[tile] = S;
-    __syncthreads();
-    if (act) {
-        // rows padded to a multiple of 8 with the empty slot SM (a position
-        // far away, so its pair term is exactly zero)
-        const int m = min(cnt, a.cap);
-        for (int k = 0; k < ((m + 7) & ~7); ++k) {
-            const size_t x = list16_index<TILE>(tile, t, k, a.cap);
-            a.list16[x] = k < m ? used[a.list16[x]] : (unsigned short)SM;
-        }
-        uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
-        for (int e = 0; e < ntop; ++e) {
-            const uint2 v = trw[(size_t)e * TILE];
-            const unsigned sl2 = (v.x & 0x80000000u) ? (unsigned)n_used + (v.x & 0x7fffffffu) : used[v.x];
-            trw[(size_t)e * TILE] = make_uint2(sl2, v.y);
-        }
+    if (!lead)
+        return;
+    for (int e = 0; e < ntop; ++e) {
+        const unsigned v = trw[(size_t)e * TILE].x;
+        if ((v & CODE_WINDOW) == 0 && (v & CODE_EXTRA))
+            trw[(size_t)e * TILE].x = (unsigned)slot_base + (v & ~CODE_EXTRA);
     }
+    if ((cnt & 3) && cnt < a.cap)
+        lrow[(size_t)(cnt >> 2) * TILE] = acc;
+    a.list_cnt[i] = cnt;
+    if (cnt > a.cap)
+        atomicOr(a.err, ERR_OVERFLOW);
 }
 
 struct TileArgs {
@@ -669,127 +813,238 @@ struct TileArgs {
     TipDev tip;
 };
 
-// One workgroup per tile, one lane per residue: stage the tile's slots in
-// LDS, then every pair term reads LDS.
-// Few waves per SIMD (about one residue per lane across the GPU), so the
-// compiler may trade registers for loads in flight.
-template <int TILE, bool ENERGY, int MODE>
-__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tile_step(TileArgs a)
+// Position relative to the tile's origin O as an unevaluated sum rh + rl:
+// (hi - O) + lo by two error-free TwoSum steps, so rh + rl carries the
+// compensated position to about 2^-44 relative.
+__device__ __forceinline__ void tile_frame(const float4 &hi, const float4 &lo, const float4 &O, float4 &rh,
+                                           float4 &rl)
 {
+    float h[3], l[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const float x = comp(hi, ax), o = comp(O, ax), xl = comp(lo, ax);
+        const float s = x - o;  // TwoSum(x, -o)
+        const float bb = s - x;
+        const float e = (x - (s - bb)) + (-o - bb);
+        const float t = e + xl;
+        const float r = s + t;  // TwoSum(s, t)
+        const float bp = r - s;
+        h[ax] = r;
+        l[ax] = (s - (r - bp)) + (t - bp);
+    }
+    rh = make_float4(h[0], h[1], h[2], 0.0f);
+    rl = make_float4(l[0], l[1], l[2], 0.0f);
+}
+
+// Staged coordinates within this distance of the tile origin let list pairs
+// use rh alone (separation error below 4e-6 A); wider tiles use rh + rl.
+constexpr float NARROW_TILE = 64.0f;
+
+// One workgroup of 256 lanes per tile of TILE residues: NL = 256/TILE lanes
+// per residue.  Lane t works on residue t % TILE and takes part q = t / TILE
+// of its row (list chunks c = q mod NL, bonded/native entries e = q mod NL);
+// part 0 adds the other parts' sums in a fixed order and does the update.
+template <int TILE, bool ENERGY, int MODE>
+__global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
+{
+    constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
-    __shared__ float4 sh[2 * (SM + 1)];  // slot SM: the far-away empty slot
+    __shared__ float4 rh_s[SM + 1];  // slot SM: the far-away empty slot
+    __shared__ float4 rl_s[SM + 1];
+    __shared__ float red_f[NL > 1 ? (NL - 1) * 3 * TILE : 1];
+    __shared__ double red_e[(ENERGY && NL > 1) ? (NL - 1) * 4 * TILE : 1];
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
     const int per = gridDim.x >> 3;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (tile >= a.n_tiles)
-        return;
+        return;  // uniform over the workgroup
     const int t = threadIdx.x;
-    const int i = tile * TILE + t;
+    const int rho = t % TILE, q = t / TILE;
+    const int i = tile * TILE + rho;
     const bool act = i < a.n;
     const int S = a.stage_cnt[tile];
     const int *st = a.stage + (size_t)tile * SM;
-    // independent loads of this residue's data first
+    const int mid = min(tile * TILE + TILE / 2, a.n - 1);
+    // loads that do not depend on the staging first: own row, list chunks
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
     int cnt = 0;
-    const uint4 *lp4 = reinterpret_cast<const uint4 *>(a.list16) + (size_t)tile * (a.cap >> 3) * TILE + t;
-    const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + t;
-    uint4 cur = make_uint4(0u, 0u, 0u, 0u);
+    const int capc = a.cap >> 2;
+    const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16) + (size_t)tile * capc * TILE + rho;
+    const int last_ch = capc - 1;
+    auto fetch = [&](int c) -> uint2 { return lp[(size_t)min(c, last_ch) * TILE]; };
+    uint2 q0 = make_uint2(0u, 0u), q1 = q0, q2 = q0, q3 = q0;
     if (act) {
         hi0 = a.pin[2 * i];
         lo0 = a.pin[2 * i + 1];
         row = a.trow[i];
         cnt = min(a.list_cnt[i], a.cap);
-        cur = lp4[0];
+        q0 = fetch(q);
+        q1 = fetch(q + NL);
+        q2 = fetch(q + 2 * NL);
+        q3 = fetch(q + 3 * NL);
     }
+    const float4 O = a.pin[2 * mid];
+    bool far = false;
     {
-        // all slot ids first, then all positions, so the loads overlap
-        constexpr int PER = SM / TILE;
+        constexpr int PER = SM / 256;
         int ids[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int s = t + u * TILE;
-            ids[u] = s < S ? st[s] : -1;
+            const int sl = t + u * 256;
+            ids[u] = sl < S ? st[sl] : -1;
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             if (ids[u] >= 0) {
-                const int s = t + u * TILE;
-                sh[2 * s] = a.pin[2 * ids[u]];
-                sh[2 * s + 1] = a.pin[2 * ids[u] + 1];
+                const int sl = t + u * 256;
+                float4 rh, rl;
+                tile_frame(a.pin[2 * ids[u]], a.pin[2 * ids[u] + 1], O, rh, rl);
+                far |= !(fmaxf(fabsf(rh.x), fmaxf(fabsf(rh.y), fabsf(rh.z))) < NARROW_TILE);
+                rh_s[sl] = rh;
+                rl_s[sl] = rl;
             }
         }
         if (t == 0) {
-            sh[2 * SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
-            sh[2 * SM + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rh_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+            rl_s[SM] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
     }
-    __syncthreads();
-    if (!act)
-        return;
+    float4 rh0, rl0;
+    tile_frame(hi0, lo0, O, rh0, rl0);
+    if (act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE))
+        far = true;
+    const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
     const PairConsts k = pair_consts(a.c);
-    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     Acc A;
     bool broken = false;
-    const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
-    // bonds and natives, four entries per block
-    for (int e0 = 0; e0 < ntop; e0 += 4) {
-        uint2 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            v[u] = e0 + u < ntop ? tp[(size_t)(e0 + u) * TILE] : make_uint2((unsigned)SM, __float_as_uint(1.0f));
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u, sj = (int)v[u].x;
-            const float r0 = __uint_as_float(v[u].y);
+    if (act) {
+        // bonded and native partners, entries e = q mod NL
+        const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
+        const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
+        for (int e = q; e < ntop; e += NL) {
+            const uint2 v = tp[(size_t)e * TILE];
+            const int sj = (int)v.x;
+            const float4 hj = rh_s[sj], lj = rl_s[sj];
+            const float3 d = make_float3((rh0.x - hj.x) + (rl0.x - lj.x), (rh0.y - hj.y) + (rl0.y - lj.y),
+                                         (rh0.z - hj.z) + (rl0.z - lj.z));
             if (e < nb)
-                add_fene(A, hi0, lo0, sh[2 * sj], sh[2 * sj + 1], r0, k, ENERGY, broken);
-            else if (e < ntop)
-                add_native(A, hi0, lo0, sh[2 * sj], sh[2 * sj + 1], r0, k, ENERGY);
+                add_fene_d(A, d, __uint_as_float(v.y), k, ENERGY, broken);
+            else
+                add_native_d(A, d, __uint_as_float(v.y), k, ENERGY);
+        }
+        // list partners: chunks of 4 slots, four chunks in flight; loads are
+        // unconditional (clamped into the row's region) so that no branch
+        // sits between them
+        const int nch = (cnt + 3) >> 2;
+        const int mine = nch > q ? (nch - q + NL - 1) / NL : 0;
+        if (!wide) {
+            auto chunk = [&](const uint2 &w) {
+                float4 pj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    pj[u] = rh_s[((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    add_repulsive_d(A, make_float3(rh0.x - pj[u].x, rh0.y - pj[u].y, rh0.z - pj[u].z), k,
+                                    ENERGY);
+            };
+            int m = 0;
+            for (; m + 4 <= mine; m += 4) {
+                const int c = q + m * NL;
+                chunk(q0);
+                q0 = fetch(c + 4 * NL);
+                chunk(q1);
+                q1 = fetch(c + 5 * NL);
+                chunk(q2);
+                q2 = fetch(c + 6 * NL);
+                chunk(q3);
+                q3 = fetch(c + 7 * NL);
+            }
+            if (m < mine)
+                chunk(q0);
+            if (m + 1 < mine)
+                chunk(q1);
+            if (m + 2 < mine)
+                chunk(q2);
+        } else {
+            auto chunk = [&](const uint2 &w) {
+                float4 ph[4], pl[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const unsigned sj = ((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu;
+                    ph[u] = rh_s[sj];
+                    pl[u] = rl_s[sj];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    add_repulsive_d(A,
+                                    make_float3((rh0.x - ph[u].x) + (rl0.x - pl[u].x),
+                                                (rh0.y - ph[u].y) + (rl0.y - pl[u].y),
+                                                (rh0.z - ph[u].z) + (rl0.z - pl[u].z)),
+                                    k, ENERGY);
+            };
+            int m = 0;
+            for (; m + 4 <= mine; m += 4) {
+                const int c = q + m * NL;
+                chunk(q0);
+                q0 = fetch(c + 4 * NL);
+                chunk(q1);
+                q1 = fetch(c + 5 * NL);
+                chunk(q2);
+                q2 = fetch(c + 6 * NL);
+                chunk(q3);
+                q3 = fetch(c + 7 * NL);
+            }
+            if (m < mine)
+                chunk(q0);
+            if (m + 1 < mine)
+                chunk(q1);
+            if (m + 2 < mine)
+                chunk(q2);
+        }
+        if (broken)
+            atomicOr(a.err, ERR_FENE);
+    }
+    if (NL > 1) {
+        // parts 1..NL-1 hand their sums to part 0
+        if (q > 0) {
+            float *rf = red_f + (q - 1) * 3 * TILE;
+            rf[rho] = A.fx;
+            rf[TILE + rho] = A.fy;
+            rf[2 * TILE + rho] = A.fz;
+            if (ENERGY) {
+                double *re = red_e + (q - 1) * 4 * TILE;
+                re[rho] = A.e_b;
+                re[TILE + rho] = A.e_n;
+                re[2 * TILE + rho] = A.e_r;
+                re[3 * TILE + rho] = A.vir;
+            }
+        }
+        __syncthreads();
+        if (q > 0)
+            return;
+#pragma unroll
+        for (int p = 0; p < NL - 1; ++p) {
+            const float *rf = red_f + p * 3 * TILE;
+            A.fx += rf[rho];
+            A.fy += rf[TILE + rho];
+            A.fz += rf[2 * TILE + rho];
+            if (ENERGY) {
+                const double *re = red_e + p * 4 * TILE;
+                A.e_b += re[rho];
+                A.e_n += re[TILE + rho];
+                A.e_r += re[2 * TILE + rho];
+                A.vir += re[3 * TILE + rho];
+            }
         }
     }
-    // list partners: chunks of 8 slots with four chunks in flight
-    const int nch = (cnt + 7) >> 3;
-    auto chunk8 = [&](const uint4 &q) {
-        const unsigned w[4] = {q.x, q.y, q.z, q.w};
-        float4 ph[8], pl[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {  // all 16 LDS reads before any use
-            const int sj = (int)((w[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
-            ph[u] = sh[2 * sj];
-            pl[u] = sh[2 * sj + 1];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            add_repulsive(A, hi0, lo0, ph[u], pl[u], k, ENERGY);
-    };
-    // unconditional loads (a branch around them would force a full wait);
-    // chunks past the row are clamped into the row's region and never used
-    const int last_ch = (a.cap >> 3) - 1;
-    auto fetch = [&](int ch) -> uint4 { return lp4[(size_t)min(ch, last_ch) * TILE]; };
-    uint4 q0 = cur, q1 = fetch(1), q2 = fetch(2), q3 = fetch(3);
-    int ch = 0;
-    for (; ch + 4 <= nch; ch += 4) {  // whole groups: no branches between the loads
-        chunk8(q0);
-        q0 = fetch(ch + 4);
-        chunk8(q1);
-        q1 = fetch(ch + 5);
-        chunk8(q2);
-        q2 = fetch(ch + 6);
-        chunk8(q3);
-        q3 = fetch(ch + 7);
-    }
-    if (ch < nch)
-        chunk8(q0);
-    if (ch + 1 < nch)
-        chunk8(q1);
-    if (ch + 2 < nch)
-        chunk8(q2);
+    if (!act)
+        return;
+    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     double e_x = 0.0, f_rep = 0.0;
     add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
                  a.tip, ENERGY, a.err);
-    if (broken)
-        atomicOr(a.err, ERR_FENE);
     if (ENERGY) {
         double *er = a.res_energy + (size_t)i * RES_E;
         // each internal pair appears in both partners' rows
@@ -1049,8 +1304,8 @@ __global__ void k_set_step(long long *dst, long long v)
 inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per); }
 
 template <int TILE>
-void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, float rc2, float edge,
-                  float cull2, hipStream_t s)
+void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, float rc2, int multi,
+                  hipStream_t s)
 {
     BuildArgs a{};
     a.pos = b.pos[cur];
@@ -1070,11 +1325,10 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
     a.err = b.err;
     a.g = g;
     a.rc2 = rc2;
-    a.edge = edge;
-    a.cull2 = cull2;
     a.n = n;
     a.cap = cap;
-    hipLaunchKernelGGL(k_tile_build<TILE>, dim3(blocks_for(n, TILE)), dim3(TILE), 0, s, a);
+    a.multi = multi;
+    hipLaunchKernelGGL(k_tile_build<TILE>, dim3(blocks_for(n, TILE)), dim3(256), 0, s, a);
 }
 
 template <int TILE, bool ENERGY, int MODE>
@@ -1083,7 +1337,7 @@ void tile_step(const TileArgs &a, hipStream_t s)
     TileArgs x = a;
     x.n_tiles = blocks_for(a.n, TILE);
     const int blocks = ((x.n_tiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_tile_step<TILE, ENERGY, MODE>), dim3(blocks), dim3(TILE), 0, s, x);
+    hipLaunchKernelGGL((k_tile_step<TILE, ENERGY, MODE>), dim3(blocks), dim3(256), 0, s, x);
 }
 
 template <bool ENERGY, int MODE>
@@ -1099,20 +1353,16 @@ void tile_dispatch(int tile, const TileArgs &a, hipStream_t s)
 }  // namespace
 
 void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int tile, const GridDev &g, float rc2,
-                    float edge, hipStream_t s, bool advance_step_base, int list_every)
+                    int multi, hipStream_t s, bool advance_step_base, int list_every)
 {
     hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells);
     hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, WG)), dim3(WG), 0, s, b.pos[cur], n, g, b.traj_cell,
                        b.cell_count, b.cells, b.cell_of, b.err,
                        advance_step_base ? b.step_base : nullptr, b.step_next, list_every);
-    // a cell whose box is farther than the cutoff plus a rounding margin
-    // holds no partner
-    const float rc = sqrtf(rc2) + 0.1f;
-    const float cull2 = rc * rc;
     switch (tile) {
-    case 64: rebuild_tile<64>(b, cur, n, cap, g, rc2, edge, cull2, s); break;
-    case 128: rebuild_tile<128>(b, cur, n, cap, g, rc2, edge, cull2, s); break;
-    default: rebuild_tile<256>(b, cur, n, cap, g, rc2, edge, cull2, s); break;
+    case 64: rebuild_tile<64>(b, cur, n, cap, g, rc2, multi, s); break;
+    case 128: rebuild_tile<128>(b, cur, n, cap, g, rc2, multi, s); break;
+    default: rebuild_tile<256>(b, cur, n, cap, g, rc2, multi, s); break;
     }
 }
 
