@@ -235,8 +235,9 @@ sop_status sop_get_step(const sop_ctx *ctx, int64_t *step);
 sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
 
 /*
- * Same as sop_step, launched kernel by kernel with HIP events on the
- * context's stream around each kernel group; waits after every launch.
+ * Same as sop_step, launched kernel by kernel (no graph), back to back,
+ * with a pair of HIP events on the context's stream around each kernel
+ * group; waits once, after the last launch.
  * Plain schedule: ms_out[0] = mean duration of the fused step kernel,
  * ms_out[1] = mean duration of one list rebuild (all its kernels),
  * ms_out[2] = 1.  Batched schedule: ms_out[0] = mean duration of one

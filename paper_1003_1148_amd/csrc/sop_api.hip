@@ -1159,45 +1159,62 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
             HIP_TRY(c, hipGetLastError());
         return out;
     }
-    double sum[3] = {0, 0, 0};
-    long long cnt[3] = {0, 0, 0};
+    // back-to-back launches with an event pair around each kernel group;
+    // one synchronisation at the end
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    std::vector<hipEvent_t> evs;
+    std::vector<int> kind;  // per event pair: 0 = step, 1 = rebuild
+    auto pair = [&](int k) -> sop_status {
+        for (int u = 0; u < 2; ++u) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            evs.push_back(e);
+        }
+        kind.push_back(k);
+        return SOP_OK;
+    };
     sop_status out = SOP_OK;
     for (long long q = 0; q < n_steps && out == SOP_OK; ++q) {
-        float ms = 0.0f;
-        bool rebuilt = false;
         if (!c->list_valid || c->step % L == 0) {
-            (void)hipEventRecord(ev[0], c->stream);
+            out = pair(1);
+            if (out != SOP_OK)
+                break;
+            (void)hipEventRecord(evs[evs.size() - 2], c->stream);
             rebuild(c, c->stream, false);
-            (void)hipEventRecord(ev[1], c->stream);
+            (void)hipEventRecord(evs.back(), c->stream);
             c->list_valid = true;
-            rebuilt = true;
         }
         const bool en = E > 0 && c->step % E == 0;
-        (void)hipEventRecord(ev[2], c->stream);
+        out = pair(0);
+        if (out != SOP_OK)
+            break;
+        (void)hipEventRecord(evs[evs.size() - 2], c->stream);
         launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                     c->pulls.empty() ? 0 : 1, en, 0, nullptr, c->step, c->stream);
-        (void)hipEventRecord(ev[3], c->stream);
-        if (en)
+        (void)hipEventRecord(evs.back(), c->stream);
+        if (en) {
             launch_reduce_energy(c->b, c->n_traj, c->stream);
-        hipError_t e = hipEventSynchronize(ev[3]);
-        if (e != hipSuccess) {
-            out = hip_fail(c, e, "hipEventSynchronize");
-            break;
-        }
-        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) {
-            sum[0] += ms;
-            cnt[0]++;
-        }
-        if (rebuilt && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) {
-            sum[1] += ms;
-            cnt[1]++;
-        }
-        if (en)
             c->energy_step = c->step;
+        }
         c->cur ^= 1;
         ++c->step;
     }
-    for (auto &e : ev)
+    double sum[2] = {0, 0};
+    long long cnt[2] = {0, 0};
+    if (out == SOP_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess)
+            out = hip_fail(c, e, "hipStreamSynchronize");
+    }
+    for (size_t k = 0; out == SOP_OK && k < kind.size(); ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]) == hipSuccess) {
+            sum[kind[k]] += ms;
+            cnt[kind[k]]++;
+        }
+    }
+    for (auto &e : evs)
         (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k)
         ms_out[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;

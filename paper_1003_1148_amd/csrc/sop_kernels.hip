@@ -298,23 +298,28 @@ __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep,
     }
 }
 
-// Noise (Section III.C) and the first-order update (Eq. 2 / Algorithm 7)
-// with compensated positions: (hi, lo) <- TwoSum(hi, delta + lo) per axis.
-__device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Acc &A, long long step,
-                                                unsigned stream, const StepConsts &c, unsigned *err)
+// Philox words of one residue and step: counter (index in the trajectory,
+// stream id, step), key = seed.
+__device__ __forceinline__ uint4 noise_words(unsigned tag, unsigned stream, long long step, const StepConsts &c)
 {
-    const unsigned tag = __float_as_uint(hi.w);
-    if (tag >> 31)
+    return philox10(make_uint4(tag & 0x7fffffffu, stream, (unsigned)step,
+                               (unsigned)((unsigned long long)step >> 32)),
+                    c.key0, c.key1);
+}
+
+// First-order update with the Gaussian components g:
+// (hi, lo) <- TwoSum(hi, f h/zeta + g sqrt(2 kB T h/zeta) + lo) per axis.
+__device__ __forceinline__ void update_with_noise(float4 &hi, float4 &lo, const Acc &A, const float g[3],
+                                                  const StepConsts &c, unsigned *err)
+{
+    if (__float_as_uint(hi.w) >> 31)
         return;  // fixed residue
-    const uint4 w = philox10(make_uint4(tag & 0x7fffffffu, stream, (unsigned)step,
-                                        (unsigned)((unsigned long long)step >> 32)),
-                             c.key0, c.key1);
     float nh[3], nl[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const float f = ax == 0 ? A.fx : (ax == 1 ? A.fy : A.fz);
         const float h0 = comp(hi, ax), l0 = comp(lo, ax);
-        const float delta = c.c_drift * f + c.c_noise * gaussian_axis(w, ax);
+        const float delta = c.c_drift * f + c.c_noise * g[ax];
         const float y = delta + l0;
         const float t = h0 + y;
         const float bp = t - h0;
@@ -327,6 +332,19 @@ __device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Ac
         atomicOr(err, ERR_NONFINITE);
     hi = make_float4(nh[0], nh[1], nh[2], hi.w);
     lo = make_float4(nl[0], nl[1], nl[2], lo.w);
+}
+
+// Noise (Section III.C) and the first-order update (Eq. 2 / Algorithm 7)
+// with compensated positions.
+__device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Acc &A, long long step,
+                                                unsigned stream, const StepConsts &c, unsigned *err)
+{
+    const unsigned tag = __float_as_uint(hi.w);
+    if (tag >> 31)
+        return;  // fixed residue
+    const uint4 w = noise_words(tag, stream, step, c);
+    const float g[3] = {gaussian_axis(w, 0), gaussian_axis(w, 1), gaussian_axis(w, 2)};
+    update_with_noise(hi, lo, A, g, c, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,10 +361,11 @@ constexpr int stage_max() { return TILE >= 256 ? 2048 : 1024; }
 constexpr int CAND_WIN = 1024;
 // Distinct cells around one tile, and the bits of its open-addressing table.
 template <int TILE>
-constexpr int cells_max() { return TILE >= 256 ? 512 : 1024; }
+constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640); }
 template <int TILE>
-constexpr int chash_bits() { return TILE >= 256 ? 10 : 11; }
+constexpr int chash_bits() { return TILE == 128 ? 11 : 10; }
 constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
+constexpr int TREG = 16;        // bonded/native entries per residue kept in registers
 
 struct BuildArgs {
     const float4 *pos;
@@ -366,7 +385,7 @@ struct BuildArgs {
     unsigned *err;
     GridDev g;
     float rc2;
-    int n, cap, multi;
+    int n, cap;
 };
 
 // Exclusive prefix sum over the NT lanes of a workgroup (all lanes call it).
@@ -388,17 +407,21 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *part, int &total
     return r;
 }
 
-__device__ __forceinline__ int wrap_int(int v, int n)
-{
-    const int r = v % n;
-    return r < 0 ? r + n : r;
-}
-
-// Along one axis of the wrapped grid, cell c is u's own or an adjacent one.
+// Along one axis of the wrapped grid (n >= 3 cells), cell c is u's own or an
+// adjacent one.
 __device__ __forceinline__ bool adjacent_cell(int c, int u, int n)
 {
-    const int d = wrap_int(c - u, n);
-    return d <= 1 || d == n - 1;
+    const int d = c - u;
+    return (unsigned)(d + 1) <= 2u || d == n - 1 || d == 1 - n;
+}
+
+// OR of a 32-bit value over the 64 lanes of a wave.
+__device__ __forceinline__ unsigned wave_or(unsigned v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v |= (unsigned)__shfl_xor((int)v, off, 64);
+    return v;
 }
 
 // Bonded/native entry codes while a tile is built.
@@ -407,22 +430,25 @@ constexpr unsigned CODE_WINDOW = 0x80000000u;   // | candidate index in the curr
 constexpr unsigned CODE_EXTRA = 0x40000000u;    // | index among the extra slots
 
 // One workgroup of 256 lanes per tile of TILE consecutive residues; lane t
-// serves residue t % TILE and part t / TILE of its work.
+// serves residue t % TILE and part q = t / TILE of its work (NLB = 256/TILE
+// parts).
 //  1. The cells around the tile's residues (each residue's own and adjacent
 //     cells) go into an LDS hash table and are sorted by cell index; their
 //     residues, sorted by (cell, residue index), are the tile's candidates.
 //  2. Per window of whole cells (at most CAND_WIN candidates, usually one
 //     window): candidates go to LDS; each residue is tested against them 32
 //     at a time with the single-precision predicate r < r_list of
-//     Algorithm 3, one bit per candidate (groups of 32 outside every
-//     neighbourhood of a wave are skipped); self, bonded and native partners
-//     are cleared; candidates some row or entry uses get the next staging
-//     slots in sorted order, and rows are appended as slots.
+//     Algorithm 3, one bit per candidate, part q taking a contiguous range
+//     of the 32-candidate words (words outside every neighbourhood of a wave
+//     are skipped).  Self, bonded and native partners are cleared; the
+//     candidates some row or entry uses get the next staging slots in sorted
+//     order; each part appends its words' partners to the row at the offset
+//     the lower parts leave.
 //  3. Bonded/native partners outside the cells take extra slots at the end.
 // A row lists its partners in (cell, residue index) order whatever the tile
 // size or the order in which residues were binned.
-template <int TILE>
-__global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
+template <int TILE, bool MULTI>
+__global__ __launch_bounds__(256, 2) void k_tile_build(BuildArgs a)
 {
     constexpr int NT = 256, NLB = NT / TILE;
     constexpr int SM = stage_max<TILE>();
@@ -431,19 +457,19 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
     constexpr int CELLS_MAX = cells_max<TILE>();
     constexpr int CHASH_BITS = chash_bits<TILE>();
     constexpr int CHASH = 1 << CHASH_BITS;
-    static_assert(NW * TILE >= CM, "arrival ids alias the row bits");
+    static_assert(NW * TILE >= CM && NW * TILE >= CELLS_MAX, "arrival data alias the row bits");
     __shared__ float4 cand[CM];           // the window's candidates, sorted
-    __shared__ unsigned bits[NW * TILE];  // row bits, word-major; first the arrival ids
+    __shared__ unsigned bits[NW * TILE];  // row bits, word-major; first arrival cells / ids
     __shared__ int hkey[CHASH];
     __shared__ short hval[CHASH];         // cell number: arrival, then sorted
-    __shared__ int ccell[CELLS_MAX];      // arrival order
     __shared__ short rank_of[CELLS_MAX];
-    __shared__ int scell[CELLS_MAX];      // sorted: cell index and its packed coordinates
-    __shared__ unsigned sxyz[CELLS_MAX];
+    __shared__ unsigned sxyz[CELLS_MAX];  // sorted cells: packed coordinates
     __shared__ int cbase[CELLS_MAX + 1];
     __shared__ unsigned used[NW];
     __shared__ int wbase[NW];
     __shared__ short wlo[NW], whi[NW];    // sorted cells spanned by each word
+    __shared__ short pcnt[NT];            // partners of (part, residue) in this window
+    __shared__ int rowbase[TILE];         // partners of the residue in earlier windows
     __shared__ int extra[EXTRA_MAX];
     __shared__ int part[NT];
     __shared__ int n_cu, n_extra, bad_cells, n_used_w;
@@ -452,10 +478,13 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
     const int rho = t % TILE, q = t / TILE;
     const int i = tile * TILE + rho;
     const bool act = i < a.n;
-    const bool lead = act && q == 0;  // owns the residue's row and entries
+    const bool lead = act && q == 0;  // writes the residue's count and padding
     const GridDev g = a.g;
+    int *ccell = reinterpret_cast<int *>(bits);  // arrival order of the cells
     for (int h = t; h < CHASH; h += NT)
         hkey[h] = -1;
+    if (t < TILE)
+        rowbase[t] = 0;
     if (t == 0) {
         n_cu = 0;
         n_extra = 0;
@@ -478,17 +507,42 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
     };
 
     // ---- 1. cells around the tile ----
+    // independent loads first; this part's bonded/native entries (u = q mod
+    // NLB, the first TREG kept in registers) and their partners' cells are
+    // needed only in step 2
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-    int ux = 0, uy = 0, uz = 0;  // own wrapped cell coordinates
+    int own = 0;
+    int2 row = make_int2(0, 0);
     if (act) {
         p = a.pos[2 * i];
-        const int4 off = a.traj_cell[__float_as_int(a.pos[2 * i + 1].w)];
-        ux = wrap_cell(p.x, g.inv_cell, off.x, g.gx);
-        uy = wrap_cell(p.y, g.inv_cell, off.y, g.gy);
-        uz = wrap_cell(p.z, g.inv_cell, off.z, g.gz);
+        own = a.cell_of[i];
+        row = a.trow[i];
+    }
+    const int ntop = (row.y & 4095) + (row.y >> 12);
+    // entry e = v * NLB + q of the first TREG is this part's v-th
+    constexpr int TPP = TREG / NLB;
+    int tj[TPP], tm[TPP];
+    unsigned tr0[TPP], tcode[TPP];
+#pragma unroll
+    for (int v = 0; v < TPP; ++v) {
+        const int e = v * NLB + q;
+        const float2 te = e < ntop ? a.tent[row.x + e] : make_float2(0.0f, 0.0f);
+        tj[v] = __float_as_int(te.x);
+        tr0[v] = __float_as_uint(te.y);
+        tcode[v] = CODE_NONE;
+    }
+#pragma unroll
+    for (int v = 0; v < TPP; ++v)
+        tm[v] = v * NLB + q < ntop ? a.cell_of[tj[v]] : -1;
+    const int tlo = (MULTI && act) ? a.traj_lo[i] : 0, thi = (MULTI && act) ? a.traj_hi[i] : 0;
+    // own wrapped cell coordinates
+    const int ux = own % g.gx, uy = (own / g.gx) % g.gy, uz = own / (g.gx * g.gy);
+    if (act) {
         for (int d = q; d < 27; d += NLB) {
-            const int cid = wrap_int(ux + d % 3 - 1, g.gx) +
-                            g.gx * (wrap_int(uy + (d / 3) % 3 - 1, g.gy) + g.gy * wrap_int(uz + d / 9 - 1, g.gz));
+            const int cx = ux + d % 3 - 1, cy = uy + (d / 3) % 3 - 1, cz = uz + d / 9 - 1;
+            const int cid = (cx < 0 ? cx + g.gx : (cx >= g.gx ? cx - g.gx : cx)) +
+                            g.gx * ((cy < 0 ? cy + g.gy : (cy >= g.gy ? cy - g.gy : cy)) +
+                                    g.gy * (cz < 0 ? cz + g.gz : (cz >= g.gz ? cz - g.gz : cz)));
             int h = hslot(cid);
             for (int probe = 0; probe < CHASH; ++probe) {
                 const int prev = atomicCAS(&hkey[h], -1, cid);
@@ -511,8 +565,6 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
         }
     }
     __syncthreads();
-    const int2 row = lead ? a.trow[i] : make_int2(0, 0);
-    const int ntop = (row.y & 4095) + (row.y >> 12);
     uint2 *trw = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
     auto fail_tile = [&]() {
         // report; leave the tile pointing at the empty slot so steps stay in bounds
@@ -534,6 +586,7 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
     // coordinates packed in bx + by + bz <= 32 bits (the grid has at most 2^21 cells)
     const int bx = 32 - __clz(g.gx), by = 32 - __clz(g.gy);
     const unsigned mx = (1u << bx) - 1u, my = (1u << by) - 1u;
+    auto cell_id = [&](unsigned v) { return (int)(v & mx) + g.gx * ((int)((v >> bx) & my) + g.gy * (int)(v >> (bx + by))); };
     // sort the cells by index (rank by counting; indices are distinct)
     for (int m = t; m < NC; m += NT) {
         const int c = ccell[m];
@@ -541,7 +594,6 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
         for (int m2 = 0; m2 < NC; ++m2)
             r += ccell[m2] < c;
         rank_of[m] = (short)r;
-        scell[r] = c;
         sxyz[r] = (unsigned)(c % g.gx) | ((unsigned)((c / g.gx) % g.gy) << bx) |
                   ((unsigned)(c / (g.gx * g.gy)) << (bx + by));
     }
@@ -554,21 +606,31 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
         const int cper = (NC + NT - 1) / NT;
         const int m0 = min(NC, t * cper), m1 = min(NC, m0 + cper);
         int csum = 0;
-        for (int m = m0; m < m1; ++m)
-            csum += min(a.count[scell[m]], CELL_CAP);
+        for (int m = m0; m < m1; ++m) {
+            const int c = min(a.count[cell_id(sxyz[m])], CELL_CAP);
+            cbase[m] = c;
+            csum += c;
+        }
         int M = 0;
         int cb = block_exclusive_scan<NT>(csum, part, M);
         for (int m = m0; m < m1; ++m) {
+            const int c = cbase[m];
             cbase[m] = cb;
-            cb += min(a.count[scell[m]], CELL_CAP);
+            cb += c;
         }
         if (t == 0)
             cbase[NC] = M;
     }
+    // this part's entries beyond TREG live in the topology output meanwhile
     if (lead)
-        for (int e = 0; e < ntop; ++e)
+        for (int e = TREG; e < ntop; ++e)
             trw[(size_t)e * TILE] = make_uint2(CODE_NONE, __float_as_uint(a.tent[row.x + e].y));
     __syncthreads();
+    // partners' cells -> sorted cell numbers (or -1 outside the tile's cells)
+#pragma unroll
+    for (int v = 0; v < TPP; ++v)
+        tm[v] = tm[v] >= 0 ? lookup(tm[v]) : -1;
+    const int own_m = lead ? lookup(own) : -1;
     auto segment_of = [&](int ci) {  // last m with cbase[m] <= ci
         int lo = 0, hi = NC;
         while (hi - lo > 1) {
@@ -582,12 +644,12 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
     };
 
     // ---- 2. windows of whole cells ----
-    const unsigned pad = (unsigned)SM | ((unsigned)SM << 16);
-    uint2 *lrow = reinterpret_cast<uint2 *>(a.list16) + (size_t)tile * (a.cap >> 2) * TILE + rho;
     int *st = a.stage + (size_t)tile * SM;
-    int cnt = 0;
-    uint2 acc = make_uint2(pad, pad);
-    const int tlo = act ? a.traj_lo[i] : 0, thi = act ? a.traj_hi[i] : 0;
+    unsigned short *lrow = a.list16 + (size_t)tile * a.cap * TILE + (size_t)rho * 4;
+    auto row_store = [&](int k, unsigned short sl) {  // entry k of the residue's row
+        if (k < a.cap)
+            lrow[(size_t)(k >> 2) * (4 * TILE) + (k & 3)] = sl;
+    };
     int slot_base = 0;
     int *aid = reinterpret_cast<int *>(bits);
     for (int mA = 0; mA < NC;) {
@@ -603,21 +665,32 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
             }
         }
         const int base = cbase[mA], Mw = cbase[mB] - base;
-        for (int ci = t; ci < Mw; ci += NT) {
-            const int m = segment_of(base + ci);
-            aid[ci] = __float_as_int(a.cells[(size_t)scell[m] * CELL_CAP + (base + ci - cbase[m])].w);
+        constexpr int CPT = CM / NT;  // candidates per lane
+        float4 cv[CPT];
+        int cm[CPT];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int ci = t + u * NT;
+            cm[u] = ci < Mw ? segment_of(base + ci) : 0;
+            cv[u] = ci < Mw ? a.cells[(size_t)cell_id(sxyz[cm[u]]) * CELL_CAP + (base + ci - cbase[cm[u]])]
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ci < Mw)
+                aid[ci] = __float_as_int(cv[u].w);
         }
         for (int w = t; w < NW; w += NT)
             used[w] = 0u;
         __syncthreads();
-        for (int ci = t; ci < Mw; ci += NT) {
-            const int m = segment_of(base + ci);
-            const int id = aid[ci];
-            const int k0 = cbase[m] - base, k1 = cbase[m + 1] - base;
-            int r = k0;
-            for (int k = k0; k < k1; ++k)
-                r += aid[k] < id;
-            cand[r] = a.cells[(size_t)scell[m] * CELL_CAP + (base + ci - cbase[m])];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int ci = t + u * NT;
+            if (ci < Mw) {
+                const int id = __float_as_int(cv[u].w);
+                const int k0 = cbase[cm[u]] - base, k1 = cbase[cm[u] + 1] - base;
+                int r = k0;
+                for (int k = k0; k < k1; ++k)
+                    r += aid[k] < id;
+                cand[r] = cv[u];
+            }
         }
         const int NWm = (Mw + 31) >> 5;
         for (int w = t; w < NWm; w += NT) {
@@ -625,8 +698,10 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
             whi[w] = (short)segment_of(base + min(32 * w + 31, Mw - 1));
         }
         __syncthreads();
-        // row bits; part q takes words w = q mod NLB (uniform over a wave)
-        for (int w = q; w < NWm; w += NLB) {
+        // row bits; part q takes words [w0, w1) (uniform over a wave)
+        const int wpp = (NWm + NLB - 1) / NLB;
+        const int w0 = min(NWm, q * wpp), w1 = min(NWm, w0 + wpp);
+        for (int w = w0; w < w1; ++w) {
             bool reach = false;
             if (act)
                 for (int m = wlo[w]; m <= whi[w]; ++m) {
@@ -641,19 +716,23 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
                 for (int k = 0; k < 32; ++k) {
                     const int r = 32 * w + k;
                     const float4 c = cand[r];
-                    const int j = __float_as_int(c.w);
                     bool pass = act && r < Mw && within_cutoff(p, c, a.rc2);
-                    if (a.multi)
+                    if (MULTI) {
+                        const int j = __float_as_int(c.w);
                         pass = pass && j >= tlo && j < thi;
+                    }
                     word |= pass ? (1u << k) : 0u;
                 }
+                const unsigned u = wave_or(word);
+                if ((t & 63) == 0 && u)
+                    atomicOr(&used[w], u);
             }
             bits[w * TILE + rho] = word;
         }
         __syncthreads();
         // self, bonded and native partners in this window: clear their bits
-        auto find = [&](int j) -> int {  // window candidate of residue j, or -1
-            const int m = lookup(a.cell_of[j]);
+        // (their candidates are marked used: a partner's slot is needed anyway)
+        auto find = [&](int j, int m) -> int {  // window candidate of residue j in sorted cell m, or -1
             if (m < mA || m >= mB)
                 return -1;
             int lo = cbase[m] - base, hi = cbase[m + 1] - base;
@@ -667,30 +746,38 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
             }
             return (lo < end && __float_as_int(cand[lo].w) == j) ? lo : -1;
         };
+        auto take = [&](int r) {
+            atomicAnd(&bits[(r >> 5) * TILE + rho], ~(1u << (r & 31)));
+            atomicOr(&used[r >> 5], 1u << (r & 31));
+        };
         if (lead) {
-            const int rs = find(i);
+            const int rs = find(i, own_m);
             if (rs >= 0)
-                bits[(rs >> 5) * TILE + rho] &= ~(1u << (rs & 31));
-            for (int e = 0; e < ntop; ++e) {
+                atomicAnd(&bits[(rs >> 5) * TILE + rho], ~(1u << (rs & 31)));
+            for (int e = TREG; e < ntop; ++e) {
                 if (trw[(size_t)e * TILE].x != CODE_NONE)
                     continue;
-                const int r = find(__float_as_int(a.tent[row.x + e].x));
+                const int j = __float_as_int(a.tent[row.x + e].x);
+                const int r = find(j, lookup(a.cell_of[j]));
                 if (r >= 0) {
-                    bits[(r >> 5) * TILE + rho] &= ~(1u << (r & 31));
-                    atomicOr(&used[r >> 5], 1u << (r & 31));
+                    take(r);
                     trw[(size_t)e * TILE].x = CODE_WINDOW | (unsigned)r;
                 }
             }
         }
-        __syncthreads();
-        for (int w = t; w < NWm; w += NT) {
-            unsigned u = 0u;
-            for (int l = 0; l < TILE; ++l)
-                u |= bits[w * TILE + l];
-            used[w] |= u;  // this lane alone writes word w now
+#pragma unroll
+        for (int v = 0; v < TPP; ++v) {
+            if (v * NLB + q < ntop && tcode[v] == CODE_NONE) {
+                const int r = find(tj[v], tm[v]);
+                if (r >= 0) {
+                    take(r);
+                    tcode[v] = CODE_WINDOW | (unsigned)r;
+                }
+            }
         }
         __syncthreads();
-        // slots of the used candidates: prefix over the window's words (<= 32)
+        // slots of the used candidates: prefix over the window's words (<= 32);
+        // row counts of each part
         if (t < 64) {
             const int c = t < NWm ? __popc(used[t]) : 0;
             int v = c;
@@ -703,6 +790,12 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
                 wbase[t] = slot_base + v - c;
             if (t == 63)
                 n_used_w = v;
+        }
+        {
+            int c = 0;
+            for (int w = w0; w < w1; ++w)
+                c += __popc(bits[w * TILE + rho]);
+            pcnt[t] = (short)c;
         }
         __syncthreads();
         const int nu = n_used_w;
@@ -719,52 +812,66 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
                 st[sl++] = __float_as_int(cand[32 * t + b].w);
             }
         }
-        if (lead) {
-            // append this window's partners: chunks of 4 slots, the last one
-            // padded with the empty slot SM (far away: its term is exactly 0)
-            for (int w = 0; w < NWm; ++w) {
+        if (act) {
+            // this part's partners, after those of the lower parts
+            int k = rowbase[rho];
+            for (int pq = 0; pq < q; ++pq)
+                k += pcnt[pq * TILE + rho];
+            for (int w = w0; w < w1; ++w) {
                 unsigned b = bits[w * TILE + rho];
+                const unsigned uw = used[w];
+                const int wb = wbase[w];
                 while (b) {
-                    const int k = __ffs(b) - 1;
+                    const int kb = __ffs(b) - 1;
                     b &= b - 1u;
-                    const unsigned sl = (unsigned)(wbase[w] + __popc(used[w] & ((1u << k) - 1u)));
-                    if (cnt < a.cap) {
-                        const int pos = cnt & 3, sh = (pos & 1) * 16;
-                        if (pos < 2)
-                            acc.x = (acc.x & ~(0xffffu << sh)) | (sl << sh);
-                        else
-                            acc.y = (acc.y & ~(0xffffu << sh)) | (sl << sh);
-                        if (pos == 3) {
-                            lrow[(size_t)(cnt >> 2) * TILE] = acc;
-                            acc = make_uint2(pad, pad);
-                        }
-                    }
-                    ++cnt;
+                    row_store(k++, (unsigned short)(wb + __popc(uw & ((1u << kb) - 1u))));
                 }
             }
-            for (int e = 0; e < ntop; ++e) {
-                const unsigned v = trw[(size_t)e * TILE].x;
-                if (v != CODE_NONE && (v & CODE_WINDOW)) {
-                    const int r = (int)(v & ~CODE_WINDOW), w = r >> 5;
-                    trw[(size_t)e * TILE].x =
-                        (unsigned)(wbase[w] + __popc(used[w] & ((1u << (r & 31)) - 1u)));
+            auto slot_of = [&](unsigned v) {
+                const int r = (int)(v & ~CODE_WINDOW), w = r >> 5;
+                return (unsigned)(wbase[w] + __popc(used[w] & ((1u << (r & 31)) - 1u)));
+            };
+#pragma unroll
+            for (int v = 0; v < TPP; ++v)
+                if (tcode[v] != CODE_NONE && (tcode[v] & CODE_WINDOW))
+                    tcode[v] = slot_of(tcode[v]);
+            if (lead)
+                for (int e = TREG; e < ntop; ++e) {
+                    const unsigned v = trw[(size_t)e * TILE].x;
+                    if (v != CODE_NONE && (v & CODE_WINDOW))
+                        trw[(size_t)e * TILE].x = slot_of(v);
                 }
-            }
         }
         slot_base += nu;
         mA = mB;
         __syncthreads();  // the window's buffers are reused
+        if (lead) {
+            int c = rowbase[rho];
+            for (int pq = 0; pq < NLB; ++pq)
+                c += pcnt[pq * TILE + rho];
+            rowbase[rho] = c;
+        }
     }
 
     // ---- 3. partners outside the cells ----
-    if (lead)
-        for (int e = 0; e < ntop; ++e)
-            if (trw[(size_t)e * TILE].x == CODE_NONE) {
+    if (act) {
+#pragma unroll
+        for (int v = 0; v < TPP; ++v)
+            if (v * NLB + q < ntop && tcode[v] == CODE_NONE) {
                 const int k = atomicAdd(&n_extra, 1);
                 if (k < EXTRA_MAX)
-                    extra[k] = __float_as_int(a.tent[row.x + e].x);
-                trw[(size_t)e * TILE].x = CODE_EXTRA | (unsigned)k;
+                    extra[k] = tj[v];
+                tcode[v] = CODE_EXTRA | (unsigned)k;
             }
+        if (lead)
+            for (int e = TREG; e < ntop; ++e)
+                if (trw[(size_t)e * TILE].x == CODE_NONE) {
+                    const int k = atomicAdd(&n_extra, 1);
+                    if (k < EXTRA_MAX)
+                        extra[k] = __float_as_int(a.tent[row.x + e].x);
+                    trw[(size_t)e * TILE].x = CODE_EXTRA | (unsigned)k;
+                }
+    }
     __syncthreads();
     const int n_ex = n_extra;
     const int S = slot_base + min(n_ex, EXTRA_MAX);
@@ -776,15 +883,24 @@ __global__ __launch_bounds__(256) void k_tile_build(BuildArgs a)
         st[slot_base + k] = extra[k];
     if (t == 0)
         a.stage_cnt[tile] = S;
+    if (!act)
+        return;
+    auto final_slot = [&](unsigned v) {
+        return ((v & CODE_WINDOW) == 0 && (v & CODE_EXTRA)) ? (unsigned)slot_base + (v & ~CODE_EXTRA) : v;
+    };
+#pragma unroll
+    for (int v = 0; v < TPP; ++v)
+        if (v * NLB + q < ntop)
+            trw[(size_t)(v * NLB + q) * TILE] = make_uint2(final_slot(tcode[v]), tr0[v]);
     if (!lead)
         return;
-    for (int e = 0; e < ntop; ++e) {
-        const unsigned v = trw[(size_t)e * TILE].x;
-        if ((v & CODE_WINDOW) == 0 && (v & CODE_EXTRA))
-            trw[(size_t)e * TILE].x = (unsigned)slot_base + (v & ~CODE_EXTRA);
-    }
-    if ((cnt & 3) && cnt < a.cap)
-        lrow[(size_t)(cnt >> 2) * TILE] = acc;
+    for (int e = TREG; e < ntop; ++e)
+        trw[(size_t)e * TILE].x = final_slot(trw[(size_t)e * TILE].x);
+    // count; the last chunk padded with the empty slot SM (far away: its
+    // term is exactly 0)
+    const int cnt = rowbase[rho];
+    for (int k = cnt; k < ((cnt + 3) & ~3); ++k)
+        row_store(k, (unsigned short)SM);
     a.list_cnt[i] = cnt;
     if (cnt > a.cap)
         atomicOr(a.err, ERR_OVERFLOW);
@@ -836,22 +952,57 @@ __device__ __forceinline__ void tile_frame(const float4 &hi, const float4 &lo, c
     rl = make_float4(l[0], l[1], l[2], 0.0f);
 }
 
+// The low part of a tile coordinate is at most half an ulp of the high part;
+// a staged slot keeps it as a 10-bit multiple of ulp/1000 per axis in the
+// high part's w word, so one 16-byte LDS read brings both.
+__device__ __forceinline__ float ulp_of(float x)
+{
+    return __int_as_float(__float_as_int(x) & 0x7f800000) * 0x1p-23f;
+}
+
+__device__ __forceinline__ unsigned pack_low(const float4 &rh, const float4 &rl)
+{
+    unsigned bitsw = 0u;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const float u = ulp_of(comp(rh, ax));
+        const float v = u > 0.0f ? comp(rl, ax) / u * 1000.0f : 0.0f;
+        const int qv = (int)rintf(fminf(fmaxf(v, -511.0f), 511.0f));
+        bitsw |= ((unsigned)qv & 0x3ffu) << (10 * ax);
+    }
+    return bitsw;
+}
+
+__device__ __forceinline__ float3 unpack_low(const float4 &s)
+{
+    const unsigned w = __float_as_uint(s.w);
+    float l[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int qv = ((int)(w << (22 - 10 * ax))) >> 22;  // sign-extended 10-bit field
+        l[ax] = (float)qv * (ulp_of(comp(s, ax)) * 1.0e-3f);
+    }
+    return make_float3(l[0], l[1], l[2]);
+}
+
 // Staged coordinates within this distance of the tile origin let list pairs
-// use rh alone (separation error below 4e-6 A); wider tiles use rh + rl.
+// use the high part alone (separation error below 4e-6 A); wider tiles add
+// the low parts.
 constexpr float NARROW_TILE = 64.0f;
 
 // One workgroup of 256 lanes per tile of TILE residues: NL = 256/TILE lanes
 // per residue.  Lane t works on residue t % TILE and takes part q = t / TILE
 // of its row (list chunks c = q mod NL, bonded/native entries e = q mod NL);
-// part 0 adds the other parts' sums in a fixed order and does the update.
+// parts 1..NL-1 also draw the residue's Gaussian components, and part 0 adds
+// the other parts' sums in a fixed order and does the update.
 template <int TILE, bool ENERGY, int MODE>
-__global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
+__global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs a)
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
-    __shared__ float4 rh_s[SM + 1];  // slot SM: the far-away empty slot
-    __shared__ float4 rl_s[SM + 1];
+    __shared__ float4 sl_s[SM + 1];  // {rh.xyz, packed rl}; slot SM: the far-away empty slot
     __shared__ float red_f[NL > 1 ? (NL - 1) * 3 * TILE : 1];
+    __shared__ float red_g[(NL > 1 && MODE == 0) ? 3 * TILE : 1];
     __shared__ double red_e[(ENERGY && NL > 1) ? (NL - 1) * 4 * TILE : 1];
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
     const int per = gridDim.x >> 3;
@@ -897,23 +1048,21 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             if (ids[u] >= 0) {
-                const int sl = t + u * 256;
                 float4 rh, rl;
                 tile_frame(a.pin[2 * ids[u]], a.pin[2 * ids[u] + 1], O, rh, rl);
                 far |= !(fmaxf(fabsf(rh.x), fmaxf(fabsf(rh.y), fabsf(rh.z))) < NARROW_TILE);
-                rh_s[sl] = rh;
-                rl_s[sl] = rl;
+                rh.w = __uint_as_float(pack_low(rh, rl));
+                sl_s[t + u * 256] = rh;
             }
         }
-        if (t == 0) {
-            rh_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
-            rl_s[SM] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
+        if (t == 0)
+            sl_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
     }
     float4 rh0, rl0;
     tile_frame(hi0, lo0, O, rh0, rl0);
     if (act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE))
         far = true;
+    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
     const PairConsts k = pair_consts(a.c);
     Acc A;
@@ -924,10 +1073,10 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
         const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
         for (int e = q; e < ntop; e += NL) {
             const uint2 v = tp[(size_t)e * TILE];
-            const int sj = (int)v.x;
-            const float4 hj = rh_s[sj], lj = rl_s[sj];
-            const float3 d = make_float3((rh0.x - hj.x) + (rl0.x - lj.x), (rh0.y - hj.y) + (rl0.y - lj.y),
-                                         (rh0.z - hj.z) + (rl0.z - lj.z));
+            const float4 sj = sl_s[v.x];
+            const float3 lj = unpack_low(sj);
+            const float3 d = make_float3((rh0.x - sj.x) + (rl0.x - lj.x), (rh0.y - sj.y) + (rl0.y - lj.y),
+                                         (rh0.z - sj.z) + (rl0.z - lj.z));
             if (e < nb)
                 add_fene_d(A, d, __uint_as_float(v.y), k, ENERGY, broken);
             else
@@ -938,16 +1087,15 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
         // sits between them
         const int nch = (cnt + 3) >> 2;
         const int mine = nch > q ? (nch - q + NL - 1) / NL : 0;
-        if (!wide) {
+        auto run = [&](auto &&pair_delta_of) {
             auto chunk = [&](const uint2 &w) {
                 float4 pj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    pj[u] = rh_s[((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu];
+                    pj[u] = sl_s[((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive_d(A, make_float3(rh0.x - pj[u].x, rh0.y - pj[u].y, rh0.z - pj[u].z), k,
-                                    ENERGY);
+                    add_repulsive_d(A, pair_delta_of(pj[u]), k, ENERGY);
             };
             int m = 0;
             for (; m + 4 <= mine; m += 4) {
@@ -967,47 +1115,20 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
                 chunk(q1);
             if (m + 2 < mine)
                 chunk(q2);
-        } else {
-            auto chunk = [&](const uint2 &w) {
-                float4 ph[4], pl[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const unsigned sj = ((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu;
-                    ph[u] = rh_s[sj];
-                    pl[u] = rl_s[sj];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    add_repulsive_d(A,
-                                    make_float3((rh0.x - ph[u].x) + (rl0.x - pl[u].x),
-                                                (rh0.y - ph[u].y) + (rl0.y - pl[u].y),
-                                                (rh0.z - ph[u].z) + (rl0.z - pl[u].z)),
-                                    k, ENERGY);
-            };
-            int m = 0;
-            for (; m + 4 <= mine; m += 4) {
-                const int c = q + m * NL;
-                chunk(q0);
-                q0 = fetch(c + 4 * NL);
-                chunk(q1);
-                q1 = fetch(c + 5 * NL);
-                chunk(q2);
-                q2 = fetch(c + 6 * NL);
-                chunk(q3);
-                q3 = fetch(c + 7 * NL);
-            }
-            if (m < mine)
-                chunk(q0);
-            if (m + 1 < mine)
-                chunk(q1);
-            if (m + 2 < mine)
-                chunk(q2);
-        }
+        };
+        if (!wide)
+            run([&](const float4 &sj) { return make_float3(rh0.x - sj.x, rh0.y - sj.y, rh0.z - sj.z); });
+        else
+            run([&](const float4 &sj) {
+                const float3 lj = unpack_low(sj);
+                return make_float3((rh0.x - sj.x) + (rl0.x - lj.x), (rh0.y - sj.y) + (rl0.y - lj.y),
+                                   (rh0.z - sj.z) + (rl0.z - lj.z));
+            });
         if (broken)
             atomicOr(a.err, ERR_FENE);
     }
     if (NL > 1) {
-        // parts 1..NL-1 hand their sums to part 0
+        // parts 1..NL-1 hand their sums and the Gaussian components to part 0
         if (q > 0) {
             float *rf = red_f + (q - 1) * 3 * TILE;
             rf[rho] = A.fx;
@@ -1019,6 +1140,11 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
                 re[TILE + rho] = A.e_n;
                 re[2 * TILE + rho] = A.e_r;
                 re[3 * TILE + rho] = A.vir;
+            }
+            if (MODE == 0 && act && !(__float_as_uint(hi0.w) >> 31)) {
+                const uint4 w = noise_words(__float_as_uint(hi0.w), a.stream_ids[__float_as_int(lo0.w)], step, a.c);
+                for (int ax = q - 1; ax < 3; ax += NL - 1)
+                    red_g[ax * TILE + rho] = gaussian_axis(w, ax);
             }
         }
         __syncthreads();
@@ -1041,7 +1167,6 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
     }
     if (!act)
         return;
-    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     double e_x = 0.0, f_rep = 0.0;
     add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
                  a.tip, ENERGY, a.err);
@@ -1060,7 +1185,12 @@ __global__ __launch_bounds__(256) void k_tile_step(TileArgs a)
         return;
     }
     float4 hi = hi0, lo = lo0;
-    langevin_update(hi, lo, A, step, a.stream_ids[__float_as_int(lo0.w)], a.c, a.err);
+    if (NL > 1) {
+        const float g[3] = {red_g[rho], red_g[TILE + rho], red_g[2 * TILE + rho]};
+        update_with_noise(hi, lo, A, g, a.c, a.err);
+    } else {
+        langevin_update(hi, lo, A, step, a.stream_ids[__float_as_int(lo0.w)], a.c, a.err);
+    }
     a.pout[2 * i] = hi;
     a.pout[2 * i + 1] = lo;
 }
@@ -1327,8 +1457,10 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
     a.rc2 = rc2;
     a.n = n;
     a.cap = cap;
-    a.multi = multi;
-    hipLaunchKernelGGL(k_tile_build<TILE>, dim3(blocks_for(n, TILE)), dim3(256), 0, s, a);
+    if (multi)
+        hipLaunchKernelGGL((k_tile_build<TILE, true>), dim3(blocks_for(n, TILE)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_tile_build<TILE, false>), dim3(blocks_for(n, TILE)), dim3(256), 0, s, a);
 }
 
 template <int TILE, bool ENERGY, int MODE>
