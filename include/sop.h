@@ -176,11 +176,12 @@ sop_status sop_autotune(sop_ctx *ctx, double budget_ms, const char *cache_path);
 
 /*
  * Plain schedule: residues per workgroup ("tile" of consecutive residues;
- * 64, 128 or 256; 0 selects a default from the system size).  At each list
- * rebuild a tile gathers the residues it interacts with into at most 1024
- * (tiles of 64 or 128) or 2048 (tiles of 256) LDS slots; a tile that needs
- * more reports SOP_E_LIST_OVERFLOW.  May be changed after binding; the list
- * is rebuilt at the next step.
+ * 64, 128 or 256; 0 selects the default, 64).  At each list rebuild a tile
+ * gathers the residues it interacts with into at most 1024 (tiles of 64 or
+ * 128) or 2048 (tiles of 256) LDS slots, and the cells around it must number
+ * at most 640, 1024 or 512 respectively; a tile that needs more reports
+ * SOP_E_LIST_OVERFLOW.  May be changed after binding; the list is rebuilt at
+ * the next step.
  */
 sop_status sop_set_tile(sop_ctx *ctx, int32_t tile);
 

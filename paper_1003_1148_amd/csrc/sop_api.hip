@@ -174,14 +174,9 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
 
 // Residues per workgroup of the plain schedule: enough tiles to cover the
 // 256 compute units a few times over.
-int default_tile(long long n)
-{
-    if (n >= 4 * 256 * 256)
-        return 256;
-    if (n >= 2 * 256 * 128)
-        return 128;
-    return 64;
-}
+// 64-residue tiles: four lanes per residue in the step kernel, four waves
+// sharing each tile's rebuild (sop_autotune measures the others).
+int default_tile(long long) { return 64; }
 
 void destroy_graphs(sop_ctx *c)
 {

@@ -47,6 +47,15 @@ __device__ __forceinline__ float gaussian_axis(const uint4 &w, int axis)
     return rad * (axis == 1 ? s : c);
 }
 
+// Axes 0 and 1 together (one radius, one sincos); equal to gaussian_axis.
+__device__ __forceinline__ float2 gaussian_pair(const uint4 &w)
+{
+    const float rad = sqrtf(-2.0f * logf(unit23(w.x)));
+    float s, c;
+    sincospif(2.0f * unit23(w.y), &s, &c);
+    return make_float2(rad * c, rad * s);
+}
+
 __device__ __forceinline__ float comp(const float4 &v, int a)
 {
     return a == 0 ? v.x : (a == 1 ? v.y : v.z);
@@ -149,7 +158,7 @@ struct Acc {
 };
 
 struct PairConsts {
-    float kf, inv_R0sq, R0sq, eh, eh12, el, el6, sg2;
+    float kf, inv_R0sq, R0sq, eh, eh12, el, el6, sg2, sg6, c6;
 };
 
 __device__ __forceinline__ PairConsts pair_consts(const StepConsts &c)
@@ -163,6 +172,8 @@ __device__ __forceinline__ PairConsts pair_consts(const StepConsts &c)
     k.el = c.eps_l;
     k.el6 = 6.0f * c.eps_l;
     k.sg2 = c.sigma2;
+    k.sg6 = c.sigma2 * c.sigma2 * c.sigma2;
+    k.c6 = k.el6 * k.sg6;  // force coefficient 6 eps_l sigma^6 / r^8
     return k;
 }
 
@@ -212,13 +223,13 @@ __device__ __forceinline__ void add_repulsive_d(Acc &A, const float3 &d, const P
 {
     const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
     const float ir2 = fast_rcp(r2);
-    const float s = k.sg2 * ir2;
-    const float q = s * s * s;
-    const float coef = k.el6 * q * ir2;
+    const float ir4 = ir2 * ir2;
+    const float coef = k.c6 * ir4 * ir4;
     A.fx += coef * d.x;
     A.fy += coef * d.y;
     A.fz += coef * d.z;
     if (rec) {
+        const float q = k.sg6 * ir4 * ir2;
         A.e_r += (double)(k.el * q);
         A.vir += (double)(k.el6 * q);
     }
@@ -448,7 +459,7 @@ constexpr unsigned CODE_EXTRA = 0x40000000u;    // | index among the extra slots
 // A row lists its partners in (cell, residue index) order whatever the tile
 // size or the order in which residues were binned.
 template <int TILE, bool MULTI>
-__global__ __launch_bounds__(256, 2) void k_tile_build(BuildArgs a)
+__global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArgs a)
 {
     constexpr int NT = 256, NLB = NT / TILE;
     constexpr int SM = stage_max<TILE>();
@@ -686,8 +697,12 @@ __global__ __launch_bounds__(256, 2) void k_tile_build(BuildArgs a)
             if (ci < Mw) {
                 const int id = __float_as_int(cv[u].w);
                 const int k0 = cbase[cm[u]] - base, k1 = cbase[cm[u] + 1] - base;
-                int r = k0;
-                for (int k = k0; k < k1; ++k)
+                int r = k0, k = k0;
+                for (; k + 4 <= k1; k += 4) {
+                    const int a0 = aid[k], a1 = aid[k + 1], a2 = aid[k + 2], a3 = aid[k + 3];
+                    r += (a0 < id) + (a1 < id) + (a2 < id) + (a3 < id);
+                }
+                for (; k < k1; ++k)
                     r += aid[k] < id;
                 cand[r] = cv[u];
             }
@@ -712,17 +727,26 @@ __global__ __launch_bounds__(256, 2) void k_tile_build(BuildArgs a)
                 }
             unsigned word = 0u;
             if (__any(reach)) {
-#pragma unroll 8
-                for (int k = 0; k < 32; ++k) {
-                    const int r = 32 * w + k;
-                    const float4 c = cand[r];
-                    bool pass = act && r < Mw && within_cutoff(p, c, a.rc2);
-                    if (MULTI) {
-                        const int j = __float_as_int(c.w);
-                        pass = pass && j >= tlo && j < thi;
+                // branch-free: eight LDS reads in flight, then the tests; the
+                // window's tail and inactive lanes are masked afterwards
+#pragma unroll 2
+                for (int k0 = 0; k0 < 32; k0 += 8) {
+                    float4 c8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        c8[u] = cand[32 * w + k0 + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        bool pass = within_cutoff(p, c8[u], a.rc2);
+                        if (MULTI) {
+                            const int j = __float_as_int(c8[u].w);
+                            pass = pass & (j >= tlo) & (j < thi);
+                        }
+                        word |= (unsigned)pass << (k0 + u);
                     }
-                    word |= pass ? (1u << k) : 0u;
                 }
+                const int left = Mw - 32 * w;
+                word &= act ? (left >= 32 ? 0xffffffffu : ((1u << left) - 1u)) : 0u;
                 const unsigned u = wave_or(word);
                 if ((t & 63) == 0 && u)
                     atomicOr(&used[w], u);
@@ -965,8 +989,10 @@ __device__ __forceinline__ unsigned pack_low(const float4 &rh, const float4 &rl)
     unsigned bitsw = 0u;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const float u = ulp_of(comp(rh, ax));
-        const float v = u > 0.0f ? comp(rl, ax) / u * 1000.0f : 0.0f;
+        // 1/ulp is a power of two: biased exponent 277 - E for exponent field E
+        const int E = (__float_as_int(comp(rh, ax)) >> 23) & 0xff;
+        const float inv_u = (E >= 24 && E <= 253) ? __int_as_float((277 - E) << 23) : 0.0f;
+        const float v = comp(rl, ax) * inv_u * 1000.0f;
         const int qv = (int)rintf(fminf(fmaxf(v, -511.0f), 511.0f));
         bitsw |= ((unsigned)qv & 0x3ffu) << (10 * ax);
     }
@@ -1025,6 +1051,11 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
     const int last_ch = capc - 1;
     auto fetch = [&](int c) -> uint2 { return lp[(size_t)min(c, last_ch) * TILE]; };
     uint2 q0 = make_uint2(0u, 0u), q1 = q0, q2 = q0, q3 = q0;
+    // this part's first bonded/native entries e = q + k NL (read whether or
+    // not they exist: the reads stay inside the tile's entry block)
+    constexpr int TPRE = 4;
+    const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
+    uint2 tv[TPRE];
     if (act) {
         hi0 = a.pin[2 * i];
         lo0 = a.pin[2 * i + 1];
@@ -1034,6 +1065,9 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
         q1 = fetch(q + NL);
         q2 = fetch(q + 2 * NL);
         q3 = fetch(q + 3 * NL);
+#pragma unroll
+        for (int k = 0; k < TPRE; ++k)
+            tv[k] = tp[(size_t)(q + k * NL) * TILE];
     }
     const float4 O = a.pin[2 * mid];
     bool far = false;
@@ -1070,9 +1104,7 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
     if (act) {
         // bonded and native partners, entries e = q mod NL
         const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
-        const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
-        for (int e = q; e < ntop; e += NL) {
-            const uint2 v = tp[(size_t)e * TILE];
+        auto entry = [&](int e, const uint2 &v) {
             const float4 sj = sl_s[v.x];
             const float3 lj = unpack_low(sj);
             const float3 d = make_float3((rh0.x - sj.x) + (rl0.x - lj.x), (rh0.y - sj.y) + (rl0.y - lj.y),
@@ -1081,7 +1113,13 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
                 add_fene_d(A, d, __uint_as_float(v.y), k, ENERGY, broken);
             else
                 add_native_d(A, d, __uint_as_float(v.y), k, ENERGY);
-        }
+        };
+#pragma unroll
+        for (int kk = 0; kk < TPRE; ++kk)
+            if (q + kk * NL < ntop)
+                entry(q + kk * NL, tv[kk]);
+        for (int e = q + TPRE * NL; e < ntop; e += NL)
+            entry(e, tp[(size_t)e * TILE]);
         // list partners: chunks of 4 slots, four chunks in flight; loads are
         // unconditional (clamped into the row's region) so that no branch
         // sits between them
@@ -1141,10 +1179,16 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
                 re[2 * TILE + rho] = A.e_r;
                 re[3 * TILE + rho] = A.vir;
             }
-            if (MODE == 0 && act && !(__float_as_uint(hi0.w) >> 31)) {
+            // part 1: the (x, y) Box-Muller pair; part 2 (or part 1 alone): z
+            if (MODE == 0 && act && q <= 2 && !(__float_as_uint(hi0.w) >> 31)) {
                 const uint4 w = noise_words(__float_as_uint(hi0.w), a.stream_ids[__float_as_int(lo0.w)], step, a.c);
-                for (int ax = q - 1; ax < 3; ax += NL - 1)
-                    red_g[ax * TILE + rho] = gaussian_axis(w, ax);
+                if (q == 1) {
+                    const float2 gxy = gaussian_pair(w);
+                    red_g[rho] = gxy.x;
+                    red_g[TILE + rho] = gxy.y;
+                }
+                if (q == 2 || NL == 2)
+                    red_g[2 * TILE + rho] = gaussian_axis(w, 2);
             }
         }
         __syncthreads();
