@@ -958,7 +958,7 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
         for (long long i = 0; i < n; ++i) {
             const size_t tile = (size_t)(i / T);
             for (int k = 0; k < std::min(cnt[i], c->cap); ++k) {
-                const int sl = list[list16_index_host(i, k, c->cap, T)];
+                const int sl = list[list16_index_host(i, k, c->cap)];
                 if (sl >= stage_cnt[tile])
                     return fail(c, SOP_E_LIST_OVERFLOW, "list entry outside its tile's staging set");
                 const int j = stage[tile * SM + sl];

@@ -125,11 +125,7 @@ void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long lo
 
 // Plain schedule: entry k of residue r's row (a slot of its tile), and the
 // slots a tile of `tile` residues can stage.
-inline size_t list16_index_host(long long r, int k, int cap, int tile)
-{
-    return (size_t)(r / tile) * (size_t)cap * tile + (size_t)(k >> 2) * (4 * (size_t)tile) +
-           (size_t)(r % tile) * 4 + (size_t)(k & 3);
-}
+inline size_t list16_index_host(long long r, int k, int cap) { return (size_t)r * cap + (size_t)k; }
 inline int stage_max_host(int tile) { return tile >= 256 ? 2048 : 1024; }
 
 }  // namespace sop

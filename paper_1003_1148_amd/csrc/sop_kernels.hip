@@ -459,7 +459,7 @@ constexpr unsigned CODE_EXTRA = 0x40000000u;    // | index among the extra slots
 // A row lists its partners in (cell, residue index) order whatever the tile
 // size or the order in which residues were binned.
 template <int TILE, bool MULTI>
-__global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArgs a)
+__global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArgs a)
 {
     constexpr int NT = 256, NLB = NT / TILE;
     constexpr int SM = stage_max<TILE>();
@@ -468,12 +468,14 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
     constexpr int CELLS_MAX = cells_max<TILE>();
     constexpr int CHASH_BITS = chash_bits<TILE>();
     constexpr int CHASH = 1 << CHASH_BITS;
-    static_assert(NW * TILE >= CM && NW * TILE >= CELLS_MAX, "arrival data alias the row bits");
-    __shared__ float4 cand[CM];           // the window's candidates, sorted
-    __shared__ unsigned bits[NW * TILE];  // row bits, word-major; first arrival cells / ids
-    __shared__ int hkey[CHASH];
-    __shared__ short hval[CHASH];         // cell number: arrival, then sorted
-    __shared__ short rank_of[CELLS_MAX];
+    static_assert(NW * TILE >= CM, "arrival ids alias the row bits");
+    // Step 1 (cell table) and step 2 (candidates, row bits) share one region.
+    constexpr int P1 = (CHASH + CELLS_MAX) * 4, P2 = CM * 16 + NW * TILE * 4;
+    __shared__ __align__(16) unsigned char shared_region[P1 > P2 ? P1 : P2];
+    int *hkey = reinterpret_cast<int *>(shared_region);               // step 1: open addressing
+    int *ccell = reinterpret_cast<int *>(shared_region + CHASH * 4);  // step 1: arrival order
+    float4 *cand = reinterpret_cast<float4 *>(shared_region);         // step 2: window, sorted
+    unsigned *bits = reinterpret_cast<unsigned *>(shared_region + CM * 16);  // row bits, word-major
     __shared__ unsigned sxyz[CELLS_MAX];  // sorted cells: packed coordinates
     __shared__ int cbase[CELLS_MAX + 1];
     __shared__ unsigned used[NW];
@@ -491,7 +493,6 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
     const bool act = i < a.n;
     const bool lead = act && q == 0;  // writes the residue's count and padding
     const GridDev g = a.g;
-    int *ccell = reinterpret_cast<int *>(bits);  // arrival order of the cells
     for (int h = t; h < CHASH; h += NT)
         hkey[h] = -1;
     if (t < TILE)
@@ -504,18 +505,6 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
     __syncthreads();
 
     auto hslot = [](int key) { return (int)(((unsigned)key * 2654435761u) >> (32 - CHASH_BITS)); };
-    auto lookup = [&](int key) -> int {
-        int h = hslot(key);
-        for (int probe = 0; probe < CHASH; ++probe) {
-            const int k = hkey[h];
-            if (k == key)
-                return hval[h];
-            if (k < 0)
-                return -1;
-            h = (h + 1) & (CHASH - 1);
-        }
-        return -1;
-    };
 
     // ---- 1. cells around the tile ----
     // independent loads first; this part's bonded/native entries (u = q mod
@@ -559,12 +548,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
                 const int prev = atomicCAS(&hkey[h], -1, cid);
                 if (prev == -1) {
                     const int m = atomicAdd(&n_cu, 1);
-                    if (m < CELLS_MAX) {
+                    if (m < CELLS_MAX)
                         ccell[m] = cid;
-                        hval[h] = (short)m;
-                    } else {
+                    else
                         bad_cells = 1;
-                    }
                     break;
                 }
                 if (prev == cid)
@@ -604,14 +591,21 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
         int r = 0;
         for (int m2 = 0; m2 < NC; ++m2)
             r += ccell[m2] < c;
-        rank_of[m] = (short)r;
         sxyz[r] = (unsigned)(c % g.gx) | ((unsigned)((c / g.gx) % g.gy) << bx) |
                   ((unsigned)(c / (g.gx * g.gy)) << (bx + by));
     }
     __syncthreads();
-    for (int h = t; h < CHASH; h += NT)
-        if (hkey[h] >= 0)
-            hval[h] = rank_of[hval[h]];
+    auto lookup = [&](int key) -> int {  // sorted number of cell `key`, or -1
+        int lo = 0, hi = NC;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cell_id(sxyz[mid]) < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return (lo < NC && cell_id(sxyz[lo]) == key) ? lo : -1;
+    };
     // candidate counts -> cbase (exclusive prefix in sorted cell order)
     {
         const int cper = (NC + NT - 1) / NT;
@@ -656,10 +650,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
 
     // ---- 2. windows of whole cells ----
     int *st = a.stage + (size_t)tile * SM;
-    unsigned short *lrow = a.list16 + (size_t)tile * a.cap * TILE + (size_t)rho * 4;
+    unsigned short *lrow = a.list16 + (size_t)i * a.cap;  // rows are residue-major
     auto row_store = [&](int k, unsigned short sl) {  // entry k of the residue's row
         if (k < a.cap)
-            lrow[(size_t)(k >> 2) * (4 * TILE) + (k & 3)] = sl;
+            lrow[k] = sl;
     };
     int slot_base = 0;
     int *aid = reinterpret_cast<int *>(bits);
@@ -729,7 +723,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 4 : 2) void k_tile_build(BuildArg
             if (__any(reach)) {
                 // branch-free: eight LDS reads in flight, then the tests; the
                 // window's tail and inactive lanes are masked afterwards
-#pragma unroll 2
+#pragma unroll 1
                 for (int k0 = 0; k0 < 32; k0 += 8) {
                     float4 c8[8];
 #pragma unroll
@@ -1016,20 +1010,33 @@ __device__ __forceinline__ float3 unpack_low(const float4 &s)
 // the low parts.
 constexpr float NARROW_TILE = 64.0f;
 
-// One workgroup of 256 lanes per tile of TILE residues: NL = 256/TILE lanes
-// per residue.  Lane t works on residue t % TILE and takes part q = t / TILE
-// of its row (list chunks c = q mod NL, bonded/native entries e = q mod NL);
-// parts 1..NL-1 also draw the residue's Gaussian components, and part 0 adds
-// the other parts' sums in a fixed order and does the update.
+// One workgroup of 256 lanes per tile of TILE residues.
+//  - Bonded/native entries and the noise: NL = 256/TILE lanes per residue;
+//    lane t serves residue t % TILE as part q = t / TILE (entries e = q mod
+//    NL; parts 1 and 2 draw the Gaussian components).
+//  - List partners: the tile's rows, cut into chunks of 4 slots and laid end
+//    to end (residue by residue), are split into 256 equal contiguous ranges,
+//    one per lane, so that every lane evaluates the same number of pairs
+//    whatever the spread of row lengths.  A residue covered by one range gets
+//    its sum directly; otherwise the ranges' partial sums are added in lane
+//    order.
+// Lane 0 of each residue then adds everything in a fixed order, adds the
+// external terms and does the update.
 template <int TILE, bool ENERGY, int MODE>
-__global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs a)
+__global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_tile_step(TileArgs a)
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
+    constexpr int RPL = TILE / 64;  // residues per lane of wave 0 in the chunk scan
     __shared__ float4 sl_s[SM + 1];  // {rh.xyz, packed rl}; slot SM: the far-away empty slot
+    __shared__ float4 own_s[TILE];   // own high parts
+    __shared__ int coff[TILE + 1];   // first chunk of each row in the tile's sequence
+    __shared__ float pf[2][3][256];  // partial list sums: first / last residue of a range
+    __shared__ float df[3][TILE];    // list sums of residues inside one range
     __shared__ float red_f[NL > 1 ? (NL - 1) * 3 * TILE : 1];
     __shared__ float red_g[(NL > 1 && MODE == 0) ? 3 * TILE : 1];
-    __shared__ double red_e[(ENERGY && NL > 1) ? (NL - 1) * 4 * TILE : 1];
+    __shared__ double red_e[ENERGY ? (NL + 1) * 4 * TILE : 1];   // energies: parts, then list direct
+    __shared__ double pe[ENERGY ? 2 * 2 * 256 : 1];              // list energy partials (e_r, vir)
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
     const int per = gridDim.x >> 3;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -1042,32 +1049,27 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
     const int S = a.stage_cnt[tile];
     const int *st = a.stage + (size_t)tile * SM;
     const int mid = min(tile * TILE + TILE / 2, a.n - 1);
-    // loads that do not depend on the staging first: own row, list chunks
+    // loads that do not depend on the staging first
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
-    int cnt = 0;
-    const int capc = a.cap >> 2;
-    const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16) + (size_t)tile * capc * TILE + rho;
-    const int last_ch = capc - 1;
-    auto fetch = [&](int c) -> uint2 { return lp[(size_t)min(c, last_ch) * TILE]; };
-    uint2 q0 = make_uint2(0u, 0u), q1 = q0, q2 = q0, q3 = q0;
-    // this part's first bonded/native entries e = q + k NL (read whether or
-    // not they exist: the reads stay inside the tile's entry block)
-    constexpr int TPRE = 4;
+    constexpr int TPRE = 4;  // this part's first bonded/native entries e = q + k NL
     const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
     uint2 tv[TPRE];
     if (act) {
         hi0 = a.pin[2 * i];
         lo0 = a.pin[2 * i + 1];
         row = a.trow[i];
-        cnt = min(a.list_cnt[i], a.cap);
-        q0 = fetch(q);
-        q1 = fetch(q + NL);
-        q2 = fetch(q + 2 * NL);
-        q3 = fetch(q + 3 * NL);
 #pragma unroll
-        for (int k = 0; k < TPRE; ++k)
+        for (int k = 0; k < TPRE; ++k)  // inside the tile's entry block whether or not they exist
             tv[k] = tp[(size_t)(q + k * NL) * TILE];
+    }
+    int rc[RPL];  // wave 0: chunks of residues RPL*t .. RPL*t + RPL - 1
+    if (t < 64) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            const int ii = tile * TILE + RPL * t + u;
+            rc[u] = ii < a.n ? (min(a.list_cnt[ii], a.cap) + 3) >> 2 : 0;
+        }
     }
     const float4 O = a.pin[2 * mid];
     bool far = false;
@@ -1096,9 +1098,131 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
     tile_frame(hi0, lo0, O, rh0, rl0);
     if (act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE))
         far = true;
+    if (q == 0) {
+        rh0.w = __uint_as_float(pack_low(rh0, rl0));
+        own_s[rho] = rh0;
+    }
+    if (t < 64) {
+        // chunk offsets of the rows: inclusive scan over wave 0
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u)
+            sum += rc[u];
+        int v = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(v, off, 64);
+            if (t >= off)
+                v += y;
+        }
+        int c = v - sum;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            coff[RPL * t + u] = c;
+            c += rc[u];
+        }
+        if (t == 63)
+            coff[TILE] = v;
+    }
     const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
     const PairConsts k = pair_consts(a.c);
+    // ---- list partners: this lane's range of chunks ----
+    const int C = coff[TILE];
+    const int c0 = (int)(((long long)t * C) >> 8), c1 = (int)(((long long)(t + 1) * C) >> 8);
+    {
+        auto row_of = [&](int c) {  // the residue whose chunks contain c (last r with coff[r] <= c)
+            int lo = 0, hi = TILE;
+            while (hi - lo > 1) {
+                const int m = (lo + hi) >> 1;
+                if (coff[m] <= c)
+                    lo = m;
+                else
+                    hi = m;
+            }
+            return lo;
+        };
+        const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16) + (size_t)tile * TILE * (a.cap >> 2);
+        const int capc = a.cap >> 2;
+        int r = c0 < c1 ? row_of(c0) : 0;
+        const int r_first = r;
+        int rend = coff[r + 1];
+        Acc L;
+        float4 ph0 = own_s[r];
+        float3 pl0 = unpack_low(ph0);
+        auto flush = [&]() {
+            if (coff[r] >= c0 && rend <= c1) {  // the whole row is in this range
+                df[0][r] = L.fx;
+                df[1][r] = L.fy;
+                df[2][r] = L.fz;
+                if (ENERGY) {
+                    red_e[(NL * 4 + 0) * TILE + r] = L.e_r;
+                    red_e[(NL * 4 + 1) * TILE + r] = L.vir;
+                }
+            } else {
+                const int s2 = r == r_first ? 0 : 1;
+                pf[s2][0][t] = L.fx;
+                pf[s2][1][t] = L.fy;
+                pf[s2][2][t] = L.fz;
+                if (ENERGY) {
+                    pe[(s2 * 2 + 0) * 256 + t] = L.e_r;
+                    pe[(s2 * 2 + 1) * 256 + t] = L.vir;
+                }
+            }
+            L = Acc();
+        };
+        auto pairs4 = [&](const uint2 &w) {
+            float4 pj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                pj[u] = sl_s[((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu];
+            if (!wide) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    add_repulsive_d(L, make_float3(ph0.x - pj[u].x, ph0.y - pj[u].y, ph0.z - pj[u].z), k, ENERGY);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float3 lj = unpack_low(pj[u]);
+                    add_repulsive_d(L,
+                                    make_float3((ph0.x - pj[u].x) + (pl0.x - lj.x), (ph0.y - pj[u].y) + (pl0.y - lj.y),
+                                                (ph0.z - pj[u].z) + (pl0.z - lj.z)),
+                                    k, ENERGY);
+                }
+            }
+        };
+        // batches of up to 4 chunks: addresses and loads first, then the pairs
+        constexpr int KB = 4;
+        for (int cb = c0; cb < c1; cb += KB) {
+            uint2 w[KB];
+            int rr[KB];
+            int r2 = r, e2 = rend;
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const int c = min(cb + u, c1 - 1);
+                while (c >= e2) {  // next non-empty row
+                    ++r2;
+                    e2 = coff[r2 + 1];
+                }
+                rr[u] = r2;
+                w[u] = lp[(size_t)r2 * capc + (c - coff[r2])];
+            }
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                if (cb + u < c1) {
+                    if (rr[u] != r) {
+                        flush();
+                        r = rr[u];
+                        rend = coff[r + 1];
+                        ph0 = own_s[r];
+                        pl0 = unpack_low(ph0);
+                    }
+                    pairs4(w[u]);
+                }
+            }
+        }
+        if (c0 < c1)
+            flush();
+    }
     Acc A;
     bool broken = false;
     if (act) {
@@ -1120,97 +1244,101 @@ __global__ __launch_bounds__(256, TILE >= 256 ? 4 : 5) void k_tile_step(TileArgs
                 entry(q + kk * NL, tv[kk]);
         for (int e = q + TPRE * NL; e < ntop; e += NL)
             entry(e, tp[(size_t)e * TILE]);
-        // list partners: chunks of 4 slots, four chunks in flight; loads are
-        // unconditional (clamped into the row's region) so that no branch
-        // sits between them
-        const int nch = (cnt + 3) >> 2;
-        const int mine = nch > q ? (nch - q + NL - 1) / NL : 0;
-        auto run = [&](auto &&pair_delta_of) {
-            auto chunk = [&](const uint2 &w) {
-                float4 pj[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    pj[u] = sl_s[((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    add_repulsive_d(A, pair_delta_of(pj[u]), k, ENERGY);
-            };
-            int m = 0;
-            for (; m + 4 <= mine; m += 4) {
-                const int c = q + m * NL;
-                chunk(q0);
-                q0 = fetch(c + 4 * NL);
-                chunk(q1);
-                q1 = fetch(c + 5 * NL);
-                chunk(q2);
-                q2 = fetch(c + 6 * NL);
-                chunk(q3);
-                q3 = fetch(c + 7 * NL);
-            }
-            if (m < mine)
-                chunk(q0);
-            if (m + 1 < mine)
-                chunk(q1);
-            if (m + 2 < mine)
-                chunk(q2);
-        };
-        if (!wide)
-            run([&](const float4 &sj) { return make_float3(rh0.x - sj.x, rh0.y - sj.y, rh0.z - sj.z); });
-        else
-            run([&](const float4 &sj) {
-                const float3 lj = unpack_low(sj);
-                return make_float3((rh0.x - sj.x) + (rl0.x - lj.x), (rh0.y - sj.y) + (rl0.y - lj.y),
-                                   (rh0.z - sj.z) + (rl0.z - lj.z));
-            });
         if (broken)
             atomicOr(a.err, ERR_FENE);
     }
-    if (NL > 1) {
-        // parts 1..NL-1 hand their sums and the Gaussian components to part 0
-        if (q > 0) {
-            float *rf = red_f + (q - 1) * 3 * TILE;
-            rf[rho] = A.fx;
-            rf[TILE + rho] = A.fy;
-            rf[2 * TILE + rho] = A.fz;
-            if (ENERGY) {
-                double *re = red_e + (q - 1) * 4 * TILE;
-                re[rho] = A.e_b;
-                re[TILE + rho] = A.e_n;
-                re[2 * TILE + rho] = A.e_r;
-                re[3 * TILE + rho] = A.vir;
+    // parts 1..NL-1 hand their sums and the Gaussian components to part 0
+    if (NL > 1 && q > 0) {
+        float *rf = red_f + (q - 1) * 3 * TILE;
+        rf[rho] = A.fx;
+        rf[TILE + rho] = A.fy;
+        rf[2 * TILE + rho] = A.fz;
+        // part 1: the (x, y) Box-Muller pair; part 2 (or part 1 alone): z
+        if (MODE == 0 && act && q <= 2 && !(__float_as_uint(hi0.w) >> 31)) {
+            const uint4 w = noise_words(__float_as_uint(hi0.w), a.stream_ids[__float_as_int(lo0.w)], step, a.c);
+            if (q == 1) {
+                const float2 gxy = gaussian_pair(w);
+                red_g[rho] = gxy.x;
+                red_g[TILE + rho] = gxy.y;
             }
-            // part 1: the (x, y) Box-Muller pair; part 2 (or part 1 alone): z
-            if (MODE == 0 && act && q <= 2 && !(__float_as_uint(hi0.w) >> 31)) {
-                const uint4 w = noise_words(__float_as_uint(hi0.w), a.stream_ids[__float_as_int(lo0.w)], step, a.c);
-                if (q == 1) {
-                    const float2 gxy = gaussian_pair(w);
-                    red_g[rho] = gxy.x;
-                    red_g[TILE + rho] = gxy.y;
-                }
-                if (q == 2 || NL == 2)
-                    red_g[2 * TILE + rho] = gaussian_axis(w, 2);
-            }
+            if (q == 2 || NL == 2)
+                red_g[2 * TILE + rho] = gaussian_axis(w, 2);
         }
-        __syncthreads();
-        if (q > 0)
-            return;
-#pragma unroll
-        for (int p = 0; p < NL - 1; ++p) {
-            const float *rf = red_f + p * 3 * TILE;
-            A.fx += rf[rho];
-            A.fy += rf[TILE + rho];
-            A.fz += rf[2 * TILE + rho];
-            if (ENERGY) {
-                const double *re = red_e + p * 4 * TILE;
-                A.e_b += re[rho];
-                A.e_n += re[TILE + rho];
-                A.e_r += re[2 * TILE + rho];
-                A.vir += re[3 * TILE + rho];
+    }
+    if (ENERGY) {
+        double *re = red_e + q * 4 * TILE;
+        re[rho] = A.e_b;
+        re[TILE + rho] = A.e_n;
+        re[2 * TILE + rho] = A.e_r;
+        re[3 * TILE + rho] = A.vir;
+    }
+    __syncthreads();
+    if (q > 0 || !act)
+        return;
+    // list sums of this residue
+    float lx = 0.0f, ly = 0.0f, lz = 0.0f;
+    double ler = 0.0, lvir = 0.0;
+    {
+        const int b0 = coff[rho], b1 = coff[rho + 1];
+        if (b1 > b0) {
+            const int ta = (int)((256LL * (b0 + 1) - 1) / C), tb = (int)((256LL * b1 - 1) / C);
+            const int ca = (int)(((long long)ta * C) >> 8), cb = (int)(((long long)(ta + 1) * C) >> 8);
+            if (b0 >= ca && b1 <= cb) {
+                lx = df[0][rho];
+                ly = df[1][rho];
+                lz = df[2][rho];
+                if (ENERGY) {
+                    ler = red_e[(NL * 4 + 0) * TILE + rho];
+                    lvir = red_e[(NL * 4 + 1) * TILE + rho];
+                }
+            } else {
+                const int s0 = b0 > ca ? 1 : 0;
+                lx = pf[s0][0][ta];
+                ly = pf[s0][1][ta];
+                lz = pf[s0][2][ta];
+                if (ENERGY) {
+                    ler = pe[(s0 * 2 + 0) * 256 + ta];
+                    lvir = pe[(s0 * 2 + 1) * 256 + ta];
+                }
+                for (int tt = ta + 1; tt <= tb; ++tt) {
+                    if ((((long long)tt * C) >> 8) == (((long long)(tt + 1) * C) >> 8))
+                        continue;  // an empty range (fewer chunks than lanes)
+                    lx += pf[0][0][tt];
+                    ly += pf[0][1][tt];
+                    lz += pf[0][2][tt];
+                    if (ENERGY) {
+                        ler += pe[0 * 256 + tt];
+                        lvir += pe[1 * 256 + tt];
+                    }
+                }
             }
         }
     }
-    if (!act)
-        return;
+    // fixed order: bonded/native parts 0..NL-1, then the list
+#pragma unroll
+    for (int p = 0; p < NL - 1; ++p) {
+        const float *rf = red_f + p * 3 * TILE;
+        A.fx += rf[rho];
+        A.fy += rf[TILE + rho];
+        A.fz += rf[2 * TILE + rho];
+    }
+    A.fx += lx;
+    A.fy += ly;
+    A.fz += lz;
+    if (ENERGY) {
+        double eb = 0.0, en = 0.0, er = 0.0, vir = 0.0;
+        for (int p = 0; p < NL; ++p) {
+            const double *re = red_e + p * 4 * TILE;
+            eb += re[rho];
+            en += re[TILE + rho];
+            er += re[2 * TILE + rho];
+            vir += re[3 * TILE + rho];
+        }
+        A.e_b = eb;
+        A.e_n = en;
+        A.e_r = er + ler;
+        A.vir = vir + lvir;
+    }
     double e_x = 0.0, f_rep = 0.0;
     add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
                  a.tip, ENERGY, a.err);
