@@ -31,6 +31,7 @@ struct sop_ctx {
     std::vector<PullDev> pulls;
     std::vector<int> pull_slot;
     std::vector<int4> traj_cell;
+    std::vector<int> tiles[3];  // plain: first residue of each tile (+ n) for tiles of 64, 128, 256
     TipDev tip{};
 
     // schedule: plain (kernel per step) or batched (persistent packs)
@@ -124,12 +125,16 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     // padded for the largest tile so that any tile size fits
     const size_t n_pad = ((n + 255) / 256) * 256;
     const size_t list16_elems = plain ? n_pad * (size_t)c->cap : n * (size_t)c->cap;
-    const size_t topo2_elems = plain ? n_pad * TOPO_CAP : 0;
-    const size_t n_tiles_max = plain ? (n + 63) / 64 : 0;   // tiles of the smallest size
-    // slots of every tile, for the largest need over the tile sizes
-    const size_t stage_elems =
-        plain ? std::max({((n + 63) / 64) * 1024, ((n + 127) / 128) * 1024, ((n + 255) / 256) * 2048})
-              : 0;
+    // per-tile blocks, for the largest need over the tile sizes
+    size_t topo2_elems = 0, n_tiles_max = 0, stage_elems = 0, tf_elems[3] = {1, 1, 1};
+    if (plain)
+        for (int k = 0; k < 3; ++k) {
+            const size_t T = (size_t)64 << k, nt = c->tiles[k].size() - 1;
+            topo2_elems = std::max(topo2_elems, nt * T * TOPO_CAP);
+            stage_elems = std::max(stage_elems, nt * (size_t)stage_max_host((int)T));
+            n_tiles_max = std::max(n_tiles_max, nt);
+            tf_elems[k] = nt + 1;
+        }
     const size_t ncell = plain ? (size_t)c->n_cells_cap : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -152,6 +157,10 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.cell_count = (int *)take(ncell * sizeof(int));
     d.cells = (float4 *)take(ncell * CELL_CAP * sizeof(float4));
     d.cell_of = (int *)take((plain ? n : 0) * sizeof(int));
+    for (int k = 0; k < 3; ++k) {
+        d.tile_first[k] = (int *)take(tf_elems[k] * sizeof(int));
+        d.n_tiles[k] = plain ? (int)(tf_elems[k] - 1) : 0;
+    }
     d.traj_cell = (int4 *)take(T * sizeof(int4));
     d.traj_lo = (int *)take(n * sizeof(int));
     d.traj_hi = (int *)take(n * sizeof(int));
@@ -581,6 +590,30 @@ sop_status sop_load_topology(sop_ctx *c, int32_t n_traj, const int64_t *res_offs
             c->tent.push_back(float2{f, e.second});
         }
     }
+    // plain-schedule tiles: consecutive residues, a new tile at a chain start
+    // (first residue of a trajectory or not bonded to its predecessor) once
+    // the current one is half full, so that tiles stay compact in space
+    std::vector<char> chain_start(n, 0);
+    for (long long i = 0; i < n; ++i) {
+        bool bonded = false;
+        for (auto &e : rb[i])
+            bonded |= e.first == i - 1;
+        chain_start[i] = (i == c->traj_lo[i] || !bonded) ? 1 : 0;
+    }
+    for (int k = 0; k < 3; ++k) {
+        const int T = 64 << k;
+        auto &tl = c->tiles[k];
+        tl.clear();
+        int cnt = 0;
+        for (long long i = 0; i < n; ++i) {
+            if (cnt == 0 || cnt == T || (chain_start[i] && 2 * cnt >= T)) {
+                tl.push_back((int)i);
+                cnt = 0;
+            }
+            ++cnt;
+        }
+        tl.push_back((int)n);
+    }
     c->pulls.clear();
     c->pull_slot.assign(n, -1);
     c->tip = TipDev{};
@@ -809,9 +842,17 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
     if (c->schedule == SOP_SCHEDULE_PLAIN) {
         // slot arrays start as slot 0, which every tile's staging holds
         const size_t n_pad = ((n + 255) / 256) * 256;
+        size_t topo2_elems = 0, n_tiles_max = 0;
+        for (int k = 0; k < 3; ++k) {
+            const size_t nt = c->tiles[k].size() - 1;
+            topo2_elems = std::max(topo2_elems, nt * ((size_t)64 << k) * TOPO_CAP);
+            n_tiles_max = std::max(n_tiles_max, nt);
+            HIP_TRY(c, hipMemcpyAsync(b.tile_first[k], c->tiles[k].data(), c->tiles[k].size() * sizeof(int),
+                                      hipMemcpyHostToDevice, s));
+        }
         HIP_TRY(c, hipMemsetAsync(b.list16, 0, n_pad * c->cap * sizeof(unsigned short), s));
-        HIP_TRY(c, hipMemsetAsync(b.topo2, 0, n_pad * TOPO_CAP * sizeof(uint2), s));
-        HIP_TRY(c, hipMemsetAsync(b.stage_cnt, 0, ((n + 63) / 64) * sizeof(int), s));
+        HIP_TRY(c, hipMemsetAsync(b.topo2, 0, topo2_elems * sizeof(uint2), s));
+        HIP_TRY(c, hipMemsetAsync(b.stage_cnt, 0, n_tiles_max * sizeof(int), s));
     }
     HIP_TRY(c, hipMemsetAsync(b.res_energy, 0, n * RES_E * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.energy, 0, (size_t)c->n_traj * SOP_NTERMS * sizeof(double), s));
@@ -948,15 +989,18 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
     } else {
         // rows hold slots of their tile; the tile's stage maps slots to ids
         const int T = c->tile, SM = stage_max_host(T);
-        const size_t n_tiles = (size_t)((n + T - 1) / T);
-        std::vector<unsigned short> list(n_tiles * (size_t)T * c->cap);
+        const auto &tl = c->tiles[tile_index(T)];
+        const size_t n_tiles = tl.size() - 1;
+        std::vector<unsigned short> list((size_t)n * c->cap);
         std::vector<int> stage(n_tiles * (size_t)SM), stage_cnt(n_tiles);
         HIP_TRY(c, hipMemcpy(list.data(), c->b.list16, list.size() * sizeof(unsigned short),
                              hipMemcpyDeviceToHost));
         HIP_TRY(c, hipMemcpy(stage.data(), c->b.stage, stage.size() * sizeof(int), hipMemcpyDeviceToHost));
         HIP_TRY(c, hipMemcpy(stage_cnt.data(), c->b.stage_cnt, n_tiles * sizeof(int), hipMemcpyDeviceToHost));
+        size_t tile = 0;
         for (long long i = 0; i < n; ++i) {
-            const size_t tile = (size_t)(i / T);
+            while (i >= tl[tile + 1])
+                ++tile;
             for (int k = 0; k < std::min(cnt[i], c->cap); ++k) {
                 const int sl = list[list16_index_host(i, k, c->cap)];
                 if (sl >= stage_cnt[tile])

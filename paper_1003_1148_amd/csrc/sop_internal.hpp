@@ -79,6 +79,8 @@ struct DevBufs {
     int *cell_count;  // residues per cell
     float4 *cells;    // CELL_CAP slots per cell: {hi.xyz, residue id bits}
     int *cell_of;     // per residue: its cell at the last rebuild
+    int *tile_first[3];  // plain: first residue of each tile (+ n) for tiles of 64, 128, 256
+    int n_tiles[3];
     int4 *traj_cell;  // per trajectory: cell-index offset that keeps trajectories apart
     int *traj_lo;     // per residue: first residue of its trajectory
     int *traj_hi;     // per residue: one past the last residue of its trajectory
@@ -127,5 +129,6 @@ void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long lo
 // slots a tile of `tile` residues can stage.
 inline size_t list16_index_host(long long r, int k, int cap) { return (size_t)r * cap + (size_t)k; }
 inline int stage_max_host(int tile) { return tile >= 256 ? 2048 : 1024; }
+inline int tile_index(int tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : 2); }
 
 }  // namespace sop

@@ -379,6 +379,7 @@ constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cel
 constexpr int TREG = 16;        // bonded/native entries per residue kept in registers
 
 struct BuildArgs {
+    const int *tile_first;  // first residue of each tile, then n
     const float4 *pos;
     const int *cell_of;
     const int *count;
@@ -489,8 +490,9 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
 
     const int tile = blockIdx.x, t = threadIdx.x;
     const int rho = t % TILE, q = t / TILE;
-    const int i = tile * TILE + rho;
-    const bool act = i < a.n;
+    const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
+    const int i = first + rho;
+    const bool act = rho < tcnt;
     const bool lead = act && q == 0;  // writes the residue's count and padding
     const GridDev g = a.g;
     for (int h = t; h < CHASH; h += NT)
@@ -925,6 +927,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
 }
 
 struct TileArgs {
+    const int *tile_first;  // first residue of each tile, then n
     const float4 *pin;
     float4 *pout;
     const int2 *trow;
@@ -1044,11 +1047,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         return;  // uniform over the workgroup
     const int t = threadIdx.x;
     const int rho = t % TILE, q = t / TILE;
-    const int i = tile * TILE + rho;
-    const bool act = i < a.n;
+    const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
+    const int i = first + rho;
+    const bool act = rho < tcnt;
     const int S = a.stage_cnt[tile];
     const int *st = a.stage + (size_t)tile * SM;
-    const int mid = min(tile * TILE + TILE / 2, a.n - 1);
+    const int mid = first + tcnt / 2;
     // loads that do not depend on the staging first
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
@@ -1067,8 +1071,8 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     if (t < 64) {
 #pragma unroll
         for (int u = 0; u < RPL; ++u) {
-            const int ii = tile * TILE + RPL * t + u;
-            rc[u] = ii < a.n ? (min(a.list_cnt[ii], a.cap) + 3) >> 2 : 0;
+            const int rr = RPL * t + u;
+            rc[u] = rr < tcnt ? (min(a.list_cnt[first + rr], a.cap) + 3) >> 2 : 0;
         }
     }
     const float4 O = a.pin[2 * mid];
@@ -1141,7 +1145,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             }
             return lo;
         };
-        const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16) + (size_t)tile * TILE * (a.cap >> 2);
+        const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16) + (size_t)first * (a.cap >> 2);
         const int capc = a.cap >> 2;
         int r = c0 < c1 ? row_of(c0) : 0;
         const int r_first = r;
@@ -1610,6 +1614,7 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
                   hipStream_t s)
 {
     BuildArgs a{};
+    a.tile_first = b.tile_first[tile_index(TILE)];
     a.pos = b.pos[cur];
     a.cell_of = b.cell_of;
     a.count = b.cell_count;
@@ -1629,18 +1634,18 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
     a.rc2 = rc2;
     a.n = n;
     a.cap = cap;
+    const int nt = b.n_tiles[tile_index(TILE)];
     if (multi)
-        hipLaunchKernelGGL((k_tile_build<TILE, true>), dim3(blocks_for(n, TILE)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_tile_build<TILE, true>), dim3(nt), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_tile_build<TILE, false>), dim3(blocks_for(n, TILE)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_tile_build<TILE, false>), dim3(nt), dim3(256), 0, s, a);
 }
 
 template <int TILE, bool ENERGY, int MODE>
 void tile_step(const TileArgs &a, hipStream_t s)
 {
-    TileArgs x = a;
-    x.n_tiles = blocks_for(a.n, TILE);
-    const int blocks = ((x.n_tiles + 7) / 8) * 8;
+    const int blocks = ((a.n_tiles + 7) / 8) * 8;
+    const TileArgs &x = a;
     hipLaunchKernelGGL((k_tile_step<TILE, ENERGY, MODE>), dim3(blocks), dim3(256), 0, s, x);
 }
 
@@ -1675,6 +1680,8 @@ void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const Step
                  long long step_off, hipStream_t s)
 {
     TileArgs a{};
+    a.tile_first = b.tile_first[tile_index(tile)];
+    a.n_tiles = b.n_tiles[tile_index(tile)];
     a.pin = b.pos[cur];
     a.pout = b.pos[cur ^ 1];
     a.trow = b.trow;
