@@ -293,11 +293,12 @@ __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep,
             atomicOr(err, ERR_TIP);
             return;
         }
-        const float sg = (float)tip.sigma / gap;
+        const float igap = fast_rcp(gap);
+        const float sg = (float)tip.sigma * igap;
         const float s3 = sg * sg * sg;
         const float q = s3 * s3;
-        const float mag = 6.0f * (float)tip.eps * q / gap;
-        const float cx = mag * dx / rr, cy = mag * dy / rr, cz = mag * dz / rr;
+        const float mag_r = 6.0f * (float)tip.eps * q * igap * fast_rcp(rr);  // magnitude / r
+        const float cx = mag_r * dx, cy = mag_r * dy, cz = mag_r * dz;
         A.fx += cx;
         A.fy += cy;
         A.fz += cz;
@@ -1131,8 +1132,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
     const PairConsts k = pair_consts(a.c);
     // ---- list partners: this lane's range of chunks ----
+    // lane ranges [c0(t), c0(t+1)), c0(t) = t C / 256 (C <= 64 cap: 32-bit products)
     const int C = coff[TILE];
-    const int c0 = (int)(((long long)t * C) >> 8), c1 = (int)(((long long)(t + 1) * C) >> 8);
+    auto cstart = [&](int tt) { return (tt * C) >> 8; };
+    const int c0 = cstart(t), c1 = cstart(t + 1);
     {
         auto row_of = [&](int c) {  // the residue whose chunks contain c (last r with coff[r] <= c)
             int lo = 0, hi = TILE;
@@ -1285,8 +1288,18 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     {
         const int b0 = coff[rho], b1 = coff[rho + 1];
         if (b1 > b0) {
-            const int ta = (int)((256LL * (b0 + 1) - 1) / C), tb = (int)((256LL * b1 - 1) / C);
-            const int ca = (int)(((long long)ta * C) >> 8), cb = (int)(((long long)(ta + 1) * C) >> 8);
+            // the lanes whose ranges hold chunks b0 and b1 - 1: the last t with c0(t) <= c
+            const float invC = 1.0f / (float)C;
+            auto lane_of = [&](int c) {
+                int tt = min(255, (int)((float)(256 * c + 255) * invC));
+                while (tt < 255 && cstart(tt + 1) <= c)
+                    ++tt;
+                while (cstart(tt) > c)
+                    --tt;
+                return tt;
+            };
+            const int ta = lane_of(b0), tb = lane_of(b1 - 1);
+            const int ca = cstart(ta), cb = cstart(ta + 1);
             if (b0 >= ca && b1 <= cb) {
                 lx = df[0][rho];
                 ly = df[1][rho];
@@ -1305,7 +1318,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
                     lvir = pe[(s0 * 2 + 1) * 256 + ta];
                 }
                 for (int tt = ta + 1; tt <= tb; ++tt) {
-                    if ((((long long)tt * C) >> 8) == (((long long)(tt + 1) * C) >> 8))
+                    if (cstart(tt) == cstart(tt + 1))
                         continue;  // an empty range (fewer chunks than lanes)
                     lx += pf[0][0][tt];
                     ly += pf[0][1][tt];
