@@ -40,7 +40,7 @@ def kernel_source_hash():
 def measured_traffic(bytes_alg_per_launch):
     """HBM bytes per step-kernel launch from the committed counter summary,
     if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_step_c2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_tile_step_c2_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--graph-periods", type=int, default=10)
     ap.add_argument("--energy-every", type=int, default=1000)
     ap.add_argument("--timing-steps", type=int, default=300)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
@@ -220,7 +220,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step (fused forces + Philox noise + compensated update)",
+            "kernel": "k_tile_step (fused forces + Philox noise + compensated update)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -236,14 +236,16 @@ sop_status sop_get_step(const sop_ctx *ctx, int64_t *step);
 sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
 
 /*
- * Same as sop_step, launched kernel by kernel (no graph), back to back,
- * with a pair of HIP events on the context's stream around each kernel
- * group; waits once, after the last launch.
- * Plain schedule: ms_out[0] = mean duration of the fused step kernel,
- * ms_out[1] = mean duration of one list rebuild (all its kernels),
- * ms_out[2] = 1.  Batched schedule: ms_out[0] = mean duration of one
- * persistent launch, ms_out[1] = 0, ms_out[2] = steps per launch.
- * For measurement only.
+ * Kernel timing (measurement only).  Plain schedule: the fused step kernel
+ * and, separately, the list rebuild (all its kernels) are each captured
+ * n_steps times back to back in one HIP graph and timed with a pair of HIP
+ * events on the context's stream around the graph launch; ms_out[0] = mean
+ * step-kernel duration, ms_out[1] = mean rebuild duration, ms_out[2] = 1.
+ * The step launches reuse the current list, so the coordinates and the list
+ * are restored afterwards (the step counter does not move).  Batched schedule:
+ * n_steps steps in persistent launches, each timed with events and waited
+ * for; ms_out[0] = mean duration of one launch, ms_out[1] = 0, ms_out[2] =
+ * steps per launch (these steps advance the state).
  */
 sop_status sop_step_timed(sop_ctx *ctx, int64_t n_steps, double *ms_out);
 

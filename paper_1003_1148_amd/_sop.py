@@ -243,10 +243,11 @@ class Context:
         self._check(lib().sop_step(self.h, int(n)))
 
     def step_timed(self, n):
-        """Advance n steps launch by launch with events around each kernel group.
-
-        Plain schedule: (mean step-kernel ms, mean rebuild ms, 1); batched:
-        (mean persistent-launch ms, 0, steps per launch)."""
+        """Kernel timing. Plain schedule: n back-to-back launches of the step
+        kernel, then n of the list rebuild, each timed as one graph; returns
+        (mean step-kernel ms, mean rebuild ms, 1) and leaves the state as it
+        was. Batched: advances n steps; (mean persistent-launch ms, 0, steps
+        per launch)."""
         ms = np.zeros(3)
         self._check(lib().sop_step_timed(self.h, int(n), _p(ms)))
         return float(ms[0]), float(ms[1]), float(ms[2])

@@ -1157,8 +1157,6 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
         return fail(c, SOP_E_ARG, "bad timing arguments");
     if (c->sticky)
         return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
-    const int L = c->p.list_every;
-    const long long E = c->energy_every;
     hipEvent_t ev[4];
     for (auto &e : ev)
         HIP_TRY(c, hipEventCreate(&e));
@@ -1198,68 +1196,94 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
             HIP_TRY(c, hipGetLastError());
         return out;
     }
-    // back-to-back launches with an event pair around each kernel group;
-    // one synchronisation at the end
+    // Plain schedule: each kernel group is captured n_steps times back to back
+    // in one graph (the step kernel reuses the current list; the rebuild
+    // re-bins the same positions), so the events around the graph launch see
+    // kernel time plus the short gaps between graph nodes.  The positions and
+    // the error word are saved first and restored afterwards: steps on a
+    // stale list may trip the error checks, which must not outlive the timing.
     for (auto &e : ev)
         (void)hipEventDestroy(e);
-    std::vector<hipEvent_t> evs;
-    std::vector<int> kind;  // per event pair: 0 = step, 1 = rebuild
-    auto pair = [&](int k) -> sop_status {
-        for (int u = 0; u < 2; ++u) {
-            hipEvent_t e;
-            HIP_TRY(c, hipEventCreate(&e));
-            evs.push_back(e);
-        }
-        kind.push_back(k);
-        return SOP_OK;
-    };
-    sop_status out = SOP_OK;
-    for (long long q = 0; q < n_steps && out == SOP_OK; ++q) {
-        if (!c->list_valid || c->step % L == 0) {
-            out = pair(1);
-            if (out != SOP_OK)
-                break;
-            (void)hipEventRecord(evs[evs.size() - 2], c->stream);
-            rebuild(c, c->stream, false);
-            (void)hipEventRecord(evs.back(), c->stream);
-            c->list_valid = true;
-        }
-        const bool en = E > 0 && c->step % E == 0;
-        out = pair(0);
-        if (out != SOP_OK)
-            break;
-        (void)hipEventRecord(evs[evs.size() - 2], c->stream);
-        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
-                    c->pulls.empty() ? 0 : 1, en, 0, nullptr, c->step, c->stream);
-        (void)hipEventRecord(evs.back(), c->stream);
-        if (en) {
-            launch_reduce_energy(c->b, c->n_traj, c->stream);
-            c->energy_step = c->step;
-        }
-        c->cur ^= 1;
-        ++c->step;
-    }
-    double sum[2] = {0, 0};
-    long long cnt[2] = {0, 0};
-    if (out == SOP_OK) {
-        hipError_t e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess)
-            out = hip_fail(c, e, "hipStreamSynchronize");
-    }
-    for (size_t k = 0; out == SOP_OK && k < kind.size(); ++k) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]) == hipSuccess) {
-            sum[kind[k]] += ms;
-            cnt[kind[k]]++;
-        }
-    }
-    for (auto &e : evs)
-        (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k)
-        ms_out[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    const long long K = n_steps;
+    ms_out[0] = ms_out[1] = 0.0;
     ms_out[2] = 1.0;
-    if (out == SOP_OK)
-        HIP_TRY(c, hipGetLastError());
+    if (K == 0)
+        return SOP_OK;
+    const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
+    hipStream_t s = c->stream;
+    unsigned err_saved = 0;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(&err_saved, c->b.err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpyAsync(c->b.pos_save, c->b.pos[c->cur], bytes, hipMemcpyDeviceToDevice, s));
+    if (!c->list_valid) {
+        rebuild(c, s, false);
+        c->list_valid = true;
+    }
+    if (!c->cap_stream)
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    sop_status out = SOP_OK;
+    for (int kind = 0; kind < 2 && out == SOP_OK; ++kind) {
+        const int saved = c->cur;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) {
+            out = hip_fail(c, e, "hipStreamBeginCapture");
+            break;
+        }
+        for (long long q = 0; q < K; ++q) {
+            if (kind == 0) {
+                launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
+                            c->pulls.empty() ? 0 : 1, false, 0, nullptr, c->step + q, c->cap_stream);
+                c->cur ^= 1;
+            } else {
+                rebuild(c, c->cap_stream, false);
+            }
+        }
+        e = hipStreamEndCapture(c->cap_stream, &g);
+        c->cur = saved;
+        if (e != hipSuccess) {
+            out = hip_fail(c, e, "hipStreamEndCapture");
+            break;
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            out = hip_fail(c, e, "hipGraphInstantiate");
+            break;
+        }
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first replay warms up
+            (void)hipEventRecord(e0, s);
+            e = hipGraphLaunch(ex, s);
+            (void)hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+        }
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipGraphExecDestroy(ex);
+        if (e != hipSuccess) {
+            out = hip_fail(c, e, "timed graph");
+            break;
+        }
+        ms_out[kind] = (double)ms / (double)K;
+        // back to the saved positions; the next list is built from them
+        HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, s));
+        if (kind == 0) {
+            rebuild(c, s, false);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->list_valid = false;
+    if (out == SOP_OK) {
+        HIP_TRY(c, hipStreamSynchronize(s));
+        HIP_TRY(c, hipMemcpy(c->b.err, &err_saved, sizeof(unsigned), hipMemcpyHostToDevice));
+    }
     return out;
 }
 

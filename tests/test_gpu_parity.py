@@ -329,3 +329,19 @@ def test_coincident_residues_are_reported(P):
     assert e.value.name == "SOP_E_NONFINITE"
     with pytest.raises(P.SopError):
         c.set_coordinates(np.full_like(x, np.nan))   # rejected on the host
+
+
+def test_step_timing_leaves_the_state(P):
+    """Timing runs the kernels on a copy of the state and restores it."""
+    s = cfg("c1")
+    a = ctx_for(P, s)
+    a.step(20)
+    x0 = a.get_coordinates()
+    k_ms, rb_ms, one = a.step_timed(40)
+    assert k_ms > 0.0 and rb_ms > 0.0 and one == 1.0
+    assert a.get_step() == 20
+    assert np.array_equal(a.get_coordinates(), x0)
+    a.step(10)
+    b = ctx_for(P, s)
+    b.step(30)
+    assert np.array_equal(a.get_coordinates(), b.get_coordinates())
