@@ -369,8 +369,10 @@ template <int TILE>
 constexpr int stage_max() { return TILE >= 256 ? 2048 : 1024; }
 
 // Candidate residues (the residues of the cells around a tile) held in LDS
-// at once during a rebuild; more are taken in windows of whole cells.
-constexpr int CAND_WIN = 1024;
+// at once during a rebuild; more are taken in windows of whole cells.  Small
+// tiles keep less so that five workgroups fit a CU.
+template <int TILE>
+constexpr int cand_win() { return TILE == 64 ? 768 : 1024; }
 // Distinct cells around one tile, and the bits of its open-addressing table.
 template <int TILE>
 constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640); }
@@ -448,7 +450,7 @@ constexpr unsigned CODE_EXTRA = 0x40000000u;    // | index among the extra slots
 //  1. The cells around the tile's residues (each residue's own and adjacent
 //     cells) go into an LDS hash table and are sorted by cell index; their
 //     residues, sorted by (cell, residue index), are the tile's candidates.
-//  2. Per window of whole cells (at most CAND_WIN candidates, usually one
+//  2. Per window of whole cells (at most cand_win candidates, usually one
 //     window): candidates go to LDS; each residue is tested against them 32
 //     at a time with the single-precision predicate r < r_list of
 //     Algorithm 3, one bit per candidate, part q taking a contiguous range
@@ -465,7 +467,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
 {
     constexpr int NT = 256, NLB = NT / TILE;
     constexpr int SM = stage_max<TILE>();
-    constexpr int CM = CAND_WIN;
+    constexpr int CM = cand_win<TILE>();
     constexpr int NW = CM / 32;
     constexpr int CELLS_MAX = cells_max<TILE>();
     constexpr int CHASH_BITS = chash_bits<TILE>();
@@ -724,16 +726,17 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
                 }
             unsigned word = 0u;
             if (__any(reach)) {
-                // branch-free: eight LDS reads in flight, then the tests; the
+                // branch-free: BB LDS reads in flight, then the tests; the
                 // window's tail and inactive lanes are masked afterwards
+                constexpr int BB = TILE == 64 ? 4 : 8;
 #pragma unroll 1
-                for (int k0 = 0; k0 < 32; k0 += 8) {
-                    float4 c8[8];
+                for (int k0 = 0; k0 < 32; k0 += BB) {
+                    float4 c8[BB];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
+                    for (int u = 0; u < BB; ++u)
                         c8[u] = cand[32 * w + k0 + u];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < BB; ++u) {
                         bool pass = within_cutoff(p, c8[u], a.rc2);
                         if (MULTI) {
                             const int j = __float_as_int(c8[u].w);
