@@ -32,6 +32,7 @@ struct sop_ctx {
     std::vector<int> pull_slot;
     std::vector<int4> traj_cell;
     std::vector<int> tiles[3];  // plain: first residue of each tile (+ n) for tiles of 64, 128, 256
+    std::vector<int> chunk_lo, chunk_first;  // energy reduction chunks
     TipDev tip{};
 
     // schedule: plain (kernel per step) or batched (persistent packs)
@@ -169,6 +170,10 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.stream_ids = (unsigned *)take(T * sizeof(unsigned));
     d.res_offsets = (long long *)take((T + 1) * sizeof(long long));
     d.res_energy = (double *)take(n * RES_E * sizeof(double));
+    d.n_chunks = (int)c->chunk_lo.size() - 1;
+    d.chunk_lo = (int *)take(c->chunk_lo.size() * sizeof(int));
+    d.chunk_first = (int *)take(c->chunk_first.size() * sizeof(int));
+    d.chunk_sum = (double *)take((size_t)std::max(d.n_chunks, 1) * RES_E * sizeof(double));
     d.energy = (double *)take(T * SOP_NTERMS * sizeof(double));
     d.f_ext = (double *)take(T * sizeof(double));
     d.fout = (float4 *)take(n * sizeof(float4));
@@ -614,6 +619,20 @@ sop_status sop_load_topology(sop_ctx *c, int32_t n_traj, const int64_t *res_offs
         }
         tl.push_back((int)n);
     }
+    // energy-reduction chunks: ECHUNK residues, never across trajectories
+    c->chunk_lo.clear();
+    c->chunk_first.clear();
+    for (int t = 0; t < n_traj; ++t) {
+        c->chunk_first.push_back((int)c->chunk_lo.size());
+        const long long a0 = res_offsets[t], b0 = res_offsets[t + 1];
+        for (long long r = a0; r < b0 || r == a0; r += ECHUNK) {
+            c->chunk_lo.push_back((int)r);
+            if (b0 == a0)
+                break;
+        }
+    }
+    c->chunk_first.push_back((int)c->chunk_lo.size());
+    c->chunk_lo.push_back((int)n);
     c->pulls.clear();
     c->pull_slot.assign(n, -1);
     c->tip = TipDev{};
@@ -855,6 +874,10 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
         HIP_TRY(c, hipMemsetAsync(b.stage_cnt, 0, n_tiles_max * sizeof(int), s));
     }
     HIP_TRY(c, hipMemsetAsync(b.res_energy, 0, n * RES_E * sizeof(double), s));
+    HIP_TRY(c, hipMemcpyAsync(b.chunk_lo, c->chunk_lo.data(), c->chunk_lo.size() * sizeof(int),
+                              hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(b.chunk_first, c->chunk_first.data(), c->chunk_first.size() * sizeof(int),
+                              hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(b.energy, 0, (size_t)c->n_traj * SOP_NTERMS * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.f_ext, 0, (size_t)c->n_traj * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.err, 0, sizeof(unsigned), s));

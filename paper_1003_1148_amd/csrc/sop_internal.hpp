@@ -89,6 +89,10 @@ struct DevBufs {
     unsigned *stream_ids;    // per trajectory
     long long *res_offsets;  // n_traj + 1
     double *res_energy;      // n_res * RES_E
+    int *chunk_lo;           // energy reduction: first residue of each chunk (+ n_res)
+    int *chunk_first;        // energy reduction: first chunk of each trajectory (+ n_chunks)
+    double *chunk_sum;       // energy reduction: RES_E partial sums per chunk
+    int n_chunks;
     double *energy;          // n_traj * SOP_NTERMS, last record
     double *f_ext;           // n_traj, last record
     float4 *fout;            // forces (compute_forces), noise samples
@@ -113,6 +117,8 @@ void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int tile, con
 void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode,
                  const long long *step_base, long long step_off, hipStream_t s);
+// Residues per chunk of the energy reduction (chunks never span trajectories).
+constexpr int ECHUNK = 1024;
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
 // Batched ensemble: n_steps steps of every pack in one launch (mode 1: one
 // force evaluation, no update).

@@ -1566,19 +1566,21 @@ __global__ void k_add_step(long long *base, long long k)
 }
 
 // One workgroup per trajectory: double sums of the per-residue records.
-__global__ __launch_bounds__(WG) void k_reduce_energy(const double *__restrict__ res_energy,
-                                                      const long long *__restrict__ offs,
-                                                      double *__restrict__ energy,
-                                                      double *__restrict__ f_ext)
+// Per-trajectory FP64 energy and virial sums in two fixed-order levels:
+// one workgroup per chunk of at most ECHUNK residues of one trajectory, then
+// one lane per trajectory over its chunks in order.
+__global__ __launch_bounds__(WG) void k_reduce_chunks(const double *__restrict__ res_energy,
+                                                      const int *__restrict__ chunk_lo,
+                                                      double *__restrict__ chunk_sum)
 {
     __shared__ double part[WG / 64][RES_E];
-    const int t = blockIdx.x;
-    const long long a = offs[t], b = offs[t + 1];
+    const int ch = blockIdx.x;
+    const int a = chunk_lo[ch], b = chunk_lo[ch + 1];
     double s[RES_E] = {0, 0, 0, 0, 0, 0};
-    for (long long i = a + threadIdx.x; i < b; i += WG)
+    for (int i = a + threadIdx.x; i < b; i += WG)
 #pragma unroll
         for (int k = 0; k < RES_E; ++k)
-            s[k] += res_energy[i * RES_E + k];
+            s[k] += res_energy[(size_t)i * RES_E + k];
 #pragma unroll
     for (int k = 0; k < RES_E; ++k)
         for (int m = 32; m >= 1; m >>= 1)
@@ -1587,16 +1589,37 @@ __global__ __launch_bounds__(WG) void k_reduce_energy(const double *__restrict__
         for (int k = 0; k < RES_E; ++k)
             part[threadIdx.x >> 6][k] = s[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < RES_E; ++k) {
-            double v = 0.0;
-            for (int w = 0; w < WG / 64; ++w)
-                v += part[w][k];
-            if (k < SOP_NTERMS)
-                energy[(size_t)t * SOP_NTERMS + k] = v;
-            else
-                f_ext[t] = v;
-        }
+    if (threadIdx.x < RES_E) {
+        double v = 0.0;
+        for (int w = 0; w < WG / 64; ++w)
+            v += part[w][threadIdx.x];
+        chunk_sum[(size_t)ch * RES_E + threadIdx.x] = v;
+    }
+}
+
+// One wave per trajectory: lane l takes chunks l, l + 64, ... in order, then
+// a fixed butterfly over the lanes.
+__global__ __launch_bounds__(WG) void k_reduce_energy(const double *__restrict__ chunk_sum,
+                                                      const int *__restrict__ chunk_first, int n_traj,
+                                                      double *__restrict__ energy, double *__restrict__ f_ext)
+{
+    const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    if (t >= n_traj)
+        return;  // uniform over the wave
+    double v[RES_E] = {0, 0, 0, 0, 0, 0};
+    for (int ch = chunk_first[t] + lane; ch < chunk_first[t + 1]; ch += 64)
+#pragma unroll
+        for (int k = 0; k < RES_E; ++k)
+            v[k] += chunk_sum[(size_t)ch * RES_E + k];
+#pragma unroll
+    for (int k = 0; k < RES_E; ++k)
+        for (int m = 32; m >= 1; m >>= 1)
+            v[k] += __shfl_xor(v[k], m, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < SOP_NTERMS; ++k)
+            energy[(size_t)t * SOP_NTERMS + k] = v[k];
+        f_ext[t] = v[SOP_NTERMS];
     }
 }
 
@@ -1789,8 +1812,10 @@ void launch_add_step(long long *base, long long k, hipStream_t s)
 
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_energy, dim3(n_traj), dim3(WG), 0, s, b.res_energy, b.res_offsets,
-                       b.energy, b.f_ext);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(b.n_chunks), dim3(WG), 0, s, b.res_energy, b.chunk_lo,
+                       b.chunk_sum);
+    hipLaunchKernelGGL(k_reduce_energy, dim3(blocks_for((long long)n_traj * 64, WG)), dim3(WG), 0, s,
+                       b.chunk_sum, b.chunk_first, n_traj, b.energy, b.f_ext);
 }
 
 void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long long step, uint4 *words,
