@@ -1403,7 +1403,7 @@ struct BatchArgs {
     const unsigned *stream_ids;
     const int *pull_slot;
     const PullDev *pulls;
-    unsigned short *list;     // pack p: entry k of residue base+t at base*cap + k*n + t
+    unsigned short *list;     // pack p: entry k of residue base+t at base*cap + ((k/4)*n + t)*4 + k%4
     int *list_cnt;
     double *energy;
     double *f_ext;
@@ -1433,10 +1433,12 @@ __device__ __forceinline__ double traj_sum(double *red, int t, bool act, double 
 }
 
 template <int WGS, int MODE>
-__global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
+__global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
 {
-    __shared__ float4 sh[2 * WGS];
+    constexpr int BT = 4;  // bonded/native entries per residue kept in LDS
+    __shared__ float4 sh[2 * WGS + 2];  // {hi, lo} per residue; slot WGS: the far-away empty slot
     __shared__ double red[WGS];
+    __shared__ int2 tsh[BT][WGS];       // {local partner, r0 bits} of the first BT entries
     const int p = blockIdx.x;
     const int base = a.pack_res[p];
     const int n = a.pack_res[p + 1] - base;
@@ -1458,9 +1460,23 @@ __global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
         sh[2 * t] = hi;
         sh[2 * t + 1] = lo;
     }
+    if (t == 0) {
+        sh[2 * WGS] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+        sh[2 * WGS + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
+    const int nt0 = min(ntop, BT);
+#pragma unroll
+    for (int u = 0; u < BT; ++u) {
+        const bool has = act && u < ntop;
+        const float2 te = has ? a.tent[row.x + u] : make_float2(0.0f, 1.0f);
+        tsh[u][t] = make_int2(has ? __float_as_int(te.x) - base : -1, __float_as_int(te.y));
+    }
     __syncthreads();
-    const int nb = row.y & 4095, nn = row.y >> 12;
-    unsigned short *lrow = a.list + (size_t)base * a.cap + t;
+    // rows in chunks of 4 slots: chunk c of residue t at chunk c * n + t of the pack's block
+    const int capc = a.cap >> 2;
+    uint2 *lrow = reinterpret_cast<uint2 *>(a.list + (size_t)base * a.cap) + t;
+    unsigned short *lrow16 = a.list + (size_t)base * a.cap + (size_t)t * 4;
     const long long s0 = (a.step_base ? *a.step_base : 0) + a.step_off;
     const PairConsts kc = pair_consts(a.c);
     const int traj = __float_as_int(lo.w);
@@ -1470,19 +1486,25 @@ __global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
         const long long step = s0 + q;
         if ((q == 0 && a.stale) || step % a.list_every == 0) {
             if (act) {
+                // Algorithm 3 over the trajectory: r < r_list, not bonded or native
                 cnt = 0;
                 for (int j = tlo; j < thi; ++j) {
                     if (j == t || !within_cutoff(hi, sh[2 * j], a.rc2))
                         continue;
                     bool ex = false;
-                    for (int e = 0; e < nb + nn; ++e)
+                    for (int u = 0; u < nt0; ++u)
+                        ex |= tsh[u][t].x == j;
+                    for (int e = BT; e < ntop; ++e)
                         ex |= (__float_as_int(a.tent[row.x + e].x) - base) == j;
                     if (ex)
                         continue;
                     if (cnt < a.cap)
-                        lrow[(size_t)cnt * n] = (unsigned short)j;
+                        lrow16[(size_t)(cnt >> 2) * 4 * n + (cnt & 3)] = (unsigned short)j;
                     ++cnt;
                 }
+                // pad the last chunk with the empty slot (its term is exactly zero)
+                for (int k = cnt; k < ((cnt + 3) & ~3) && k < a.cap; ++k)
+                    lrow16[(size_t)(k >> 2) * 4 * n + (k & 3)] = (unsigned short)WGS;
                 if (cnt > a.cap)
                     atomicOr(a.err, ERR_OVERFLOW);
                 a.list_cnt[i] = cnt;
@@ -1493,29 +1515,49 @@ __global__ __launch_bounds__(WGS) void k_batch(BatchArgs a)
         bool broken = false;
         double e_x = 0.0, f_rep = 0.0;
         if (act) {
-            for (int e = 0; e < nb; ++e) {
-                const float2 tt = a.tent[row.x + e];
-                const int j = __float_as_int(tt.x) - base;
-                add_fene(A, hi, lo, sh[2 * j], sh[2 * j + 1], tt.y, kc, rec, broken);
+            // list partners: chunks of 4, four chunks in flight, loads clamped
+            // into the row's region so that no branch sits between them
+            const int nch = (min(cnt, a.cap) + 3) >> 2;
+            const int last = capc - 1;
+            auto fetch = [&](int c) -> uint2 { return lrow[(size_t)min(c, last) * n]; };
+            auto chunk = [&](const uint2 &w) {
+                float4 ph[4], pl[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = (int)(((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu);
+                    ph[u] = sh[2 * j];
+                    pl[u] = sh[2 * j + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    add_repulsive(A, hi, lo, ph[u], pl[u], kc, rec);
+            };
+            uint2 q0 = fetch(0), q1 = fetch(1);
+            // bonded and native partners while the chunks arrive
+            for (int e = 0; e < ntop; ++e) {
+                int j;
+                float r0;
+                if (e < BT) {
+                    const int2 v = tsh[e][t];
+                    j = v.x;
+                    r0 = __int_as_float(v.y);
+                } else {
+                    const float2 te = a.tent[row.x + e];
+                    j = __float_as_int(te.x) - base;
+                    r0 = te.y;
+                }
+                if (e < nb)
+                    add_fene(A, hi, lo, sh[2 * j], sh[2 * j + 1], r0, kc, rec, broken);
+                else
+                    add_native(A, hi, lo, sh[2 * j], sh[2 * j + 1], r0, kc, rec);
             }
-            for (int e = nb; e < nb + nn; ++e) {
-                const float2 tt = a.tent[row.x + e];
-                const int j = __float_as_int(tt.x) - base;
-                add_native(A, hi, lo, sh[2 * j], sh[2 * j + 1], tt.y, kc, rec);
-            }
-            const int m = min(cnt, a.cap);
-            int k = 0;
-            for (; k + 4 <= m; k += 4) {
-                const int j0 = lrow[(size_t)(k + 0) * n], j1 = lrow[(size_t)(k + 1) * n];
-                const int j2 = lrow[(size_t)(k + 2) * n], j3 = lrow[(size_t)(k + 3) * n];
-                add_repulsive(A, hi, lo, sh[2 * j0], sh[2 * j0 + 1], kc, rec);
-                add_repulsive(A, hi, lo, sh[2 * j1], sh[2 * j1 + 1], kc, rec);
-                add_repulsive(A, hi, lo, sh[2 * j2], sh[2 * j2 + 1], kc, rec);
-                add_repulsive(A, hi, lo, sh[2 * j3], sh[2 * j3 + 1], kc, rec);
-            }
-            for (; k < m; ++k) {
-                const int j = lrow[(size_t)k * n];
-                add_repulsive(A, hi, lo, sh[2 * j], sh[2 * j + 1], kc, rec);
+            // two chunks in flight
+            for (int c = 0; c < nch; c += 2) {
+                chunk(q0);
+                q0 = fetch(c + 2);
+                if (c + 1 < nch)
+                    chunk(q1);
+                q1 = fetch(c + 3);
             }
             add_external(A, e_x, f_rep, hi, lo, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
                          a.tip, rec, a.err);
