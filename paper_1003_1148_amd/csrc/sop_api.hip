@@ -1004,7 +1004,7 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
             const long long base = c->pack_res[pk], m = c->pack_res[pk + 1] - base;
             for (long long t = 0; t < m; ++t)
                 for (int k = 0; k < std::min(cnt[base + t], c->cap); ++k) {
-                    const int j = (int)(base + list[(size_t)base * c->cap + ((size_t)(k >> 2) * m + t) * 4 + (k & 3)]);
+                    const int j = (int)(base + list[(size_t)(base + t) * c->cap + k]);
                     if (base + t < j)
                         pairs.push_back({(int)(base + t), j});
                 }

@@ -1403,7 +1403,7 @@ struct BatchArgs {
     const unsigned *stream_ids;
     const int *pull_slot;
     const PullDev *pulls;
-    unsigned short *list;     // pack p: entry k of residue base+t at base*cap + ((k/4)*n + t)*4 + k%4
+    unsigned short *list;     // entry k of residue i at i*cap + k
     int *list_cnt;
     double *energy;
     double *f_ext;
@@ -1432,13 +1432,24 @@ __device__ __forceinline__ double traj_sum(double *red, int t, bool act, double 
     return s;
 }
 
+// Batched schedule: the list partners of a residue are summed by one lane,
+// chunk by chunk in row order, so the sum does not depend on the lane or on
+// the packing. Which lane sums which row is chosen at each list rebuild by a
+// counting sort on the row length (longest first), so the lanes of a wave
+// run loops of about the same length.
+constexpr int NBUCKET = 64;
+
 template <int WGS, int MODE>
 __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
 {
     constexpr int BT = 4;  // bonded/native entries per residue kept in LDS
-    __shared__ float4 sh[2 * WGS + 2];  // {hi, lo} per residue; slot WGS: the far-away empty slot
-    __shared__ double red[WGS];
+    __shared__ float4 shh[WGS + 1];     // hi per residue; slot WGS: the far-away empty slot
+    __shared__ float4 shl[WGS + 1];     // lo per residue
+    __shared__ double red[WGS];         // trajectory sums
     __shared__ int2 tsh[BT][WGS];       // {local partner, r0 bits} of the first BT entries
+    __shared__ int perm[WGS];           // row summed by each lane: residue | chunks << 16
+    __shared__ float lsum[3][WGS];      // list force of each residue
+    __shared__ int hist[NBUCKET];
     const int p = blockIdx.x;
     const int base = a.pack_res[p];
     const int n = a.pack_res[p + 1] - base;
@@ -1457,12 +1468,12 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         thi = a.traj_hi[i] - base;
         row = a.trow[i];
         cnt = a.list_cnt[i];
-        sh[2 * t] = hi;
-        sh[2 * t + 1] = lo;
+        shh[t] = hi;
+        shl[t] = lo;
     }
     if (t == 0) {
-        sh[2 * WGS] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
-        sh[2 * WGS + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        shh[WGS] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+        shl[WGS] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
     const int nt0 = min(ntop, BT);
@@ -1472,68 +1483,156 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         const float2 te = has ? a.tent[row.x + u] : make_float2(0.0f, 1.0f);
         tsh[u][t] = make_int2(has ? __float_as_int(te.x) - base : -1, __float_as_int(te.y));
     }
-    __syncthreads();
-    // rows in chunks of 4 slots: chunk c of residue t at chunk c * n + t of the pack's block
+    // rows are residue-major: entry k of residue r at (base + r) cap + k
     const int capc = a.cap >> 2;
-    uint2 *lrow = reinterpret_cast<uint2 *>(a.list + (size_t)base * a.cap) + t;
-    unsigned short *lrow16 = a.list + (size_t)base * a.cap + (size_t)t * 4;
+    unsigned short *lrow16 = a.list + (size_t)i * a.cap;
+    const uint2 *lp = reinterpret_cast<const uint2 *>(a.list + (size_t)base * a.cap);
     const long long s0 = (a.step_base ? *a.step_base : 0) + a.step_off;
     const PairConsts kc = pair_consts(a.c);
     const int traj = __float_as_int(lo.w);
     const unsigned stream = act ? a.stream_ids[traj] : 0u;
 
+    // lane -> row assignment: counting sort of the rows by chunk count,
+    // longest first (ties in any order; the sums do not depend on it)
+    int my = 0;  // residue | chunks << 16 of the row this lane sums
+    auto assign = [&]() {
+        const int nch = act ? (min(cnt, a.cap) + 3) >> 2 : 0;
+        const int key = NBUCKET - 1 - min(nch, NBUCKET - 1);
+        if (t < NBUCKET)
+            hist[t] = 0;
+        __syncthreads();
+        if (act)
+            atomicAdd(&hist[key], 1);
+        __syncthreads();
+        if (t < 64) {  // one wave scans the buckets
+            const int v = t < NBUCKET ? hist[t] : 0;
+            int x = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (t >= o)
+                    x += y;
+            }
+            if (t < NBUCKET)
+                hist[t] = x - v;
+        }
+        __syncthreads();
+        if (act)
+            perm[atomicAdd(&hist[key], 1)] = t | (nch << 16);
+        __syncthreads();
+        my = t < n ? perm[t] : 0;
+    };
+    __syncthreads();
+    if (!(a.stale || s0 % a.list_every == 0))
+        assign();
+
     for (int q = 0; q < a.n_steps; ++q) {
         const long long step = s0 + q;
         if ((q == 0 && a.stale) || step % a.list_every == 0) {
             if (act) {
-                // Algorithm 3 over the trajectory: r < r_list, not bonded or native
+                // Algorithm 3 over the trajectory: r < r_list, not bonded or
+                // native. Candidates are tested 32 at a time into a bit word;
+                // the row is written four entries (one 8-byte chunk) at a time.
+                int ex[BT];
+#pragma unroll
+                for (int u = 0; u < BT; ++u)
+                    ex[u] = tsh[u][t].x;
+                uint2 *rowp = reinterpret_cast<uint2 *>(lrow16);
+                unsigned w_lo = 0u, w_hi = 0u;
                 cnt = 0;
-                for (int j = tlo; j < thi; ++j) {
-                    if (j == t || !within_cutoff(hi, sh[2 * j], a.rc2))
-                        continue;
-                    bool ex = false;
-                    for (int u = 0; u < nt0; ++u)
-                        ex |= tsh[u][t].x == j;
+                for (int j0 = tlo; j0 < thi; j0 += 32) {
+                    unsigned m = 0u;
+#pragma unroll 8
+                    for (int u = 0; u < 32; ++u) {
+                        const int j = min(j0 + u, thi - 1);
+                        m |= within_cutoff(hi, shh[j], a.rc2) ? (1u << u) : 0u;
+                    }
+                    if (thi - j0 < 32)
+                        m &= (1u << (thi - j0)) - 1u;
+                    unsigned x = 0u;  // the residue itself and its bonded/native partners
+                    auto drop = [&](int j) {
+                        const unsigned d = (unsigned)(j - j0);
+                        x |= d < 32u ? (1u << d) : 0u;
+                    };
+                    drop(t);
+#pragma unroll
+                    for (int u = 0; u < BT; ++u)
+                        drop(ex[u]);
                     for (int e = BT; e < ntop; ++e)
-                        ex |= (__float_as_int(a.tent[row.x + e].x) - base) == j;
-                    if (ex)
-                        continue;
-                    if (cnt < a.cap)
-                        lrow16[(size_t)(cnt >> 2) * 4 * n + (cnt & 3)] = (unsigned short)j;
-                    ++cnt;
+                        drop(__float_as_int(a.tent[row.x + e].x) - base);
+                    m &= ~x;
+                    while (m) {
+                        const unsigned v = (unsigned)(j0 + __builtin_ctz(m));
+                        m &= m - 1u;
+                        const int sl = cnt & 3;
+                        if (sl == 0)
+                            w_lo = v;
+                        else if (sl == 1)
+                            w_lo |= v << 16;
+                        else if (sl == 2)
+                            w_hi = v;
+                        else
+                            w_hi |= v << 16;
+                        ++cnt;
+                        if ((cnt & 3) == 0 && cnt <= a.cap)
+                            rowp[(cnt >> 2) - 1] = make_uint2(w_lo, w_hi);
+                    }
                 }
                 // pad the last chunk with the empty slot (its term is exactly zero)
-                for (int k = cnt; k < ((cnt + 3) & ~3) && k < a.cap; ++k)
-                    lrow16[(size_t)(k >> 2) * 4 * n + (k & 3)] = (unsigned short)WGS;
+                const int sl = cnt & 3;
+                if (sl != 0 && cnt < a.cap) {
+                    const unsigned e2 = (unsigned)WGS | ((unsigned)WGS << 16);
+                    if (sl == 1)
+                        rowp[cnt >> 2] = make_uint2(w_lo | ((unsigned)WGS << 16), e2);
+                    else if (sl == 2)
+                        rowp[cnt >> 2] = make_uint2(w_lo, e2);
+                    else
+                        rowp[cnt >> 2] = make_uint2(w_lo, w_hi | ((unsigned)WGS << 16));
+                }
                 if (cnt > a.cap)
                     atomicOr(a.err, ERR_OVERFLOW);
                 a.list_cnt[i] = cnt;
             }
+            assign();  // its barriers also publish the rows written above
         }
-        Acc A;  // energy sums are only accumulated on record steps
         const bool rec = MODE == 1 || (a.energy_every > 0 && step % a.energy_every == 0);
-        bool broken = false;
-        double e_x = 0.0, f_rep = 0.0;
-        if (act) {
-            // list partners: chunks of 4, four chunks in flight, loads clamped
-            // into the row's region so that no branch sits between them
-            const int nch = (min(cnt, a.cap) + 3) >> 2;
-            const int last = capc - 1;
-            auto fetch = [&](int c) -> uint2 { return lrow[(size_t)min(c, last) * n]; };
-            auto chunk = [&](const uint2 &w) {
-                float4 ph[4], pl[4];
+        {
+            // ---- list partners (forces) of the row this lane was given ----
+            const int r = my & 0xffff, nch = my >> 16;
+            const float4 ph = shh[r], pl = shl[r];
+            const uint2 *rp = lp + (size_t)r * capc;
+            float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+            uint2 w0 = rp[0], w1 = rp[min(1, max(nch - 1, 0))];
+            for (int c = 0; c < nch; ++c) {
+                const uint2 w = w0;
+                w0 = w1;
+                w1 = rp[min(c + 2, nch - 1)];
+                float4 qh[4], ql[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int j = (int)(((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu);
-                    ph[u] = sh[2 * j];
-                    pl[u] = sh[2 * j + 1];
+                    qh[u] = shh[j];
+                    ql[u] = shl[j];
                 }
+                Acc L;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive(A, hi, lo, ph[u], pl[u], kc, rec);
-            };
-            uint2 q0 = fetch(0), q1 = fetch(1);
-            // bonded and native partners while the chunks arrive
+                    add_repulsive(L, ph, pl, qh[u], ql[u], kc, false);
+                fx += L.fx;
+                fy += L.fy;
+                fz += L.fz;
+            }
+            if (t < n) {
+                lsum[0][r] = fx;
+                lsum[1][r] = fy;
+                lsum[2][r] = fz;
+            }
+        }
+        Acc A;  // energy sums are only accumulated on record steps
+        bool broken = false;
+        double e_x = 0.0, f_rep = 0.0;
+        if (act) {
+            // bonded and native partners
             for (int e = 0; e < ntop; ++e) {
                 int j;
                 float r0;
@@ -1547,22 +1646,30 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                     r0 = te.y;
                 }
                 if (e < nb)
-                    add_fene(A, hi, lo, sh[2 * j], sh[2 * j + 1], r0, kc, rec, broken);
+                    add_fene(A, hi, lo, shh[j], shl[j], r0, kc, rec, broken);
                 else
-                    add_native(A, hi, lo, sh[2 * j], sh[2 * j + 1], r0, kc, rec);
-            }
-            // two chunks in flight
-            for (int c = 0; c < nch; c += 2) {
-                chunk(q0);
-                q0 = fetch(c + 2);
-                if (c + 1 < nch)
-                    chunk(q1);
-                q1 = fetch(c + 3);
+                    add_native(A, hi, lo, shh[j], shl[j], r0, kc, rec);
             }
             add_external(A, e_x, f_rep, hi, lo, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
                          a.tip, rec, a.err);
             if (broken)
                 atomicOr(a.err, ERR_FENE);
+            if (rec) {
+                // record steps: the repulsive energy and virial over the own row
+                Acc E;
+                for (int k = 0; k < min(cnt, a.cap); ++k) {
+                    const int j = lrow16[k];
+                    add_repulsive(E, hi, lo, shh[j], shl[j], kc, true);
+                }
+                A.e_r = E.e_r;
+                A.vir += E.vir;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            A.fx += lsum[0][t];
+            A.fy += lsum[1][t];
+            A.fz += lsum[2][t];
         }
         if (rec) {
             // each internal pair appears in both partners' rows
@@ -1583,16 +1690,11 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 a.fout[i] = make_float4(A.fx, A.fy, A.fz, 0.0f);
             return;
         }
-        float4 nh4 = hi, nl4 = lo;
-        if (act)
-            langevin_update(nh4, nl4, A, step, stream, a.c, a.err);
-        __syncthreads();
         if (act) {
-            sh[2 * t] = nh4;
-            sh[2 * t + 1] = nl4;
+            langevin_update(hi, lo, A, step, stream, a.c, a.err);
+            shh[t] = hi;
+            shl[t] = lo;
         }
-        hi = nh4;
-        lo = nl4;
         __syncthreads();
     }
     if (MODE == 0 && act) {
