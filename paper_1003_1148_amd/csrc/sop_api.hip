@@ -42,7 +42,8 @@ struct sop_ctx {
     long long energy_every = 0;
     int batch_wg_req = 0, batch_wg = 1024, batch_steps = 100;
     long long max_len = 0;           // longest trajectory
-    std::vector<int> pack_res;       // batched: first residue of each pack
+    std::vector<int> pack_off;       // batched: first slot of each pack
+    std::vector<int> slot_res;       // batched: residue of each slot
     hipGraphExec_t bgraphs[2] = {nullptr, nullptr};  // batched launch graphs by layer parity
 
     // device state
@@ -153,7 +154,8 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.topo2 = (uint2 *)take(topo2_elems * sizeof(uint2));
     d.stage = (int *)take(stage_elems * sizeof(int));
     d.stage_cnt = (int *)take(n_tiles_max * sizeof(int));
-    d.pack_res = (int *)take((T + 1) * sizeof(int));
+    d.pack_off = (int *)take((T + 1) * sizeof(int));
+    d.slot_res = (int *)take(n * sizeof(int));
     d.pos_save = (float4 *)take(2 * n * sizeof(float4));
     d.cell_count = (int *)take(ncell * sizeof(int));
     d.cells = (float4 *)take(ncell * CELL_CAP * sizeof(float4));
@@ -207,20 +209,51 @@ void destroy_graphs(sop_ctx *c)
         }
 }
 
-// Greedy packing of consecutive trajectories into workgroups of `wg` residues.
+// Packs of whole trajectories for the batched schedule: first-fit
+// decreasing by length (ties by index) into workgroups of `wg` residues, so
+// packs start with the longest trajectories and all but one are more than
+// half full. Inside a pack the trajectories keep their index order, residues
+// consecutive. The results do not depend on the packing.
 void make_packs(sop_ctx *c)
 {
-    c->pack_res.assign(1, 0);
-    long long fill = 0;
-    for (int t = 0; t < c->n_traj; ++t) {
-        const long long len = c->res_offsets[t + 1] - c->res_offsets[t];
-        if (fill > 0 && fill + len > c->batch_wg) {
-            c->pack_res.push_back((int)c->res_offsets[t]);
-            fill = 0;
+    const int T = c->n_traj, wg = c->batch_wg;
+    std::vector<int> order(T);
+    for (int t = 0; t < T; ++t)
+        order[t] = t;
+    auto len = [&](int t) { return c->res_offsets[t + 1] - c->res_offsets[t]; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return len(x) > len(y); });
+    std::vector<long long> room;
+    std::vector<std::vector<int>> members;
+    for (int t : order) {
+        size_t k = 0;
+        while (k < room.size() && room[k] < len(t))
+            ++k;
+        if (k == room.size()) {
+            room.push_back(wg);
+            members.emplace_back();
         }
-        fill += len;
+        room[k] -= len(t);
+        members[k].push_back(t);
     }
-    c->pack_res.push_back((int)c->n_res);
+    c->pack_off.assign(1, 0);
+    c->slot_res.clear();
+    c->slot_res.reserve((size_t)c->n_res);
+    for (auto &m : members) {
+        std::sort(m.begin(), m.end());
+        for (int t : m)
+            for (long long r = c->res_offsets[t]; r < c->res_offsets[t + 1]; ++r)
+                c->slot_res.push_back((int)r);
+        c->pack_off.push_back((int)c->slot_res.size());
+    }
+}
+
+sop_status upload_packs(sop_ctx *c)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->b.pack_off, c->pack_off.data(), c->pack_off.size() * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->b.slot_res, c->slot_res.data(), c->slot_res.size() * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+    return SOP_OK;
 }
 
 int pick_batch_wg(const sop_ctx *c)
@@ -230,7 +263,7 @@ int pick_batch_wg(const sop_ctx *c)
     return c->max_len <= 256 ? 256 : (c->max_len <= 512 ? 512 : 1024);
 }
 
-int n_packs(const sop_ctx *c) { return (int)c->pack_res.size() - 1; }
+int n_packs(const sop_ctx *c) { return (int)c->pack_off.size() - 1; }
 
 StepConsts step_consts(const sop_ctx *c)
 {
@@ -767,8 +800,9 @@ sop_status sop_set_batch(sop_ctx *c, int32_t wg, int32_t steps)
     if (c->bound && c->schedule == SOP_SCHEDULE_BATCHED) {
         c->batch_wg = pick_batch_wg(c);
         make_packs(c);
-        HIP_TRY(c, hipMemcpyAsync(c->b.pack_res, c->pack_res.data(), c->pack_res.size() * sizeof(int),
-                                  hipMemcpyHostToDevice, c->stream));
+        const sop_status st = upload_packs(c);
+        if (st != SOP_OK)
+            return st;
         c->list_valid = false;  // the list layout follows the packs
     }
     return SOP_OK;
@@ -837,8 +871,9 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
         if (c->batch_wg < c->max_len)
             return fail(c, SOP_E_ARG, "batch workgroup smaller than the longest trajectory");
         make_packs(c);
-        HIP_TRY(c, hipMemcpyAsync(c->b.pack_res, c->pack_res.data(), c->pack_res.size() * sizeof(int),
-                                  hipMemcpyHostToDevice, c->stream));
+        const sop_status st = upload_packs(c);
+        if (st != SOP_OK)
+            return st;
     }
     const DevBufs &b = c->b;
     const size_t n = (size_t)c->n_res;
@@ -1000,14 +1035,20 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
         std::vector<unsigned short> list((size_t)n * c->cap);
         HIP_TRY(c, hipMemcpy(list.data(), c->b.list16, list.size() * sizeof(unsigned short),
                              hipMemcpyDeviceToHost));
+        // rows hold local slots of the residue's pack
         for (int pk = 0; pk < n_packs(c); ++pk) {
-            const long long base = c->pack_res[pk], m = c->pack_res[pk + 1] - base;
-            for (long long t = 0; t < m; ++t)
-                for (int k = 0; k < std::min(cnt[base + t], c->cap); ++k) {
-                    const int j = (int)(base + list[(size_t)(base + t) * c->cap + k]);
-                    if (base + t < j)
-                        pairs.push_back({(int)(base + t), j});
+            const int off = c->pack_off[pk], m = c->pack_off[pk + 1] - off;
+            for (int t = 0; t < m; ++t) {
+                const int i = c->slot_res[off + t];
+                for (int k = 0; k < std::min(cnt[i], c->cap); ++k) {
+                    const int sl = list[(size_t)i * c->cap + k];
+                    if (sl >= m)
+                        return fail(c, SOP_E_LIST_OVERFLOW, "list entry outside its pack");
+                    const int j = c->slot_res[off + sl];
+                    if (i < j)
+                        pairs.push_back({i, j});
                 }
+            }
         }
     } else {
         // rows hold slots of their tile; the tile's stage maps slots to ids

@@ -74,7 +74,8 @@ struct DevBufs {
     uint2 *topo2;            // plain: {slot, r0 bits} of bonded/native partners, (i/T)*TOPO_CAP*T + e*T + i%T
     int *stage;       // plain: per tile, global ids of its slots (stage_max per tile)
     int *stage_cnt;   // plain: slots per tile
-    int *pack_res;    // batched form: first residue of each pack (n_packs + 1)
+    int *pack_off;    // batched form: first slot of each pack (n_packs + 1)
+    int *slot_res;    // batched form: residue of each slot (a permutation of the residues)
     float4 *pos_save; // one saved layer (autotuning restores the state it found)
     int *cell_count;  // residues per cell
     float4 *cells;    // CELL_CAP slots per cell: {hi.xyz, residue id bits}

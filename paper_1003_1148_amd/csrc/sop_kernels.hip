@@ -1397,7 +1397,8 @@ struct BatchArgs {
     float4 *pout;
     const int2 *trow;
     const float2 *tent;
-    const int *pack_res;      // first residue of each pack (n_packs + 1)
+    const int *pack_off;      // first slot of each pack (n_packs + 1)
+    const int *slot_res;      // residue of each slot; a pack's trajectories are consecutive
     const int *traj_lo;
     const int *traj_hi;
     const unsigned *stream_ids;
@@ -1450,12 +1451,15 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     __shared__ int perm[WGS];           // row summed by each lane: residue | chunks << 16
     __shared__ float lsum[3][WGS];      // list force of each residue
     __shared__ int hist[NBUCKET];
+    __shared__ int sres[WGS];           // residue of each local slot
     const int p = blockIdx.x;
-    const int base = a.pack_res[p];
-    const int n = a.pack_res[p + 1] - base;
+    const int off = a.pack_off[p];
+    const int n = a.pack_off[p + 1] - off;
     const int t = threadIdx.x;
     const bool act = t < n;
-    const int i = base + t;
+    const int i = act ? a.slot_res[off + t] : 0;  // this lane's residue
+    // local slot of a residue of the same trajectory: residue + shift
+    const int shift = t - i;
 
     float4 hi = make_float4(0.f, 0.f, 0.f, 0.f), lo = hi;
     int tlo = 0, thi = 0;
@@ -1464,13 +1468,14 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     if (act) {
         hi = a.pin[2 * i];
         lo = a.pin[2 * i + 1];
-        tlo = a.traj_lo[i] - base;
-        thi = a.traj_hi[i] - base;
+        tlo = a.traj_lo[i] + shift;
+        thi = a.traj_hi[i] + shift;
         row = a.trow[i];
         cnt = a.list_cnt[i];
         shh[t] = hi;
         shl[t] = lo;
     }
+    sres[t] = i;
     if (t == 0) {
         shh[WGS] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
         shl[WGS] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1481,12 +1486,10 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     for (int u = 0; u < BT; ++u) {
         const bool has = act && u < ntop;
         const float2 te = has ? a.tent[row.x + u] : make_float2(0.0f, 1.0f);
-        tsh[u][t] = make_int2(has ? __float_as_int(te.x) - base : -1, __float_as_int(te.y));
+        tsh[u][t] = make_int2(has ? __float_as_int(te.x) + shift : -1, __float_as_int(te.y));
     }
-    // rows are residue-major: entry k of residue r at (base + r) cap + k
-    const int capc = a.cap >> 2;
+    // rows are residue-major: entry k (a local slot) of residue i at i cap + k
     unsigned short *lrow16 = a.list + (size_t)i * a.cap;
-    const uint2 *lp = reinterpret_cast<const uint2 *>(a.list + (size_t)base * a.cap);
     const long long s0 = (a.step_base ? *a.step_base : 0) + a.step_off;
     const PairConsts kc = pair_consts(a.c);
     const int traj = __float_as_int(lo.w);
@@ -1494,7 +1497,8 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
 
     // lane -> row assignment: counting sort of the rows by chunk count,
     // longest first (ties in any order; the sums do not depend on it)
-    int my = 0;  // residue | chunks << 16 of the row this lane sums
+    int my = 0;   // local slot | chunks << 16 of the row this lane sums
+    int myg = 0;  // its residue
     auto assign = [&]() {
         const int nch = act ? (min(cnt, a.cap) + 3) >> 2 : 0;
         const int key = NBUCKET - 1 - min(nch, NBUCKET - 1);
@@ -1521,6 +1525,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             perm[atomicAdd(&hist[key], 1)] = t | (nch << 16);
         __syncthreads();
         my = t < n ? perm[t] : 0;
+        myg = sres[my & 0xffff];
     };
     __syncthreads();
     if (!(a.stale || s0 % a.list_every == 0))
@@ -1559,7 +1564,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                     for (int u = 0; u < BT; ++u)
                         drop(ex[u]);
                     for (int e = BT; e < ntop; ++e)
-                        drop(__float_as_int(a.tent[row.x + e].x) - base);
+                        drop(__float_as_int(a.tent[row.x + e].x) + shift);
                     m &= ~x;
                     while (m) {
                         const unsigned v = (unsigned)(j0 + __builtin_ctz(m));
@@ -1600,7 +1605,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             // ---- list partners (forces) of the row this lane was given ----
             const int r = my & 0xffff, nch = my >> 16;
             const float4 ph = shh[r], pl = shl[r];
-            const uint2 *rp = lp + (size_t)r * capc;
+            const uint2 *rp = reinterpret_cast<const uint2 *>(a.list + (size_t)myg * a.cap);
             float fx = 0.0f, fy = 0.0f, fz = 0.0f;
             uint2 w0 = rp[0], w1 = rp[min(1, max(nch - 1, 0))];
             for (int c = 0; c < nch; ++c) {
@@ -1642,7 +1647,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                     r0 = __int_as_float(v.y);
                 } else {
                     const float2 te = a.tent[row.x + e];
-                    j = __float_as_int(te.x) - base;
+                    j = __float_as_int(te.x) + shift;
                     r0 = te.y;
                 }
                 if (e < nb)
@@ -1910,7 +1915,8 @@ void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const
     a.pout = b.pos[cur ^ 1];
     a.trow = b.trow;
     a.tent = b.tent;
-    a.pack_res = b.pack_res;
+    a.pack_off = b.pack_off;
+    a.slot_res = b.slot_res;
     a.traj_lo = b.traj_lo;
     a.traj_hi = b.traj_hi;
     a.stream_ids = b.stream_ids;
