@@ -256,6 +256,15 @@ __device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const fl
     add_repulsive_d(A, pair_delta(hi, lo, hj, lj), k, rec);
 }
 
+// The repulsive term from the FP32 coordinates alone (the list pairs of the
+// batched schedule): the dropped low parts are below 2^-24 of the coordinate,
+// far inside the force tolerance for pairs beyond the excluded bonded range.
+__device__ __forceinline__ void add_repulsive_hi(Acc &A, const float4 &hi, const float4 &hj,
+                                                 const PairConsts &k, bool rec)
+{
+    add_repulsive_d(A, make_float3(hi.x - hj.x, hi.y - hj.y, hi.z - hj.z), k, rec);
+}
+
 // Cantilever `pull` (index or -1) and tip on one residue at t_n = step*h.
 __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep, const float4 &hi,
                                              const float4 &lo, long long step, double h, int pull,
@@ -1444,7 +1453,7 @@ template <int WGS, int MODE>
 __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
 {
     constexpr int BT = 4;  // bonded/native entries per residue kept in LDS
-    __shared__ float4 shh[WGS + 1];     // hi per residue; slot WGS: the far-away empty slot
+    __shared__ float4 shh[WGS + 32];    // hi per residue; slots from WGS on: far away (empty slot, padding)
     __shared__ float4 shl[WGS + 1];     // lo per residue
     __shared__ double red[WGS];         // trajectory sums
     __shared__ int2 tsh[BT][WGS];       // {local partner, r0 bits} of the first BT entries
@@ -1476,10 +1485,10 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         shl[t] = lo;
     }
     sres[t] = i;
-    if (t == 0) {
-        shh[WGS] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+    if (t < 32)
+        shh[WGS + t] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+    if (t == 0)
         shl[WGS] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
     const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
     const int nt0 = min(ntop, BT);
 #pragma unroll
@@ -1546,18 +1555,25 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 unsigned w_lo = 0u, w_hi = 0u;
                 cnt = 0;
                 for (int j0 = tlo; j0 < thi; j0 += 32) {
+                    // candidate j0 + u at bit 31 - u (slots past the
+                    // trajectory are read from the padding and masked)
                     unsigned m = 0u;
-#pragma unroll 8
-                    for (int u = 0; u < 32; ++u) {
-                        const int j = min(j0 + u, thi - 1);
-                        m |= within_cutoff(hi, shh[j], a.rc2) ? (1u << u) : 0u;
+#pragma unroll 1
+                    for (int u0 = 0; u0 < 32; u0 += 8) {
+                        float4 q[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            q[u] = shh[j0 + u0 + u];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            m = m + m + (within_cutoff(hi, q[u], a.rc2) ? 1u : 0u);
                     }
                     if (thi - j0 < 32)
-                        m &= (1u << (thi - j0)) - 1u;
+                        m &= ~(0xffffffffu >> (thi - j0));
                     unsigned x = 0u;  // the residue itself and its bonded/native partners
                     auto drop = [&](int j) {
                         const unsigned d = (unsigned)(j - j0);
-                        x |= d < 32u ? (1u << d) : 0u;
+                        x |= d < 32u ? (0x80000000u >> d) : 0u;
                     };
                     drop(t);
 #pragma unroll
@@ -1567,8 +1583,9 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                         drop(__float_as_int(a.tent[row.x + e].x) + shift);
                     m &= ~x;
                     while (m) {
-                        const unsigned v = (unsigned)(j0 + __builtin_ctz(m));
-                        m &= m - 1u;
+                        const int u = __builtin_clz(m);
+                        const unsigned v = (unsigned)(j0 + u);
+                        m ^= 0x80000000u >> u;
                         const int sl = cnt & 3;
                         if (sl == 0)
                             w_lo = v;
@@ -1604,28 +1621,33 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         {
             // ---- list partners (forces) of the row this lane was given ----
             const int r = my & 0xffff, nch = my >> 16;
-            const float4 ph = shh[r], pl = shl[r];
-            const uint2 *rp = reinterpret_cast<const uint2 *>(a.list + (size_t)myg * a.cap);
+            const float4 ph = shh[r];
+            // rows are read two chunks (16 bytes) at a time, the next pair
+            // requested before the current one is used
+            const uint4 *rp = reinterpret_cast<const uint4 *>(a.list + (size_t)myg * a.cap);
+            const int nc2 = (nch + 1) >> 1;
             float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-            uint2 w0 = rp[0], w1 = rp[min(1, max(nch - 1, 0))];
-            for (int c = 0; c < nch; ++c) {
-                const uint2 w = w0;
-                w0 = w1;
-                w1 = rp[min(c + 2, nch - 1)];
-                float4 qh[4], ql[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = (int)(((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu);
-                    qh[u] = shh[j];
-                    ql[u] = shl[j];
-                }
+            auto chunk = [&](unsigned wx, unsigned wy) {
+                float4 qh[4];
+                qh[0] = shh[wx & 0xffffu];
+                qh[1] = shh[wx >> 16];
+                qh[2] = shh[wy & 0xffffu];
+                qh[3] = shh[wy >> 16];
                 Acc L;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive(L, ph, pl, qh[u], ql[u], kc, false);
+                    add_repulsive_hi(L, ph, qh[u], kc, false);
                 fx += L.fx;
                 fy += L.fy;
                 fz += L.fz;
+            };
+            uint4 w = rp[0];
+            for (int c2 = 0; c2 < nc2; ++c2) {
+                const uint4 wn = rp[min(c2 + 1, nc2 - 1)];
+                chunk(w.x, w.y);
+                if (2 * c2 + 1 < nch)  // the second chunk of an odd row's last pair is not written
+                    chunk(w.z, w.w);
+                w = wn;
             }
             if (t < n) {
                 lsum[0][r] = fx;
@@ -1662,10 +1684,8 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             if (rec) {
                 // record steps: the repulsive energy and virial over the own row
                 Acc E;
-                for (int k = 0; k < min(cnt, a.cap); ++k) {
-                    const int j = lrow16[k];
-                    add_repulsive(E, hi, lo, shh[j], shl[j], kc, true);
-                }
+                for (int k = 0; k < min(cnt, a.cap); ++k)
+                    add_repulsive_hi(E, hi, shh[lrow16[k]], kc, true);
                 A.e_r = E.e_r;
                 A.vir += E.vir;
             }
