@@ -235,6 +235,25 @@ __device__ __forceinline__ void add_repulsive_d(Acc &A, const float3 &d, const P
     }
 }
 
+// The list-pair form of the soft repulsion: accumulates d / r^8, so the
+// caller multiplies the row's sum by 6 eps_l sigma^6 once instead of every
+// pair; the energy and virial terms are the full ones.
+__device__ __forceinline__ void add_repulsive_u(Acc &A, const float3 &d, const PairConsts &k, bool rec)
+{
+    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    const float ir2 = fast_rcp(r2);
+    const float ir4 = ir2 * ir2;
+    const float ir8 = ir4 * ir4;
+    A.fx += ir8 * d.x;
+    A.fy += ir8 * d.y;
+    A.fz += ir8 * d.z;
+    if (rec) {
+        const float q = k.sg6 * ir4 * ir2;
+        A.e_r += (double)(k.el * q);
+        A.vir += (double)(k.el6 * q);
+    }
+}
+
 // The same terms from compensated positions (hi, lo) of both residues.
 __device__ __forceinline__ void add_fene(Acc &A, const float4 &hi, const float4 &lo, const float4 &hj,
                                          const float4 &lj, float r0, const PairConsts &k, bool rec,
@@ -247,13 +266,6 @@ __device__ __forceinline__ void add_native(Acc &A, const float4 &hi, const float
                                            const float4 &lj, float r0, const PairConsts &k, bool rec)
 {
     add_native_d(A, pair_delta(hi, lo, hj, lj), r0, k, rec);
-}
-
-__device__ __forceinline__ void add_repulsive(Acc &A, const float4 &hi, const float4 &lo,
-                                              const float4 &hj, const float4 &lj, const PairConsts &k,
-                                              bool rec)
-{
-    add_repulsive_d(A, pair_delta(hi, lo, hj, lj), k, rec);
 }
 
 // The repulsive term from the FP32 coordinates alone (the list pairs of the
@@ -1170,18 +1182,18 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         float3 pl0 = unpack_low(ph0);
         auto flush = [&]() {
             if (coff[r] >= c0 && rend <= c1) {  // the whole row is in this range
-                df[0][r] = L.fx;
-                df[1][r] = L.fy;
-                df[2][r] = L.fz;
+                df[0][r] = k.c6 * L.fx;
+                df[1][r] = k.c6 * L.fy;
+                df[2][r] = k.c6 * L.fz;
                 if (ENERGY) {
                     red_e[(NL * 4 + 0) * TILE + r] = L.e_r;
                     red_e[(NL * 4 + 1) * TILE + r] = L.vir;
                 }
             } else {
                 const int s2 = r == r_first ? 0 : 1;
-                pf[s2][0][t] = L.fx;
-                pf[s2][1][t] = L.fy;
-                pf[s2][2][t] = L.fz;
+                pf[s2][0][t] = k.c6 * L.fx;
+                pf[s2][1][t] = k.c6 * L.fy;
+                pf[s2][2][t] = k.c6 * L.fz;
                 if (ENERGY) {
                     pe[(s2 * 2 + 0) * 256 + t] = L.e_r;
                     pe[(s2 * 2 + 1) * 256 + t] = L.vir;
@@ -1197,12 +1209,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             if (!wide) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive_d(L, make_float3(ph0.x - pj[u].x, ph0.y - pj[u].y, ph0.z - pj[u].z), k, ENERGY);
+                    add_repulsive_u(L, make_float3(ph0.x - pj[u].x, ph0.y - pj[u].y, ph0.z - pj[u].z), k, ENERGY);
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float3 lj = unpack_low(pj[u]);
-                    add_repulsive_d(L,
+                    add_repulsive_u(L,
                                     make_float3((ph0.x - pj[u].x) + (pl0.x - lj.x), (ph0.y - pj[u].y) + (pl0.y - lj.y),
                                                 (ph0.z - pj[u].z) + (pl0.z - lj.z)),
                                     k, ENERGY);
@@ -1490,7 +1502,6 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     if (t == 0)
         shl[WGS] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
-    const int nt0 = min(ntop, BT);
 #pragma unroll
     for (int u = 0; u < BT; ++u) {
         const bool has = act && u < ntop;
@@ -1636,7 +1647,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 Acc L;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive_hi(L, ph, qh[u], kc, false);
+                    add_repulsive_u(L, make_float3(ph.x - qh[u].x, ph.y - qh[u].y, ph.z - qh[u].z), kc, false);
                 fx += L.fx;
                 fy += L.fy;
                 fz += L.fz;
@@ -1650,9 +1661,9 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 w = wn;
             }
             if (t < n) {
-                lsum[0][r] = fx;
-                lsum[1][r] = fy;
-                lsum[2][r] = fz;
+                lsum[0][r] = kc.c6 * fx;
+                lsum[1][r] = kc.c6 * fy;
+                lsum[2][r] = kc.c6 * fz;
             }
         }
         Acc A;  // energy sums are only accumulated on record steps
