@@ -1464,15 +1464,17 @@ constexpr int NBUCKET = 64;
 template <int WGS, int MODE>
 __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
 {
-    constexpr int BT = 4;  // bonded/native entries per residue kept in LDS
-    __shared__ float4 shh[WGS + 32];    // hi per residue; slots from WGS on: far away (empty slot, padding)
+    constexpr int TCAP = 8 * WGS;  // bonded/native entries of a pack kept in LDS
+    __shared__ float4 shh[WGS + 1];     // hi per residue; slot WGS: the far-away empty slot
     __shared__ float4 shl[WGS + 1];     // lo per residue
     __shared__ double red[WGS];         // trajectory sums
-    __shared__ int2 tsh[BT][WGS];       // {local partner, r0 bits} of the first BT entries
+    __shared__ unsigned short tpart[TCAP];  // bonded/native entries of the pack: local partner
+    __shared__ float tr0[TCAP];             // ... and r0 (CSR in slot order)
     __shared__ int perm[WGS];           // row summed by each lane: residue | chunks << 16
     __shared__ float lsum[3][WGS];      // list force of each residue
     __shared__ int hist[NBUCKET];
     __shared__ int sres[WGS];           // residue of each local slot
+    __shared__ float3 bblo[WGS / 32], bbhi[WGS / 32];  // list rebuild: boxes of 32-slot blocks
     const int p = blockIdx.x;
     const int off = a.pack_off[p];
     const int n = a.pack_off[p + 1] - off;
@@ -1497,17 +1499,23 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         shl[t] = lo;
     }
     sres[t] = i;
-    if (t < 32)
-        shh[WGS + t] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
-    if (t == 0)
+    if (t == 0) {
+        shh[WGS] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
         shl[WGS] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
-#pragma unroll
-    for (int u = 0; u < BT; ++u) {
-        const bool has = act && u < ntop;
-        const float2 te = has ? a.tent[row.x + u] : make_float2(0.0f, 1.0f);
-        tsh[u][t] = make_int2(has ? __float_as_int(te.x) + shift : -1, __float_as_int(te.y));
     }
+    const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
+    // the pack's bonded/native entries in LDS (entries past TCAP stay in
+    // global memory); perm is the scan's workspace until the first assignment
+    int tot_top = 0;
+    const int toff = block_exclusive_scan<WGS>(ntop, perm, tot_top);
+    for (int e = 0; e < ntop && toff + e < TCAP; ++e) {
+        const float2 te = a.tent[row.x + e];
+        tpart[toff + e] = (unsigned short)(__float_as_int(te.x) + shift);
+        tr0[toff + e] = te.y;
+    }
+    auto partner = [&](int e) {
+        return toff + e < TCAP ? (int)tpart[toff + e] : __float_as_int(a.tent[row.x + e].x) + shift;
+    };
     // rows are residue-major: entry k (a local slot) of residue i at i cap + k
     unsigned short *lrow16 = a.list + (size_t)i * a.cap;
     const long long s0 = (a.step_base ? *a.step_base : 0) + a.step_off;
@@ -1554,20 +1562,49 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     for (int q = 0; q < a.n_steps; ++q) {
         const long long step = s0 + q;
         if ((q == 0 && a.stale) || step % a.list_every == 0) {
+            {
+                // boxes of the 32-slot blocks (empty slots add nothing)
+                float3 bl = act ? make_float3(hi.x, hi.y, hi.z) : make_float3(3.0e38f, 3.0e38f, 3.0e38f);
+                float3 bh = act ? make_float3(hi.x, hi.y, hi.z) : make_float3(-3.0e38f, -3.0e38f, -3.0e38f);
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) {
+                    bl.x = fminf(bl.x, __shfl_xor(bl.x, o, 64));
+                    bl.y = fminf(bl.y, __shfl_xor(bl.y, o, 64));
+                    bl.z = fminf(bl.z, __shfl_xor(bl.z, o, 64));
+                    bh.x = fmaxf(bh.x, __shfl_xor(bh.x, o, 64));
+                    bh.y = fmaxf(bh.y, __shfl_xor(bh.y, o, 64));
+                    bh.z = fmaxf(bh.z, __shfl_xor(bh.z, o, 64));
+                }
+                if ((t & 31) == 0) {
+                    bblo[t >> 5] = bl;
+                    bbhi[t >> 5] = bh;
+                }
+                __syncthreads();
+            }
             if (act) {
                 // Algorithm 3 over the trajectory: r < r_list, not bonded or
-                // native. Candidates are tested 32 at a time into a bit word;
-                // the row is written four entries (one 8-byte chunk) at a time.
-                int ex[BT];
-#pragma unroll
-                for (int u = 0; u < BT; ++u)
-                    ex[u] = tsh[u][t].x;
+                // native. Candidates are tested a 32-slot block at a time into
+                // a bit word (blocks whose box is out of reach of every lane of
+                // the wave are skipped); the row is written four entries (one
+                // 8-byte chunk) at a time.
                 uint2 *rowp = reinterpret_cast<uint2 *>(lrow16);
                 unsigned w_lo = 0u, w_hi = 0u;
                 cnt = 0;
-                for (int j0 = tlo; j0 < thi; j0 += 32) {
-                    // candidate j0 + u at bit 31 - u (slots past the
-                    // trajectory are read from the padding and masked)
+                for (int jb = tlo >> 5; jb <= (thi - 1) >> 5; ++jb) {
+                    const int j0 = jb << 5;
+                    {
+                        // the box test errs on the side of testing: a skipped
+                        // block is farther than r_list by a margin far above
+                        // the rounding of either distance
+                        const float3 bl = bblo[jb], bh = bbhi[jb];
+                        const float gx = fmaxf(fmaxf(bl.x - hi.x, hi.x - bh.x), 0.0f);
+                        const float gy = fmaxf(fmaxf(bl.y - hi.y, hi.y - bh.y), 0.0f);
+                        const float gz = fmaxf(fmaxf(bl.z - hi.z, hi.z - bh.z), 0.0f);
+                        if (!__any(gx * gx + gy * gy + gz * gz <= a.rc2 * 1.001f))
+                            continue;
+                    }
+                    // candidate j0 + u at bit 31 - u; slots of other
+                    // trajectories are masked
                     unsigned m = 0u;
 #pragma unroll 1
                     for (int u0 = 0; u0 < 32; u0 += 8) {
@@ -1579,6 +1616,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                         for (int u = 0; u < 8; ++u)
                             m = m + m + (within_cutoff(hi, q[u], a.rc2) ? 1u : 0u);
                     }
+                    m &= 0xffffffffu >> max(tlo - j0, 0);
                     if (thi - j0 < 32)
                         m &= ~(0xffffffffu >> (thi - j0));
                     unsigned x = 0u;  // the residue itself and its bonded/native partners
@@ -1587,11 +1625,8 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                         x |= d < 32u ? (0x80000000u >> d) : 0u;
                     };
                     drop(t);
-#pragma unroll
-                    for (int u = 0; u < BT; ++u)
-                        drop(ex[u]);
-                    for (int e = BT; e < ntop; ++e)
-                        drop(__float_as_int(a.tent[row.x + e].x) + shift);
+                    for (int e = 0; e < ntop; ++e)
+                        drop(partner(e));
                     m &= ~x;
                     while (m) {
                         const int u = __builtin_clz(m);
@@ -1674,10 +1709,9 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             for (int e = 0; e < ntop; ++e) {
                 int j;
                 float r0;
-                if (e < BT) {
-                    const int2 v = tsh[e][t];
-                    j = v.x;
-                    r0 = __int_as_float(v.y);
+                if (toff + e < TCAP) {
+                    j = tpart[toff + e];
+                    r0 = tr0[toff + e];
                 } else {
                     const float2 te = a.tent[row.x + e];
                     j = __float_as_int(te.x) + shift;
