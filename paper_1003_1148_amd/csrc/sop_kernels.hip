@@ -1470,6 +1470,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     __shared__ double red[WGS];         // trajectory sums
     __shared__ unsigned short tpart[TCAP];  // bonded/native entries of the pack: local partner
     __shared__ float tr0[TCAP];             // ... and r0 (CSR in slot order)
+    __shared__ unsigned short tex[TCAP];    // the same partners in ascending order (list exclusions)
     __shared__ int perm[WGS];           // row summed by each lane: residue | chunks << 16
     __shared__ float lsum[3][WGS];      // list force of each residue
     __shared__ int hist[NBUCKET];
@@ -1508,10 +1509,20 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     // global memory); perm is the scan's workspace until the first assignment
     int tot_top = 0;
     const int toff = block_exclusive_scan<WGS>(ntop, perm, tot_top);
+    const bool top_lds = toff + ntop <= TCAP;  // all of this residue's entries are in LDS
     for (int e = 0; e < ntop && toff + e < TCAP; ++e) {
         const float2 te = a.tent[row.x + e];
-        tpart[toff + e] = (unsigned short)(__float_as_int(te.x) + shift);
+        const unsigned short j = (unsigned short)(__float_as_int(te.x) + shift);
+        tpart[toff + e] = j;
         tr0[toff + e] = te.y;
+        if (top_lds) {  // insertion into the ascending copy
+            int k = e;
+            while (k > 0 && tex[toff + k - 1] > j) {
+                tex[toff + k] = tex[toff + k - 1];
+                --k;
+            }
+            tex[toff + k] = j;
+        }
     }
     auto partner = [&](int e) {
         return toff + e < TCAP ? (int)tpart[toff + e] : __float_as_int(a.tent[row.x + e].x) + shift;
@@ -1589,6 +1600,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 // 8-byte chunk) at a time.
                 uint2 *rowp = reinterpret_cast<uint2 *>(lrow16);
                 unsigned w_lo = 0u, w_hi = 0u;
+                int ep = 0;  // next entry of the ascending exclusion list
                 cnt = 0;
                 for (int jb = tlo >> 5; jb <= (thi - 1) >> 5; ++jb) {
                     const int j0 = jb << 5;
@@ -1625,8 +1637,17 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                         x |= d < 32u ? (0x80000000u >> d) : 0u;
                     };
                     drop(t);
-                    for (int e = 0; e < ntop; ++e)
-                        drop(partner(e));
+                    if (top_lds) {
+                        for (; ep < ntop; ++ep) {  // entries below this block were passed by skipped blocks
+                            const int j = tex[toff + ep];
+                            if (j >= j0 + 32)
+                                break;
+                            drop(j);
+                        }
+                    } else {
+                        for (int e = 0; e < ntop; ++e)
+                            drop(partner(e));
+                    }
                     m &= ~x;
                     while (m) {
                         const int u = __builtin_clz(m);
