@@ -70,7 +70,7 @@ struct DevBufs {
     int2 *trow;       // per residue: {first entry, n_bond | n_native << 12}
     float2 *tent;     // {partner id bits, r0}: bonds first, then natives
     int *list_cnt;    // partners per residue
-    unsigned short *list16;  // plain: rows as tile slots, 8 per lane per chunk; batched: per-pack local indices
+    unsigned short *list16;  // rows by residue (cap entries): plain, slots of its tile; batched, local slots of its pack
     uint2 *topo2;            // plain: {slot, r0 bits} of bonded/native partners, (i/T)*TOPO_CAP*T + e*T + i%T
     int *stage;       // plain: per tile, global ids of its slots (stage_max per tile)
     int *stage_cnt;   // plain: slots per tile
