@@ -166,3 +166,47 @@ def test_batched_matches_plain_to_tolerance(P, ens):
     b.step(100)
     d = float(np.linalg.norm(a.get_coordinates() - b.get_coordinates(), axis=1).max())
     assert d <= TRAJ_TOL
+
+
+@pytest.fixture(scope="module")
+def dense():
+    """Three compact 120-residue globules whose native contacts reach 12 A:
+    about 22 bonded/native entries per residue, more than the batched kernel
+    keeps in LDS (8 per slot on average), so the entries past that capacity
+    are read from global memory."""
+    from synth.structures import System, globule, topology_from_chains
+    chains = [[globule(120, seed)] for seed in (11, 12, 13)]
+    x, offs, cid, b, br0, nn, nr0 = topology_from_chains(chains, native_cutoff=12.0)
+    return System("dense natives", x, offs, np.arange(3, dtype=np.uint32), cid, b, br0, nn, nr0)
+
+
+def test_batched_dense_topology(P, orc, dense):
+    ntop = np.bincount(np.concatenate([dense.bonds.ravel(), dense.natives.ravel()]),
+                       minlength=dense.n_res)
+    assert ntop.mean() > 16  # well past the LDS share of a pack
+    x = perturbed(dense, sd=0.1, seed=4)
+    o = orc.OracleSystem(dense, RunParams())
+    for wg in (256, 512):
+        c = ctx(P, dense, x=x, wg=wg)
+        c.build_pairlist()
+        assert np.array_equal(c.get_pairlist(), o.pairlist(x))
+        c.set_step(5)
+        F, E, fe = c.compute_forces()
+        Fo, Eo, feo, st = o.forces(x, step=5)
+        err = float(np.linalg.norm(F - Fo) / np.linalg.norm(Fo))
+        log(f"dense topology, {wg}-slot packs: force rel err {err:.3e}")
+        assert err <= FORCE_TOL
+        c.close()
+    # trajectories against the oracle, and the same bits for both packings
+    runs = []
+    for wg, k in [(256, 30), (512, 7)]:
+        c = ctx(P, dense, wg=wg, steps=k)
+        c.step(100)
+        runs.append(c.get_coordinates())
+        c.close()
+    assert np.array_equal(runs[0], runs[1])
+    xo, _, _, st = o.run(dense.x, 100)
+    assert st == 0
+    d = float(np.linalg.norm(runs[0] - xo, axis=1).max())
+    log(f"dense topology 100-step max |dx| {d:.3e} A")
+    assert d <= TRAJ_TOL
