@@ -170,6 +170,7 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.pull_slot = (int *)take(n * sizeof(int));
     d.pulls = (PullDev *)take(std::max<size_t>(c->pulls.size(), 1) * sizeof(PullDev));
     d.stream_ids = (unsigned *)take(T * sizeof(unsigned));
+    d.noise_key = (uint2 *)take(n * sizeof(uint2));
     d.res_offsets = (long long *)take((T + 1) * sizeof(long long));
     d.res_energy = (double *)take(n * RES_E * sizeof(double));
     d.n_chunks = (int)c->chunk_lo.size() - 1;
@@ -890,6 +891,14 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
                                   hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(b.stream_ids, c->stream_ids.data(), c->n_traj * sizeof(unsigned),
                               hipMemcpyHostToDevice, s));
+    {
+        std::vector<uint2> key(n);
+        for (size_t i = 0; i < n; ++i) {
+            key[i].x = (unsigned)c->local[i] | (c->fixed[i] ? 0x80000000u : 0u);
+            key[i].y = c->stream_ids[c->traj_of[i]];
+        }
+        HIP_TRY(c, hipMemcpy(b.noise_key, key.data(), n * sizeof(uint2), hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, hipMemcpyAsync(b.res_offsets, c->res_offsets.data(), (c->n_traj + 1) * sizeof(long long),
                               hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(b.list_cnt, 0, n * sizeof(int), s));

@@ -88,6 +88,7 @@ struct DevBufs {
     int *pull_slot;   // per residue: cantilever index or -1
     PullDev *pulls;
     unsigned *stream_ids;    // per trajectory
+    uint2 *noise_key;        // per residue: {tag, stream id}, the static words of its Philox counter
     long long *res_offsets;  // n_traj + 1
     double *res_energy;      // n_res * RES_E
     int *chunk_lo;           // energy reduction: first residue of each chunk (+ n_res)

@@ -963,6 +963,7 @@ struct TileArgs {
     const int *stage;
     const int *stage_cnt;
     const unsigned *stream_ids;
+    const uint2 *noise_key;  // per residue {tag, stream id}
     const int *pull_slot;
     const PullDev *pulls;
     double *res_energy;
@@ -1109,6 +1110,22 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         for (int u = 0; u < PER; ++u) {
             const int sl = t + u * 256;
             ids[u] = sl < S ? st[sl] : -1;
+        }
+        // parts 1 and 2 draw the residue's Gaussians while the gathers are in
+        // flight: part 1 the (x, y) Box-Muller pair, part 2 (or part 1 alone) z
+        if (NL > 1 && MODE == 0 && act && q >= 1 && q <= 2) {
+            const uint2 key = a.noise_key[i];
+            if (!(key.x >> 31)) {
+                const long long step0 = (a.step_base ? *a.step_base : 0) + a.step_off;
+                const uint4 w = noise_words(key.x, key.y, step0, a.c);
+                if (q == 1) {
+                    const float2 gxy = gaussian_pair(w);
+                    red_g[rho] = gxy.x;
+                    red_g[TILE + rho] = gxy.y;
+                }
+                if (q == 2 || NL == 2)
+                    red_g[2 * TILE + rho] = gaussian_axis(w, 2);
+            }
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -1284,17 +1301,6 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         rf[rho] = A.fx;
         rf[TILE + rho] = A.fy;
         rf[2 * TILE + rho] = A.fz;
-        // part 1: the (x, y) Box-Muller pair; part 2 (or part 1 alone): z
-        if (MODE == 0 && act && q <= 2 && !(__float_as_uint(hi0.w) >> 31)) {
-            const uint4 w = noise_words(__float_as_uint(hi0.w), a.stream_ids[__float_as_int(lo0.w)], step, a.c);
-            if (q == 1) {
-                const float2 gxy = gaussian_pair(w);
-                red_g[rho] = gxy.x;
-                red_g[TILE + rho] = gxy.y;
-            }
-            if (q == 2 || NL == 2)
-                red_g[2 * TILE + rho] = gaussian_axis(w, 2);
-        }
     }
     if (ENERGY) {
         double *re = red_e + q * 4 * TILE;
@@ -1966,6 +1972,7 @@ void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const Step
     a.stage = b.stage;
     a.stage_cnt = b.stage_cnt;
     a.stream_ids = b.stream_ids;
+    a.noise_key = b.noise_key;
     a.pull_slot = b.pull_slot;
     a.pulls = b.pulls;
     a.res_energy = b.res_energy;
