@@ -1064,6 +1064,9 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     __shared__ float df[3][TILE];    // list sums of residues inside one range
     __shared__ float red_f[NL > 1 ? (NL - 1) * 3 * TILE : 1];
     __shared__ float red_g[(NL > 1 && MODE == 0) ? 3 * TILE : 1];
+    // with four parts, part 3 evaluates the external terms early (force steps)
+    constexpr bool EARLY_X = NL >= 4 && MODE == 0 && !ENERGY;
+    __shared__ float red_x[EARLY_X ? 3 * TILE : 1];
     __shared__ double red_e[ENERGY ? (NL + 1) * 4 * TILE : 1];   // energies: parts, then list direct
     __shared__ double pe[ENERGY ? 2 * 2 * 256 : 1];              // list energy partials (e_r, vir)
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
@@ -1126,6 +1129,17 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
                 if (q == 2 || NL == 2)
                     red_g[2 * TILE + rho] = gaussian_axis(w, 2);
             }
+        }
+        if (EARLY_X && act && q == 3) {
+            // the cantilever and tip terms from the residue's own position
+            const long long step0 = (a.step_base ? *a.step_base : 0) + a.step_off;
+            Acc X;
+            double e_x = 0.0, f_rep = 0.0;
+            add_external(X, e_x, f_rep, hi0, lo0, step0, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
+                         a.tip, false, a.err);
+            red_x[rho] = X.fx;
+            red_x[TILE + rho] = X.fy;
+            red_x[2 * TILE + rho] = X.fz;
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -1387,8 +1401,14 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         A.vir = vir + lvir;
     }
     double e_x = 0.0, f_rep = 0.0;
-    add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
-                 a.tip, ENERGY, a.err);
+    if (EARLY_X) {
+        A.fx += red_x[rho];
+        A.fy += red_x[TILE + rho];
+        A.fz += red_x[2 * TILE + rho];
+    } else {
+        add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
+                     a.tip, ENERGY, a.err);
+    }
     if (ENERGY) {
         double *er = a.res_energy + (size_t)i * RES_E;
         // each internal pair appears in both partners' rows
