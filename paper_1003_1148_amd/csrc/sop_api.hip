@@ -223,18 +223,29 @@ void make_packs(sop_ctx *c)
         order[t] = t;
     auto len = [&](int t) { return c->res_offsets[t + 1] - c->res_offsets[t]; };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return len(x) > len(y); });
-    std::vector<long long> room;
+    // first fit: the leftmost pack with room, from a max-tree over the rooms
+    // of T packs (the ones not opened yet are empty, so the leftmost fit is
+    // an open pack or the next new one)
+    int leaves = 1;
+    while (leaves < std::max(T, 1))
+        leaves <<= 1;
+    std::vector<long long> tree(2 * (size_t)leaves, 0);
+    for (int k = 0; k < T; ++k)
+        tree[leaves + k] = wg;
+    for (int v = leaves - 1; v >= 1; --v)
+        tree[v] = std::max(tree[2 * v], tree[2 * v + 1]);
     std::vector<std::vector<int>> members;
     for (int t : order) {
-        size_t k = 0;
-        while (k < room.size() && room[k] < len(t))
-            ++k;
-        if (k == room.size()) {
-            room.push_back(wg);
-            members.emplace_back();
-        }
-        room[k] -= len(t);
+        int v = 1;
+        while (v < leaves)
+            v = tree[2 * v] >= len(t) ? 2 * v : 2 * v + 1;
+        const int k = v - leaves;  // exists: every trajectory fits an empty pack
+        if (k >= (int)members.size())
+            members.resize(k + 1);
         members[k].push_back(t);
+        tree[v] -= len(t);
+        for (v >>= 1; v >= 1; v >>= 1)
+            tree[v] = std::max(tree[2 * v], tree[2 * v + 1]);
     }
     c->pack_off.assign(1, 0);
     c->slot_res.clear();

@@ -210,3 +210,26 @@ def test_batched_dense_topology(P, orc, dense):
     d = float(np.linalg.norm(runs[0] - xo, axis=1).max())
     log(f"dense topology 100-step max |dx| {d:.3e} A")
     assert d <= TRAJ_TOL
+
+
+def ffd_pack_count(lengths, wg):
+    """First-fit decreasing (ties by index), the packing the library states."""
+    room = []
+    for L in sorted(lengths, key=lambda v: -v):
+        for k in range(len(room)):
+            if room[k] >= L:
+                room[k] -= L
+                break
+        else:
+            room.append(wg - L)
+    return len(room)
+
+
+def test_batched_packs_first_fit_decreasing(P, ens):
+    lengths = np.diff(ens.res_offsets).tolist()
+    for wg in (512, 1024):
+        c = ctx(P, ens, wg=wg)
+        w, k, n_packs = c.get_batch()
+        assert w == wg
+        assert n_packs == ffd_pack_count(lengths, wg)
+        c.close()
