@@ -848,14 +848,12 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
             fail_tile();
             return;  // uniform
         }
-        if (t < NWm) {
-            int sl = wbase[t];
-            unsigned u = used[t];
-            while (u) {
-                const int b = __ffs(u) - 1;
-                u &= u - 1u;
-                st[sl++] = __float_as_int(cand[32 * t + b].w);
-            }
+        // staging: each used candidate of the window takes the next slot in
+        // sorted order (all lanes, one candidate each)
+        for (int ci = t; ci < Mw; ci += NT) {
+            const unsigned uw = used[ci >> 5];
+            if ((uw >> (ci & 31)) & 1u)
+                st[wbase[ci >> 5] + __popc(uw & ((1u << (ci & 31)) - 1u))] = __float_as_int(cand[ci].w);
         }
         if (act) {
             // this part's partners, after those of the lower parts
