@@ -37,9 +37,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_alg_per_launch):
-    """HBM bytes per step-kernel launch from the committed counter summary,
-    if it was taken on the current kernel source."""
+def measured_counters():
+    """The committed counter summary of the step kernel (HBM bytes and VALU
+    instructions per launch), if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "k_tile_step_c2_traffic.json")
     if not os.path.exists(path):
         return None
@@ -47,22 +47,46 @@ def measured_traffic(bytes_alg_per_launch):
         d = json.load(f)
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
-def cpu_baseline(system, params, n_steps):
+def cpu_baseline(P, np, system, params, n_steps):
+    """The oracle timed on one host core over a sample of the workload, and
+    the GPU path's agreement with it on that sample: the force error at the
+    start and the largest coordinate difference after the sample's steps."""
     import oracle
     o = oracle.OracleSystem(system, params)
     t0 = time.perf_counter()
-    _, _, _, st = o.run(system.x, n_steps)
+    xo, _, _, st = o.run(system.x, n_steps)
     dt = time.perf_counter() - t0
     if st != 0:
         raise RuntimeError(f"oracle status {st}")
+    # forces at the start (the native structure: bonded and native terms
+    # near zero, so the net forces are small) and at the oracle's end point
+    Fo0, _, _, _ = o.forces(system.x, step=0)
+    Fo1, _, _, _ = o.forces(xo, step=n_steps)
+    g = P.from_system(system, params)
+    F0, _, _ = g.compute_forces()
+    g.step(n_steps)
+    xg = g.get_coordinates()
+    g.close()
+    h = P.from_system(system, params, coordinates=xo)
+    h.set_step(n_steps)
+    F1, _, _ = h.compute_forces()
+    h.close()
     return {"value": system.n_res * n_steps / dt, "unit": "residue-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{n_steps} steps ({(n_steps + params.list_every - 1) // params.list_every} "
                       f"list rebuilds) of the {system.n_res}-residue workload, FP64, one thread",
-            "seconds": dt}
+            "seconds": dt,
+            "agreement": {
+                "force_rel_err_start": float(np.linalg.norm(F0 - Fo0) / np.linalg.norm(Fo0)),
+                "force_rel_err_end": float(np.linalg.norm(F1 - Fo1) / np.linalg.norm(Fo1)),
+                "max_dx_A": float(np.linalg.norm(xg - xo, axis=1).max()),
+                "steps": n_steps,
+                "note": "GPU plain schedule against the oracle from the same start and Philox "
+                        "stream: L2 force error at the start and at the oracle's end point, "
+                        "largest coordinate difference after the steps"}}
 
 
 def batched_leg(P, make_config, RunParams, np, energy_every, steps, n_seq, seq_steps):
@@ -191,7 +215,12 @@ def main():
     note(f"fused step kernel {k_ms * 1e3:.2f} us, list rebuild {rb_ms * 1e3:.2f} us")
     bytes_step = N * (64 + 12 + 8 * b + 8 * c + 4 * pp)
     achieved = bytes_step / (k_ms * 1e-3) / 1e9
-    traffic = measured_traffic(bytes_step)
+    counters = measured_counters()
+    traffic = counters.get("hbm_bytes_per_launch") if counters else None
+    # share of the chip's vector issue slots the kernel's VALU instructions
+    # take: 4 cycles per wave instruction on 1,024 SIMDs at 2.4 GHz
+    valu = counters.get("sq_insts_valu_per_dispatch") if counters else None
+    valu_frac = valu * 4.0 / (1024 * 2.4e9 * k_ms * 1e-3) if valu else None
 
     out = {
         "metric": METRIC,
@@ -226,6 +255,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "valu_issue_frac": valu_frac,
             "alg_bytes_per_launch": bytes_step,
             "kernel_us": k_ms * 1e3,
             "rebuild_us": rb_ms * 1e3,
@@ -236,7 +266,7 @@ def main():
                                      args.batched_steps, args.seq_trajectories, args.seq_steps)
     if not args.no_cpu_baseline:
         note(f"oracle CPU baseline: {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(s, p, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(P, np, s, p, args.cpu_steps)
     print(json.dumps(out), flush=True)
     ctx.close()
 
