@@ -157,8 +157,10 @@ sop_status sop_set_schedule(sop_ctx *ctx, int32_t schedule);
 /*
  * Batched schedule: residues per workgroup (256, 512 or 1024; 0 = the
  * smallest that holds the longest trajectory) and steps per launch (>= 1).
- * Consecutive trajectories are packed greedily into workgroups.  May be
- * changed after binding; the list is rebuilt at the next step.
+ * Whole trajectories are packed into workgroups first-fit decreasing by
+ * length (ties by index); n_packs reports how many workgroups that makes.
+ * Results do not depend on these choices.  May be changed after binding;
+ * the list is rebuilt at the next step.
  */
 sop_status sop_set_batch(sop_ctx *ctx, int32_t wg_residues, int32_t steps_per_launch);
 sop_status sop_get_batch(const sop_ctx *ctx, int32_t *wg_residues, int32_t *steps_per_launch,
