@@ -229,6 +229,25 @@ def test_trajectory_200_steps(P, orc, name):
     _energy_close(Eg[0], Eo[-1][0], s.n_res)
 
 
+@pytest.mark.parametrize("tile", [128, 256])
+def test_trajectory_other_tile_sizes(P, orc, tile):
+    """The wider tiles split a residue's work over two lanes (128) or keep
+    it in one (256), so their noise draws and external terms take other
+    paths than the default tile's."""
+    s = cfg("c1")
+    p = RunParams()
+    c = ctx_for(P, s, p, tile=tile, energy_every=10)
+    c.step(100)
+    xo, Eo, _, st = orc.OracleSystem(s, p).run(s.x, 100, energy_every=10)
+    assert st == 0
+    d = float(np.linalg.norm(c.get_coordinates() - xo, axis=1).max())
+    log(f"  tile {tile}: 100-step max |dx| {d:.3e} A")
+    assert d <= TRAJ_TOL
+    Eg, estep = c.get_energies()
+    assert estep == 90
+    _energy_close(Eg[0], Eo[-1][0], s.n_res)
+
+
 def test_graph_replay_equals_direct_launches(P):
     s = cfg("c1")
     a = ctx_for(P, s, graph_steps=1, energy_every=20)
