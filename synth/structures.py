@@ -363,18 +363,41 @@ def config3(n_traj=4096, nmin=50, nmax=500, seed=3):
     return _system("c3: batched ensemble", [[c - c.mean(0)] for c in chains], steps=100_000)
 
 
+def _stack_copies(sub, n_sub, spacing, rng, min_gap=BOND, tries=16, nudge=1.0):
+    """Copies stacked along x, `spacing` apart, each re-spun about x while it
+    comes closer than min_gap to the copies before it; when no spin of the
+    `tries` clears them, the copy (and every later one) moves `nudge` further
+    along x and the spins are drawn again. The fibre is then centred at the
+    origin."""
+    placed = []
+    x = 0.0
+    for _ in range(n_sub):
+        near = placed[-2:]
+        tree = cKDTree(np.concatenate(near)) if near else None
+        while True:
+            c = np.array([x, 0.0, 0.0])
+            for _ in range(tries):
+                y = sub @ _rot_x(rng.uniform(0.0, 2.0 * np.pi)).T + c
+                if tree is None or not tree.query_ball_point(y, min_gap, return_length=True).any():
+                    break
+            else:
+                x += nudge
+                continue
+            break
+        placed.append(y)
+        x += spacing
+    mid = 0.5 * (placed[0][:, 0].mean() + placed[-1][:, 0].mean())
+    return [y - np.array([mid, 0.0, 0.0]) for y in placed]
+
+
 def config4(n_sub=1000):
     sub = subunit250(2)
     # short axis of the disc along the fibre axis x
     base = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [-1.0, 0.0, 0.0]])
     sub = sub @ base.T
     ext = np.ptp(sub[:, 0])
-    spacing = ext - 6.0
     rng = np.random.default_rng(4)
-    centres = np.zeros((n_sub, 3))
-    centres[:, 0] = (np.arange(n_sub) - (n_sub - 1) / 2.0) * spacing
-    frames = [np.eye(3)] * n_sub
-    chains = _place_copies(sub, frames, centres, rng, _rot_x)
+    chains = _stack_copies(sub, n_sub, ext - 6.0, rng)
     return _system("c4: 250k-residue fibre", [chains], steps=10_000)
 
 
