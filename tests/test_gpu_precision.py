@@ -1,8 +1,8 @@
 """Precision study on the 250,000-residue fibre: compensated FP32 positions
 and FP32 forces against the FP64 oracle where the coordinates are largest.
 
-The far end of the fibre (its last 20 subunits, |x| up to 1.45e4 A, where
-the FP32 spacing of a coordinate is 1e-3 A, larger than the thermal step's
+The far end of the fibre (its last 20 subunits, |x| up to 1.8e4 A, where
+the FP32 spacing of a coordinate is 2e-3 A, far above the thermal step's
 rounding budget) runs 1,000 steps on the GPU and in the oracle from the same
 start and Philox stream. Every 100 steps the test records the L2 force error
 of the GPU forces against the oracle's on the same coordinates, and the RMS

@@ -442,8 +442,8 @@ def test_fixed_residue_does_not_move(orc):
 
 
 def test_compensated_positions_keep_far_coordinates():
-    """Why positions are held as hi + lo: at |x| = 1.45e4 A (the fibre's
-    end) the FP32 spacing is 1e-3 A, so adding the per-step displacements
+    """Why positions are held as hi + lo: at |x| = 1.45e4 A (near the
+    fibre's end) the FP32 spacing is 1e-3 A, so adding the per-step displacements
     (sigma = 0.0437 A per axis) in plain FP32 loses about half a spacing per
     step; the TwoSum form used by the update (y = d + lo; hi, lo <- TwoSum(hi, y))
     keeps the sum to FP64 accuracy over 2,000 steps."""
