@@ -50,6 +50,25 @@ def measured_counters():
     return d
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Achievable HBM rate of a plain device copy (bytes read + written per
+    second), timed with events on the current stream."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(P, np, system, params, n_steps):
     """The oracle timed on one host core over a sample of the workload, and
     the GPU path's agreement with it on that sample: the force error at the
@@ -215,6 +234,8 @@ def main():
     note(f"fused step kernel {k_ms * 1e3:.2f} us, list rebuild {rb_ms * 1e3:.2f} us")
     bytes_step = N * (64 + 12 + 8 * b + 8 * c + 4 * pp)
     achieved = bytes_step / (k_ms * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
+    note(f"device copy {copy_gbs:.0f} GB/s")
     counters = measured_counters()
     traffic = counters.get("hbm_bytes_per_launch") if counters else None
     # share of the chip's vector issue slots the kernel's VALU instructions
@@ -254,6 +275,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
+            "copy_GBps": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
             "traffic": traffic,
             "valu_issue_frac": valu_frac,
             "alg_bytes_per_launch": bytes_step,
