@@ -393,7 +393,7 @@ constexpr int stage_max() { return TILE >= 256 ? 2048 : 1024; }
 // at once during a rebuild; more are taken in windows of whole cells.  Small
 // tiles keep less so that five workgroups fit a CU.
 template <int TILE>
-constexpr int cand_win() { return TILE == 64 ? 768 : 1024; }
+constexpr int cand_win() { return TILE == 64 ? 896 : 1024; }
 // Distinct cells around one tile, and the bits of its open-addressing table.
 template <int TILE>
 constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640); }
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
             }
         }
         const int base = cbase[mA], Mw = cbase[mB] - base;
-        constexpr int CPT = CM / NT;  // candidates per lane
+        constexpr int CPT = (CM + NT - 1) / NT;  // candidates per lane
         float4 cv[CPT];
         int cm[CPT];
 #pragma unroll
