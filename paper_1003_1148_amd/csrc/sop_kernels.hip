@@ -400,7 +400,7 @@ constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640
 template <int TILE>
 constexpr int chash_bits() { return TILE == 128 ? 11 : 10; }
 constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
-constexpr int TREG = 16;        // bonded/native entries per residue kept in registers
+constexpr int TREG = 20;        // bonded/native entries per residue kept in registers
 
 struct BuildArgs {
     const int *tile_first;  // first residue of each tile, then n
