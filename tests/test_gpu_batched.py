@@ -233,3 +233,14 @@ def test_batched_packs_first_fit_decreasing(P, ens):
         assert w == wg
         assert n_packs == ffd_pack_count(lengths, wg)
         c.close()
+
+
+def test_batched_list_overflow_is_reported(P, ens):
+    """Rows longer than the list capacity stop at the capacity (the sums
+    read only that far) and raise the overflow error at the next sync."""
+    c = ctx(P, ens, p=RunParams(list_capacity=16))
+    c.step(20)
+    with pytest.raises(P.SopError) as e:
+        c.synchronize()
+    assert e.value.name == "SOP_E_LIST_OVERFLOW"
+    c.close()
