@@ -1752,10 +1752,10 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         bool broken = false;
         double e_x = 0.0, f_rep = 0.0;
         if (act) {
-            // bonded and native partners
-            for (int e = 0; e < ntop; ++e) {
-                int j;
-                float r0;
+            // bonded, then native partners: two loops, so a wave whose
+            // residues have different bond counts (chain ends) runs each
+            // term's code alone
+            auto entry = [&](int e, int &j, float &r0) {
                 if (toff + e < TCAP) {
                     j = tpart[toff + e];
                     r0 = tr0[toff + e];
@@ -1764,10 +1764,18 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                     j = __float_as_int(te.x) + shift;
                     r0 = te.y;
                 }
-                if (e < nb)
-                    add_fene(A, hi, lo, shh[j], shl[j], r0, kc, rec, broken);
-                else
-                    add_native(A, hi, lo, shh[j], shl[j], r0, kc, rec);
+            };
+            for (int e = 0; e < nb; ++e) {
+                int j;
+                float r0;
+                entry(e, j, r0);
+                add_fene(A, hi, lo, shh[j], shl[j], r0, kc, rec, broken);
+            }
+            for (int e = nb; e < ntop; ++e) {
+                int j;
+                float r0;
+                entry(e, j, r0);
+                add_native(A, hi, lo, shh[j], shl[j], r0, kc, rec);
             }
             add_external(A, e_x, f_rep, hi, lo, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
                          a.tip, rec, a.err);
