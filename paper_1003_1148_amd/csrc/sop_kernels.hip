@@ -1481,7 +1481,7 @@ __device__ __forceinline__ double traj_sum(double *red, int t, bool act, double 
 }
 
 // Batched schedule: the list partners of a residue are summed by one lane,
-// chunk by chunk in row order, so the sum does not depend on the lane or on
+// pair by pair in row order, so the sum does not depend on the lane or on
 // the packing. Which lane sums which row is chosen at each list rebuild by a
 // counting sort on the row length (longest first), so the lanes of a wave
 // run loops of about the same length.
@@ -1719,20 +1719,16 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             // requested before the current one is used
             const uint4 *rp = reinterpret_cast<const uint4 *>(a.list + (size_t)myg * a.cap);
             const int nc2 = (nch + 1) >> 1;
-            float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+            Acc L;  // the row's sum, pair by pair in row order
             auto chunk = [&](unsigned wx, unsigned wy) {
                 float4 qh[4];
                 qh[0] = shh[wx & 0xffffu];
                 qh[1] = shh[wx >> 16];
                 qh[2] = shh[wy & 0xffffu];
                 qh[3] = shh[wy >> 16];
-                Acc L;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     add_repulsive_u(L, make_float3(ph.x - qh[u].x, ph.y - qh[u].y, ph.z - qh[u].z), kc, false);
-                fx += L.fx;
-                fy += L.fy;
-                fz += L.fz;
             };
             uint4 w = rp[0];
             for (int c2 = 0; c2 < nc2; ++c2) {
@@ -1743,9 +1739,9 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 w = wn;
             }
             if (t < n) {
-                lsum[0][r] = kc.c6 * fx;
-                lsum[1][r] = kc.c6 * fy;
-                lsum[2][r] = kc.c6 * fz;
+                lsum[0][r] = kc.c6 * L.fx;
+                lsum[1][r] = kc.c6 * L.fy;
+                lsum[2][r] = kc.c6 * L.fz;
             }
         }
         Acc A;  // energy sums are only accumulated on record steps
