@@ -171,8 +171,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
-    ap.add_argument("--seq-trajectories", type=int, default=16)
-    ap.add_argument("--seq-steps", type=int, default=1000)
+    ap.add_argument("--seq-trajectories", type=int, default=64)
+    ap.add_argument("--seq-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (for memory counters)")
     args = ap.parse_args()
