@@ -1,8 +1,9 @@
 """FP64 CPU oracle for SOP overdamped Langevin dynamics -- test infrastructure.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg import
-this package.  The arithmetic lives in ``sop_oracle.c`` (plain C, FP64,
-single-threaded); this module only marshals arrays through ctypes.  It never
+this package.  The arithmetic lives in ``sop_oracle.c`` (plain C, FP64;
+single-threaded, except the residue-parallel OpenMP forms ``forces_par`` and
+``run_par``); this module only marshals arrays through ctypes.  It never
 imports the HIP library's package, and the HIP library never imports it.
 """
 from __future__ import annotations
@@ -26,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp",
                                "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -84,6 +85,19 @@ def lib():
         L.orc_forces_rows.restype = C.c_int
         L.orc_run.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, vp]
         L.orc_run.restype = C.c_int
+        L.orc_force_scale.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
+        L.orc_force_scale.restype = C.c_int
+        L.orc_forces_par.argtypes = [vp, vp, vp, i64, vp, vp, vp, C.c_int]
+        L.orc_forces_par.restype = C.c_int
+        L.orc_run_par.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, vp, C.c_int]
+        L.orc_run_par.restype = C.c_int
+        d = C.c_double
+        L.orc_ramp_mean_exact.argtypes = [d, d, d, d, d]
+        L.orc_ramp_mean_exact.restype = d
+        L.orc_ramp_mean_recursion.argtypes = [C.c_int, d, d, d, d, d, i64]
+        L.orc_ramp_mean_recursion.restype = d
+        L.orc_ramp_run.argtypes = [C.c_int, i64, vp, i64, i64, d, d, d, d, d, u64, u32]
+        L.orc_ramp_run.restype = None
         _lib = L
     return _lib
 
@@ -175,6 +189,47 @@ class OracleSystem:
             raise RuntimeError(f"oracle forces_rows status {st}")
         return F
 
+    def force_scale(self, x, step=0, pairs=None):
+        """Per-residue scale S_i (sum of |dE/dr| over the residue's pairs plus
+        its external force magnitudes) and per-trajectory term magnitudes
+        (n_traj, 5): sums of |E| per term and of |r dE/dr| for the virial."""
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if pairs is None:
+            pairs = self.pairlist(x)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+        S = np.zeros(self.sysm.n_res)
+        Em = np.zeros((self.sysm.n_traj, NTERMS))
+        st = L.orc_force_scale(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(pairs),
+                               len(pairs), _ptr(S), _ptr(Em))
+        if st != OK:
+            raise RuntimeError(f"oracle force_scale status {st}")
+        return S, Em
+
+    def forces_par(self, x, step=0, threads=0):
+        """Residue-parallel forces with the list rebuilt at x; (F, E, f_ext, status)."""
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        F = np.zeros((self.sysm.n_res, 3))
+        E = np.zeros((self.sysm.n_traj, NTERMS))
+        fe = np.zeros(self.sysm.n_traj)
+        st = L.orc_forces_par(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(F),
+                              _ptr(E), _ptr(fe), int(threads or default_threads()))
+        return F, E, fe, st
+
+    def run_par(self, x, n_steps, step0=0, energy_every=0, threads=0):
+        """Residue-parallel run; the same return values as run()."""
+        L = lib()
+        x = np.array(x, dtype=np.float64, copy=True, order="C")
+        nrec_max = 0 if energy_every <= 0 else (n_steps // energy_every + 2)
+        E = np.zeros((max(nrec_max, 1), self.sysm.n_traj, NTERMS))
+        fe = np.zeros((max(nrec_max, 1), self.sysm.n_traj))
+        nrec = C.c_int64(0)
+        st = L.orc_run_par(C.byref(self.s), C.byref(self.p), _ptr(x), int(step0), int(n_steps),
+                           int(energy_every), _ptr(E), _ptr(fe), nrec_max, C.byref(nrec),
+                           int(threads or default_threads()))
+        return x, E[:nrec.value], fe[:nrec.value], st
+
     def run(self, x, n_steps, step0=0, energy_every=0):
         """Integrate n_steps from step0; returns (x_new, E records, f records, status)."""
         L = lib()
@@ -186,6 +241,36 @@ class OracleSystem:
         st = L.orc_run(C.byref(self.s), C.byref(self.p), _ptr(x), int(step0), int(n_steps),
                        int(energy_every), _ptr(E), _ptr(fe), nrec_max, C.byref(nrec))
         return x, E[:nrec.value], fe[:nrec.value], st
+
+
+def default_threads():
+    """Threads for the residue-parallel forms: OMP_NUM_THREADS, else the CPUs
+    this process may run on."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    if v and v.isdigit() and int(v) > 0:
+        return int(v)
+    return len(os.sched_getaffinity(0))
+
+
+# -- Section IV.C: harmonic Brownian particle under a force ramp ---------
+
+def ramp_mean_exact(X0, rf, xi, Ksp, t):
+    """Eq. 3."""
+    return lib().orc_ramp_mean_exact(float(X0), float(rf), float(xi), float(Ksp), float(t))
+
+
+def ramp_mean_recursion(order, X0, rf, xi, Ksp, h, n):
+    """Eq. 4 (order 1) or Eq. 5 (order 2) iterated n times from X0."""
+    return lib().orc_ramp_mean_recursion(int(order), float(X0), float(rf), float(xi), float(Ksp),
+                                         float(h), int(n))
+
+
+def ramp_run(order, X, step0, n, rf, xi, Ksp, kBT, h, seed, stream=0):
+    """Advance particles X (float64 array, copied) by n steps of the given scheme."""
+    X = np.array(X, dtype=np.float64, copy=True, order="C")
+    lib().orc_ramp_run(int(order), len(X), _ptr(X), int(step0), int(n), float(rf), float(xi),
+                       float(Ksp), float(kBT), float(h), int(seed), int(stream))
+    return X
 
 
 # -- scalar helpers ------------------------------------------------------

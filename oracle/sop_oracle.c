@@ -4,7 +4,10 @@
  *
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg call
  * this code.  It shares nothing with the HIP library: no headers, no helpers,
- * no tables.  It is written to be read against the paper (Zhmurov, Dima,
+ * no tables.  Everything is single-threaded except the residue-parallel
+ * forms at the end (OpenMP over residues, the same arithmetic summed in
+ * another order), which exist so that systems of 10^5 residues can be
+ * followed for 10^4 steps.  It is written to be read against the paper (Zhmurov, Dima,
  * Kholodov, Barsegov, "Langevin dynamics simulations of biomolecules on
  * graphics processors", arXiv:1003.1148), not to be fast.
  *
@@ -671,4 +674,490 @@ int orc_run(const orc_system *s, const orc_params *p, double *x, int64_t step0, 
     free(fe);
     free(list);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rounding scale of each residue's force and each energy term              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Magnitudes of the external forces on residue i of trajectory t at
+ * t_n = step*h, term by term (each cantilever attached to i, then the tip);
+ * their energies are added to *E_mag.  Returns the sum of the magnitudes.
+ */
+static double external_magnitude(const orc_system *s, const orc_params *p, const double *x,
+                                 int64_t step, int64_t t, int64_t i, double *E_mag)
+{
+    double tn = (double)step * p->h, sum = 0.0;
+    for (int32_t k = 0; k < s->n_pull; ++k) {
+        if (s->pull_traj[k] != t || s->pull_res[k] != i)
+            continue;
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double d = s->pull_anchor0[3 * k + a] + s->pull_v[3 * k + a] * tn - x[3 * i + a];
+            d2 += d * d;
+        }
+        sum += s->pull_kappa[k] * sqrt(d2);
+        *E_mag += 0.5 * s->pull_kappa[k] * d2;
+    }
+    if (s->has_tip) {
+        double r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double d = x[3 * i + a] - (s->tip_c0[a] + s->tip_v[a] * tn);
+            r2 += d * d;
+        }
+        double gap = sqrt(r2) - s->tip_radius;
+        if (gap > 0.0) {
+            double q = pow(s->tip_sigma / gap, 6.0);
+            sum += 6.0 * s->tip_eps * q / gap;
+            *E_mag += s->tip_eps * q;
+        }
+    }
+    return sum;
+}
+
+/*
+ * The scale against which an approximate evaluation of the forces and
+ * energies of Eq. 1 is compared with this oracle, term by term:
+ *   S[i]       = sum over the bonded, native and listed pairs containing i
+ *                of |dE/dr|, plus the magnitude of every external force
+ *                on i (n_res values);
+ *   Em[5t + k] = for k = 0, 1, 2: the sum of |E| over the FENE, native and
+ *                repulsive pairs of trajectory t; k = 3: the sum of the
+ *                external energies; k = 4: the sum of |r dE/dr| over the
+ *                pairs (the terms of the virial).
+ * By the triangle inequality |F_i| <= S[i], with equality when every term
+ * acting on i points the same way (a residue with a single partner).
+ */
+int orc_force_scale(const orc_system *s, const orc_params *p, const double *x, int64_t step,
+                    const int32_t *list_ij, int64_t n_list, double *S, double *Em)
+{
+    int broken = 0;
+    memset(S, 0, (size_t)s->n_res * sizeof(double));
+    if (Em)
+        memset(Em, 0, (size_t)s->n_traj * ORC_NTERMS * sizeof(double));
+    for (int64_t b = 0; b < s->n_bonds; ++b) {
+        int64_t i = s->bonds[2 * b], j = s->bonds[2 * b + 1];
+        double r = dist(x, i, j), g;
+        double en = orc_fene(r, s->bond_r0[b], p->k_fene, p->R0, &g, &broken);
+        S[i] += fabs(g);
+        S[j] += fabs(g);
+        if (Em) {
+            int64_t t = traj_of(s, i);
+            Em[t * ORC_NTERMS + 0] += fabs(en);
+            Em[t * ORC_NTERMS + 4] += fabs(r * g);
+        }
+    }
+    for (int64_t b = 0; b < s->n_native; ++b) {
+        int64_t i = s->natives[2 * b], j = s->natives[2 * b + 1];
+        double r = dist(x, i, j), g;
+        double en = orc_native(r, s->native_r0[b], p->eps_h, &g);
+        S[i] += fabs(g);
+        S[j] += fabs(g);
+        if (Em) {
+            int64_t t = traj_of(s, i);
+            Em[t * ORC_NTERMS + 1] += fabs(en);
+            Em[t * ORC_NTERMS + 4] += fabs(r * g);
+        }
+    }
+    for (int64_t b = 0; b < n_list; ++b) {
+        int64_t i = list_ij[2 * b], j = list_ij[2 * b + 1];
+        double r = dist(x, i, j), g;
+        double en = orc_repulsive(r, p->sigma, p->eps_l, &g);
+        S[i] += fabs(g);
+        S[j] += fabs(g);
+        if (Em) {
+            int64_t t = traj_of(s, i);
+            Em[t * ORC_NTERMS + 2] += fabs(en);
+            Em[t * ORC_NTERMS + 4] += fabs(r * g);
+        }
+    }
+    for (int64_t t = 0; t < s->n_traj; ++t)
+        for (int64_t i = s->res_offsets[t]; i < s->res_offsets[t + 1]; ++i) {
+            double e = 0.0;
+            S[i] += external_magnitude(s, p, x, step, t, i, &e);
+            if (Em)
+                Em[t * ORC_NTERMS + 3] += e;
+        }
+    return broken ? ORC_E_FENE : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same dynamics, residue-parallel (OpenMP): each residue's force is    */
+/* gathered from its own partners (the particle-based form of Algorithm 2)  */
+/* instead of scattered pair by pair (Algorithm 1).  Only the order of the  */
+/* floating-point sums differs from orc_forces / orc_run.                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t *ptr;  /* n_res + 1 */
+    int32_t *col;  /* partners, ascending within a row */
+} rows_t;
+
+typedef struct {
+    int64_t *ptr;  /* n_res + 1 */
+    int32_t *col;  /* bonded partners first, then native partners */
+    double *r0;
+    int32_t *nb;   /* bonded partners per residue */
+} topo_rows_t;
+
+static int topo_rows_build(const orc_system *s, topo_rows_t *tr)
+{
+    int64_t n = s->n_res, m = 2 * (s->n_bonds + s->n_native);
+    tr->ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    tr->col = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    tr->r0 = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    tr->nb = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    int64_t *fill = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    if (!tr->ptr || !tr->col || !tr->r0 || !tr->nb || !fill) {
+        free(fill);
+        return ORC_E_ARG;
+    }
+    for (int64_t b = 0; b < s->n_bonds; ++b) {
+        tr->ptr[s->bonds[2 * b] + 1]++;
+        tr->ptr[s->bonds[2 * b + 1] + 1]++;
+        tr->nb[s->bonds[2 * b]]++;
+        tr->nb[s->bonds[2 * b + 1]]++;
+    }
+    for (int64_t b = 0; b < s->n_native; ++b) {
+        tr->ptr[s->natives[2 * b] + 1]++;
+        tr->ptr[s->natives[2 * b + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        tr->ptr[i + 1] += tr->ptr[i];
+    for (int64_t b = 0; b < s->n_bonds; ++b)
+        for (int e = 0; e < 2; ++e) {
+            int32_t i = s->bonds[2 * b + e], j = s->bonds[2 * b + 1 - e];
+            tr->col[tr->ptr[i] + fill[i]] = j;
+            tr->r0[tr->ptr[i] + fill[i]++] = s->bond_r0[b];
+        }
+    for (int64_t b = 0; b < s->n_native; ++b)
+        for (int e = 0; e < 2; ++e) {
+            int32_t i = s->natives[2 * b + e], j = s->natives[2 * b + 1 - e];
+            tr->col[tr->ptr[i] + fill[i]] = j;
+            tr->r0[tr->ptr[i] + fill[i]++] = s->native_r0[b];
+        }
+    free(fill);
+    return ORC_OK;
+}
+
+static void topo_rows_free(topo_rows_t *tr)
+{
+    free(tr->ptr);
+    free(tr->col);
+    free(tr->r0);
+    free(tr->nb);
+}
+
+static int cmp_sweep_idx(const void *a, const void *b) { return cmp_sweep(a, b); }
+
+/*
+ * Verlet-list rows: for every residue i, the residues j != i of its
+ * trajectory that are neither bonded nor native to it and pass the
+ * single-precision list predicate at x (Algorithm 3, row by row), in
+ * ascending order.  A candidate is skipped untested only where the sorted x
+ * coordinates are rc or more apart (the predicate is then false, as in
+ * orc_pairlist).
+ */
+static int rows_build(const orc_system *s, const orc_params *p, const excl_t *e, const double *x,
+                      rows_t *r, int nthreads)
+{
+    int64_t n = s->n_res;
+    float rc2 = list_rc2(p);
+    float rcf = (float)p->r_list;
+    sweep_t *sw = (sweep_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(sweep_t));
+    int64_t *pos = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    r->ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!sw || !pos || !r->ptr) {
+        free(sw);
+        free(pos);
+        return ORC_E_ARG;
+    }
+    for (int64_t t = 0; t < s->n_traj; ++t) {
+        int64_t a = s->res_offsets[t], b = s->res_offsets[t + 1];
+        for (int64_t k = a; k < b; ++k) {
+            sw[k].idx = (int32_t)k;
+            sw[k].xf = (float)x[3 * k];
+        }
+        qsort(sw + a, (size_t)(b - a), sizeof(sweep_t), cmp_sweep_idx);
+        for (int64_t k = a; k < b; ++k)
+            pos[sw[k].idx] = k;
+    }
+    /* two passes over the same candidates: count, then fill */
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            for (int64_t i = 0; i < n; ++i)
+                r->ptr[i + 1] += r->ptr[i];
+            r->col = (int32_t *)malloc((size_t)(r->ptr[n] > 0 ? r->ptr[n] : 1) * sizeof(int32_t));
+            if (!r->col) {
+                free(sw);
+                free(pos);
+                return ORC_E_ARG;
+            }
+        }
+#pragma omp parallel for schedule(dynamic, 512) num_threads(nthreads)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t t = traj_of(s, i);
+            int64_t a = s->res_offsets[t], b = s->res_offsets[t + 1];
+            int64_t u = pos[i], cnt = 0;
+            int32_t *out = pass ? r->col + r->ptr[i] : NULL;
+            for (int dir = -1; dir <= 1; dir += 2)
+                for (int64_t v = u + dir; v >= a && v < b; v += dir) {
+                    float gap = dir > 0 ? sw[v].xf - sw[u].xf : sw[u].xf - sw[v].xf;
+                    if (gap >= rcf)
+                        break;
+                    int32_t j = sw[v].idx;
+                    if (!within_list_cutoff(x, i, j, rc2) || excluded(e, (int32_t)i, j))
+                        continue;
+                    if (pass)
+                        out[cnt] = j;
+                    ++cnt;
+                }
+            if (pass)
+                qsort(out, (size_t)cnt, sizeof(int32_t), cmp_i32);
+            else
+                r->ptr[i + 1] = cnt;
+        }
+    }
+    free(sw);
+    free(pos);
+    return ORC_OK;
+}
+
+/* Force on residue i from its bonded, native and listed partners and the
+ * external terms; half of each pair energy and virial term goes to i. */
+static int residue_force(const orc_system *s, const orc_params *p, const topo_rows_t *tr,
+                         const rows_t *r, const double *x, int64_t step, int64_t i, double f[3],
+                         double eh[ORC_NTERMS], double *f_report)
+{
+    int broken = 0;
+    f[0] = f[1] = f[2] = 0.0;
+    for (int k = 0; k < ORC_NTERMS; ++k)
+        eh[k] = 0.0;
+    for (int64_t e = tr->ptr[i]; e < tr->ptr[i + 1]; ++e) {
+        int64_t j = tr->col[e];
+        double rr = dist(x, i, j), g, en;
+        if (e - tr->ptr[i] < tr->nb[i]) {
+            en = orc_fene(rr, tr->r0[e], p->k_fene, p->R0, &g, &broken);
+            eh[0] += 0.5 * en;
+        } else {
+            en = orc_native(rr, tr->r0[e], p->eps_h, &g);
+            eh[1] += 0.5 * en;
+        }
+        eh[4] -= 0.5 * rr * g;
+        for (int a = 0; a < 3; ++a)
+            f[a] += -g * (x[3 * i + a] - x[3 * j + a]) / rr;
+    }
+    for (int64_t e = r->ptr[i]; e < r->ptr[i + 1]; ++e) {
+        int64_t j = r->col[e];
+        double rr = dist(x, i, j), g;
+        double en = orc_repulsive(rr, p->sigma, p->eps_l, &g);
+        eh[2] += 0.5 * en;
+        eh[4] -= 0.5 * rr * g;
+        for (int a = 0; a < 3; ++a)
+            f[a] += -g * (x[3 * i + a] - x[3 * j + a]) / rr;
+    }
+    int st = external_on_residue(s, p, x, step, traj_of(s, i), i, f, &eh[3], f_report);
+    if (broken)
+        return ORC_E_FENE;
+    return st;
+}
+
+/* Forces and energies of every residue at x (list rows built at x_list),
+ * then the per-trajectory sums in residue order. */
+static int forces_rowwise(const orc_system *s, const orc_params *p, const topo_rows_t *tr,
+                          const rows_t *r, const double *x, int64_t step, double *F, double *E,
+                          double *f_ext, double *eres, double *fres, int nthreads)
+{
+    int status = ORC_OK;
+    int64_t n = s->n_res;
+#pragma omp parallel for schedule(dynamic, 512) num_threads(nthreads)
+    for (int64_t i = 0; i < n; ++i) {
+        double rep = 0.0;
+        int st = residue_force(s, p, tr, r, x, step, i, F + 3 * i, eres + (size_t)i * ORC_NTERMS, &rep);
+        fres[i] = rep;
+        if (st != ORC_OK) {
+#pragma omp critical
+            if (status == ORC_OK)
+                status = st;
+        }
+    }
+    for (int64_t t = 0; t < s->n_traj; ++t) {
+        double acc[ORC_NTERMS] = {0, 0, 0, 0, 0}, fr = 0.0;
+        for (int64_t i = s->res_offsets[t]; i < s->res_offsets[t + 1]; ++i) {
+            for (int k = 0; k < ORC_NTERMS; ++k)
+                acc[k] += eres[(size_t)i * ORC_NTERMS + k];
+            fr += fres[i];
+        }
+        if (E)
+            memcpy(E + t * ORC_NTERMS, acc, sizeof acc);
+        if (f_ext)
+            f_ext[t] = fr;
+    }
+    if (status != ORC_OK)
+        return status;
+    for (int64_t k = 0; k < 3 * n; ++k)
+        if (!isfinite(F[k]))
+            return ORC_E_NONFINITE;
+    return ORC_OK;
+}
+
+/* Residue-parallel form of orc_forces, with the list rebuilt at x. */
+int orc_forces_par(const orc_system *s, const orc_params *p, const double *x, int64_t step,
+                   double *F, double *E, double *f_ext, int nthreads)
+{
+    excl_t e;
+    topo_rows_t tr;
+    rows_t r = {NULL, NULL};
+    if (nthreads <= 0)
+        nthreads = 1;
+    if (excl_build(s, &e) != ORC_OK || topo_rows_build(s, &tr) != ORC_OK)
+        return ORC_E_ARG;
+    int st = rows_build(s, p, &e, x, &r, nthreads);
+    double *eres = (double *)malloc((size_t)(s->n_res > 0 ? s->n_res : 1) * ORC_NTERMS * sizeof(double));
+    double *fres = (double *)malloc((size_t)(s->n_res > 0 ? s->n_res : 1) * sizeof(double));
+    if (st == ORC_OK && eres && fres)
+        st = forces_rowwise(s, p, &tr, &r, x, step, F, E, f_ext, eres, fres, nthreads);
+    else if (st == ORC_OK)
+        st = ORC_E_ARG;
+    free(eres);
+    free(fres);
+    free(r.ptr);
+    free(r.col);
+    topo_rows_free(&tr);
+    excl_free(&e);
+    return st;
+}
+
+/* Residue-parallel form of orc_run: the same steps, list rebuilds, noise
+ * and energy records. */
+int orc_run_par(const orc_system *s, const orc_params *p, double *x, int64_t step0, int64_t n_steps,
+                int64_t energy_every, double *E_out, double *f_out, int64_t max_records,
+                int64_t *n_records, int nthreads)
+{
+    int64_t n = s->n_res, rec = 0;
+    excl_t e;
+    topo_rows_t tr;
+    rows_t r = {NULL, NULL};
+    if (nthreads <= 0)
+        nthreads = 1;
+    if (excl_build(s, &e) != ORC_OK || topo_rows_build(s, &tr) != ORC_OK)
+        return ORC_E_ARG;
+    double *F = (double *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    double *E = (double *)malloc((size_t)s->n_traj * ORC_NTERMS * sizeof(double));
+    double *fe = (double *)malloc((size_t)s->n_traj * sizeof(double));
+    double *eres = (double *)malloc((size_t)(n > 0 ? n : 1) * ORC_NTERMS * sizeof(double));
+    double *fres = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    int status = (F && E && fe && eres && fres) ? ORC_OK : ORC_E_ARG;
+    double drift = p->h / p->zeta;
+    double noise = sqrt(2.0 * p->kBT * p->h / p->zeta);
+    for (int64_t q = 0; q < n_steps && status == ORC_OK; ++q) {
+        int64_t step = step0 + q;
+        if (q == 0 || step % p->list_every == 0) {
+            free(r.ptr);
+            free(r.col);
+            r.ptr = NULL;
+            r.col = NULL;
+            status = rows_build(s, p, &e, x, &r, nthreads);
+            if (status != ORC_OK)
+                break;
+        }
+        status = forces_rowwise(s, p, &tr, &r, x, step, F, E, fe, eres, fres, nthreads);
+        if (status != ORC_OK)
+            break;
+        if (energy_every > 0 && step % energy_every == 0 && rec < max_records) {
+            if (E_out)
+                memcpy(E_out + rec * s->n_traj * ORC_NTERMS, E,
+                       (size_t)s->n_traj * ORC_NTERMS * sizeof(double));
+            if (f_out)
+                memcpy(f_out + rec * s->n_traj, fe, (size_t)s->n_traj * sizeof(double));
+            ++rec;
+        }
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+        for (int64_t i = 0; i < n; ++i) {
+            if (s->fixed && s->fixed[i])
+                continue;
+            int64_t t = traj_of(s, i);
+            double g[3];
+            orc_gauss3(p->seed, (uint32_t)(i - s->res_offsets[t]), s->stream_ids[t], step, g);
+            for (int a = 0; a < 3; ++a)
+                x[3 * i + a] += drift * F[3 * i + a] + noise * g[a];
+        }
+    }
+    if (n_records)
+        *n_records = rec;
+    free(F);
+    free(E);
+    free(fe);
+    free(eres);
+    free(fres);
+    free(r.ptr);
+    free(r.col);
+    topo_rows_free(&tr);
+    excl_free(&e);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section IV.C: an exactly solvable model for the accuracy of the           */
+/* integrators.  A Brownian particle X in the harmonic well K_sp X^2/2 (well */
+/* at the origin; X(0) = X0) under the force ramp f_ext = r_f t, friction    */
+/* xi, tau = xi/K_sp.                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. 3: <X(t)> = X0 exp(-t/tau) + (r_f tau/xi) (t - tau (1 - exp(-t/tau))). */
+double orc_ramp_mean_exact(double X0, double rf, double xi, double Ksp, double t)
+{
+    double tau = xi / Ksp;
+    return X0 * exp(-t / tau) + rf * tau / xi * (t - tau * (1.0 - exp(-t / tau)));
+}
+
+/*
+ * The mean recursions from X_0 = X0 over n steps of h, t_k = k h:
+ *   order 1 (Eq. 4): X_{k+1} = X_k + (r_f t_k/xi - X_k/tau) h;
+ *   order 2 (Eq. 5): the same plus (X_k/(2 tau^2) - r_f t_k/(2 tau xi)) h^2.
+ * Returns X_n.
+ */
+double orc_ramp_mean_recursion(int order, double X0, double rf, double xi, double Ksp, double h,
+                               int64_t n)
+{
+    double tau = xi / Ksp, X = X0;
+    for (int64_t k = 0; k < n; ++k) {
+        double tk = (double)k * h;
+        double next = X + (rf * tk / xi - X / tau) * h;
+        if (order == 2)
+            next += (X / (2.0 * tau * tau) - rf * tk / (2.0 * tau * xi)) * h * h;
+        X = next;
+    }
+    return X;
+}
+
+/*
+ * M independent particles of the same model, advanced in place from step
+ * `step0` by n steps of the scheme of the given order with the random
+ * displacement sqrt(2 kB T h/xi) g (the Eq. 2 noise):
+ *   order 1: X += (r_f t_k - K_sp X) h/xi + noise;
+ *   order 2: the deterministic part of the order-2 recursion (Eq. 5) + noise.
+ * g is the first Gaussian of orc_gauss3 for counter (particle index,
+ * stream, step).  The forces are those of the per-particle Eq. 4 / Eq. 5
+ * steps, so the ensemble mean follows those recursions.
+ */
+void orc_ramp_run(int order, int64_t M, double *X, int64_t step0, int64_t n, double rf, double xi,
+                  double Ksp, double kBT, double h, uint64_t seed, uint32_t stream)
+{
+    double tau = xi / Ksp;
+    double noise = sqrt(2.0 * kBT * h / xi);
+    for (int64_t m = 0; m < M; ++m) {
+        double x = X[m];
+        for (int64_t k = step0; k < step0 + n; ++k) {
+            double tk = (double)k * h;
+            double g[3];
+            orc_gauss3(seed, (uint32_t)m, stream, k, g);
+            double next = x + (rf * tk / xi - x / tau) * h;
+            if (order == 2)
+                next += (x / (2.0 * tau * tau) - rf * tk / (2.0 * tau * xi)) * h * h;
+            x = next + noise * g[0];
+        }
+        X[m] = x;
+    }
 }
