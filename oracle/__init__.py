@@ -91,6 +91,8 @@ def lib():
         L.orc_forces_par.restype = C.c_int
         L.orc_run_par.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, vp, C.c_int]
         L.orc_run_par.restype = C.c_int
+        L.orc_force_scale_par.argtypes = [vp, vp, vp, i64, vp, C.c_int]
+        L.orc_force_scale_par.restype = C.c_int
         d = C.c_double
         L.orc_ramp_mean_exact.argtypes = [d, d, d, d, d]
         L.orc_ramp_mean_exact.restype = d
@@ -216,6 +218,17 @@ class OracleSystem:
         st = L.orc_forces_par(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(F),
                               _ptr(E), _ptr(fe), int(threads or default_threads()))
         return F, E, fe, st
+
+    def force_scale_par(self, x, step=0, threads=0):
+        """Residue-parallel S (list rebuilt at x)."""
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        S = np.zeros(self.sysm.n_res)
+        st = L.orc_force_scale_par(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(S),
+                                   int(threads or default_threads()))
+        if st != OK:
+            raise RuntimeError(f"oracle force_scale_par status {st}")
+        return S
 
     def run_par(self, x, n_steps, step0=0, energy_every=0, threads=0):
         """Residue-parallel run; the same return values as run()."""

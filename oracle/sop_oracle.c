@@ -1161,3 +1161,44 @@ void orc_ramp_run(int order, int64_t M, double *X, int64_t step0, int64_t n, dou
         X[m] = x;
     }
 }
+
+/* Residue-parallel form of orc_force_scale's S (list rebuilt at x). */
+int orc_force_scale_par(const orc_system *s, const orc_params *p, const double *x, int64_t step,
+                        double *S, int nthreads)
+{
+    excl_t e;
+    topo_rows_t tr;
+    rows_t r = {NULL, NULL};
+    if (nthreads <= 0)
+        nthreads = 1;
+    if (excl_build(s, &e) != ORC_OK || topo_rows_build(s, &tr) != ORC_OK)
+        return ORC_E_ARG;
+    int st = rows_build(s, p, &e, x, &r, nthreads);
+    int broken = 0;
+    if (st == ORC_OK) {
+#pragma omp parallel for schedule(dynamic, 512) num_threads(nthreads) reduction(| : broken)
+        for (int64_t i = 0; i < s->n_res; ++i) {
+            double sum = 0.0, g, dummy = 0.0;
+            for (int64_t k = tr.ptr[i]; k < tr.ptr[i + 1]; ++k) {
+                double rr = dist(x, i, tr.col[k]);
+                if (k - tr.ptr[i] < tr.nb[i])
+                    orc_fene(rr, tr.r0[k], p->k_fene, p->R0, &g, &broken);
+                else
+                    orc_native(rr, tr.r0[k], p->eps_h, &g);
+                sum += fabs(g);
+            }
+            for (int64_t k = r.ptr[i]; k < r.ptr[i + 1]; ++k) {
+                orc_repulsive(dist(x, i, r.col[k]), p->sigma, p->eps_l, &g);
+                sum += fabs(g);
+            }
+            S[i] = sum + external_magnitude(s, p, x, step, traj_of(s, i), i, &dummy);
+        }
+        if (broken)
+            st = ORC_E_FENE;
+    }
+    free(r.ptr);
+    free(r.col);
+    topo_rows_free(&tr);
+    excl_free(&e);
+    return st;
+}

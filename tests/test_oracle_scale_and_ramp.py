@@ -156,6 +156,16 @@ def test_parallel_forces_equal_the_pair_loop(orc, name):
         assert np.allclose(fep, fe, rtol=1e-12, atol=1e-15)
 
 
+def test_parallel_force_scale_equals_the_pair_loop(orc):
+    s = with_externals(make_config("c1"))
+    rng = np.random.default_rng(6)
+    x = s.x + 0.2 * rng.standard_normal(s.x.shape)
+    o = orc.OracleSystem(s, RunParams())
+    S, _ = o.force_scale(x, step=3)
+    Sp = o.force_scale_par(x, step=3, threads=4)
+    assert np.allclose(Sp, S, rtol=1e-12, atol=0)
+
+
 def test_parallel_run_equals_the_serial_run(orc):
     s = with_externals(make_config("c1"))
     o = orc.OracleSystem(s, RunParams())
