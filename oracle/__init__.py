@@ -93,6 +93,12 @@ def lib():
         L.orc_run_par.restype = C.c_int
         L.orc_force_scale_par.argtypes = [vp, vp, vp, i64, vp, C.c_int]
         L.orc_force_scale_par.restype = C.c_int
+        L.orc_running_average.argtypes = [vp, i64, C.c_int32, vp]
+        L.orc_running_average.restype = C.c_int
+        L.orc_peak_force.argtypes = [vp, i64, C.c_int32, vp, vp]
+        L.orc_peak_force.restype = C.c_int
+        L.orc_end_to_end.argtypes = [vp, vp, vp]
+        L.orc_end_to_end.restype = None
         d = C.c_double
         L.orc_ramp_mean_exact.argtypes = [d, d, d, d, d]
         L.orc_ramp_mean_exact.restype = d
@@ -243,6 +249,13 @@ class OracleSystem:
                            int(threads or default_threads()))
         return x, E[:nrec.value], fe[:nrec.value], st
 
+    def end_to_end(self, x):
+        """|x_last - x_first| of every trajectory."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        R = np.zeros(self.sysm.n_traj)
+        lib().orc_end_to_end(C.byref(self.s), _ptr(x), _ptr(R))
+        return R
+
     def run(self, x, n_steps, step0=0, energy_every=0):
         """Integrate n_steps from step0; returns (x_new, E records, f records, status)."""
         L = lib()
@@ -263,6 +276,24 @@ def default_threads():
     if v and v.isdigit() and int(v) > 0:
         return int(v)
     return len(os.sched_getaffinity(0))
+
+
+# -- force-spectroscopy observables (Section IV.B) -------------------------
+
+def running_average(y, w):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(max(len(y) - int(w) + 1, 1))
+    if lib().orc_running_average(_ptr(y), len(y), int(w), _ptr(out)) != OK:
+        raise ValueError("bad window")
+    return out[:len(y) - int(w) + 1]
+
+
+def peak_force(f, w):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    pk, ix = C.c_double(0.0), C.c_int64(0)
+    if lib().orc_peak_force(_ptr(f), len(f), int(w), C.byref(pk), C.byref(ix)) != OK:
+        raise ValueError("bad window")
+    return pk.value, ix.value
 
 
 # -- Section IV.C: harmonic Brownian particle under a force ramp ---------

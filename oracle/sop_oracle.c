@@ -1202,3 +1202,51 @@ int orc_force_scale_par(const orc_system *s, const orc_params *p, const double *
     excl_free(&e);
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Force-spectroscopy observables (the pulling protocol of Section IV.B)    */
+/* ------------------------------------------------------------------------ */
+
+/* Running average: out[k] = (y[k] + ... + y[k + w - 1]) / w, k = 0 .. n - w,
+ * each window summed on its own. */
+int orc_running_average(const double *y, int64_t n, int32_t w, double *out)
+{
+    if (w < 1 || n < w)
+        return ORC_E_ARG;
+    for (int64_t k = 0; k + w <= n; ++k) {
+        double s = 0.0;
+        for (int32_t j = 0; j < w; ++j)
+            s += y[k + j];
+        out[k] = s / (double)w;
+    }
+    return ORC_OK;
+}
+
+/* Peak force: the largest w-point running average and its first window. */
+int orc_peak_force(const double *f, int64_t n, int32_t w, double *peak, int64_t *index)
+{
+    if (w < 1 || n < w)
+        return ORC_E_ARG;
+    double *a = (double *)malloc((size_t)(n - w + 1) * sizeof(double));
+    if (!a)
+        return ORC_E_ARG;
+    orc_running_average(f, n, w, a);
+    int64_t best = 0;
+    for (int64_t k = 1; k <= n - w; ++k)
+        if (a[k] > a[best])
+            best = k;
+    *peak = a[best];
+    *index = best;
+    free(a);
+    return ORC_OK;
+}
+
+/* End-to-end distance |x_last - x_first| of every trajectory (0 for fewer
+ * than two residues). */
+void orc_end_to_end(const orc_system *s, const double *x, double *R)
+{
+    for (int64_t t = 0; t < s->n_traj; ++t) {
+        int64_t a = s->res_offsets[t], b = s->res_offsets[t + 1];
+        R[t] = (b - a < 2) ? 0.0 : dist(x, b - 1, a);
+    }
+}
