@@ -194,12 +194,15 @@ sop_status sop_get_tile(const sop_ctx *ctx, int32_t *tile);
  * HIP graphs: 0 launches every kernel from the host; k > 0 captures k whole
  * list periods (k rebuilds and k*list_every steps) per graph and replays it
  * while that many steps remain from a period start.  Graphs are used only when
- * the energy interval is 0 or a multiple of k*list_every.  Default: 1.
+ * the energy interval is 0 or a multiple of k*list_every, and then start only
+ * on multiples of k*list_every, so every record step is a graph's first step.
+ * Changing k drops the graphs already captured.  Default: 1.
  */
 sop_status sop_set_graph_steps(sop_ctx *ctx, int32_t k);
 
 /* Record energies every k steps (k = 0: never).  Energies of step n are
- * those of the configuration the forces of step n use, before its update. */
+ * those of the configuration the forces of step n use, before its update.
+ * Changing k drops the graphs already captured. */
 sop_status sop_set_energy_interval(sop_ctx *ctx, int64_t k);
 
 /* ---- workspace ----------------------------------------------------------- */
@@ -231,9 +234,12 @@ sop_status sop_set_step(sop_ctx *ctx, int64_t step);
 sop_status sop_get_step(const sop_ctx *ctx, int64_t *step);
 
 /*
- * Advance n_steps steps, asynchronously on the context's stream.  Before the
- * forces of step n the Verlet list is rebuilt when n % list_every == 0 or
- * when it is stale.
+ * Advance n_steps steps of the first-order overdamped scheme (Eq. 2 with the
+ * h/xi coefficient of Algorithm 7): every residue that is not fixed moves by
+ * f_i h/xi + g_i sqrt(2 kB T h/xi), all forces taken at the positions of
+ * t_n.  Asynchronous on the context's stream.  Before the forces of step n
+ * the Verlet list is rebuilt when n % list_every == 0 or when it is stale.
+ * Device-side failures surface at the next synchronizing call.
  */
 sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
 
@@ -253,12 +259,16 @@ sop_status sop_step_timed(sop_ctx *ctx, int64_t n_steps, double *ms_out);
 
 /* ---- pair list ------------------------------------------------------------- */
 
-/* Rebuild the Verlet list from the current positions now. */
+/* Rebuild the Verlet list (Section III.A, Algorithm 3) from the current
+ * positions now: every pair of one trajectory that is neither bonded nor
+ * native and whose single-precision distance is below r_list.  Asynchronous;
+ * a row longer than the list capacity is SOP_E_LIST_OVERFLOW at the next
+ * synchronizing call. */
 sop_status sop_build_pairlist(sop_ctx *ctx);
 
 /*
- * Copy the current list as the sorted set of pairs (i < j), lexicographic,
- * into host int32[2*cap].  *n_pairs receives the list size; if it exceeds
+ * Copy the current list (Algorithm 3) as the sorted set of pairs (i < j),
+ * lexicographic, into host int32[2*cap].  *n_pairs receives the list size; if it exceeds
  * cap, nothing is copied and SOP_E_ARG is returned.  Synchronizes.
  */
 sop_status sop_get_pairlist(sop_ctx *ctx, int64_t cap, int32_t *ij_host, int64_t *n_pairs);
@@ -266,8 +276,10 @@ sop_status sop_get_pairlist(sop_ctx *ctx, int64_t cap, int32_t *ij_host, int64_t
 /* ---- forces and energies ---------------------------------------------------- */
 
 /*
- * Forces and energies at the current positions and step without moving
- * anything; the list is rebuilt first when a step would rebuild it (stale,
+ * The forces f_i = -grad_i V of Eq. 1 (FENE bonds, native 12-6 contacts and
+ * the (sigma/r)^6 repulsion over the list, each pair once per partner as in
+ * Algorithms 1-2, plus the external terms) and the per-term energies at the
+ * current positions and step, without moving anything; the list is rebuilt first when a step would rebuild it (stale,
  * or step % list_every == 0).  f_host: double[3*n_res]
  * or NULL; energies_host: double[n_traj*SOP_NTERMS] or NULL; f_ext_host:
  * double[n_traj] or NULL (reported external force).  Synchronizes.
@@ -291,6 +303,35 @@ sop_status sop_get_external_force(sop_ctx *ctx, double *f_ext_host);
  * NULL.  Does not advance anything.  Synchronizes.
  */
 sop_status sop_sample_noise(sop_ctx *ctx, int64_t step, uint32_t *words_host, double *g_host);
+
+/* ---- force-spectroscopy observables (host arrays; no device work) ----------- */
+
+/*
+ * Running average of a recorded force trace (the smoothing of the pulling
+ * protocol, Section IV.B): out[k] = (y[k] + ... + y[k+w-1]) / w for
+ * k = 0 .. n-w, out has n-w+1 entries.  The windows are differences of
+ * double-double prefix sums, so each is accurate to the last bit of a double
+ * whatever n.  SOP_E_ARG for null pointers, w < 1 or n < w.
+ */
+sop_status sop_running_average(const double *y, int64_t n, int32_t w, double *out);
+
+/*
+ * Peak (unfolding) force of a trace: the largest w-point running average and
+ * the index of its first window (the first of equal maxima).  SOP_E_ARG as
+ * above.
+ */
+sop_status sop_peak_force(const double *f, int64_t n, int32_t w, double *peak, int64_t *index);
+
+/*
+ * Temperature from the virial (the paper plots a temperature without
+ * defining it; this is the equipartition estimate): for a free chain of
+ * n_res residues (no external terms, no fixed residues) the internal virial
+ * W = -sum over pairs of r dV/dr averages to -3 (n_res - 1) kB T, so
+ * T = -mean(W) / (3 (n_res - 1) kB) over n_records recorded virials.
+ * SOP_E_ARG for null pointers, n_records < 1, n_res < 2 or kB <= 0.
+ */
+sop_status sop_virial_temperature(const double *virial, int64_t n_records, int64_t n_res, double kB,
+                                  double *T);
 
 /* ---- synchronization and errors ----------------------------------------------- */
 

@@ -15,5 +15,8 @@ from ._sop import (  # noqa: F401
     declared_functions,
     from_system,
     lib,
+    peak_force,
+    running_average,
     status_string,
+    virial_temperature,
 )

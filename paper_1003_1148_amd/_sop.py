@@ -85,6 +85,9 @@ def lib():
             "sop_synchronize": [vp],
             "sop_sample_noise": [vp, i64, vp, vp],
             "sop_step_timed": [vp, i64, vp],
+            "sop_running_average": [vp, i64, i32, vp],
+            "sop_peak_force": [vp, i64, i32, vp, vp],
+            "sop_virial_temperature": [vp, i64, i64, dbl, vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -296,6 +299,37 @@ class Context:
 
 def status_string(st):
     return lib().sop_status_string(int(st)).decode()
+
+
+def _check_host(st, what):
+    if st != 0:
+        raise SopError(st, what)
+
+
+def running_average(y, w):
+    """w-point running average of a trace (sop_running_average)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n = len(y)
+    out = np.zeros(max(n - int(w) + 1, 1))
+    _check_host(lib().sop_running_average(_p(y), n, int(w), _p(out)), "running average")
+    return out[:n - int(w) + 1]
+
+
+def peak_force(f, w):
+    """(largest w-point running average, index of its first window)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    pk, ix = C.c_double(0.0), C.c_int64(0)
+    _check_host(lib().sop_peak_force(_p(f), len(f), int(w), C.byref(pk), C.byref(ix)), "peak force")
+    return pk.value, ix.value
+
+
+def virial_temperature(virial, n_res, kB):
+    """Equipartition temperature of a free chain from recorded virials."""
+    v = np.ascontiguousarray(virial, dtype=np.float64)
+    T = C.c_double(0.0)
+    _check_host(lib().sop_virial_temperature(_p(v), len(v), int(n_res), float(kB), C.byref(T)),
+                "virial temperature")
+    return T.value
 
 
 def from_system(system, params, stream=None, tile=0, graph_steps=1, energy_every=0,

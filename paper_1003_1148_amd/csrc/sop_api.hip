@@ -837,6 +837,8 @@ sop_status sop_set_graph_steps(sop_ctx *c, int32_t k)
 {
     if (!c || k < 0)
         return SOP_E_ARG;
+    if (k != c->graph_steps)
+        destroy_graphs(c);  // captured graphs hold the old span
     c->graph_steps = k;
     return SOP_OK;
 }
@@ -845,6 +847,8 @@ sop_status sop_set_energy_interval(sop_ctx *c, int64_t k)
 {
     if (!c || k < 0)
         return SOP_E_ARG;
+    if (k != c->energy_every)
+        destroy_graphs(c);  // batched graphs hold the interval as a kernel argument
     c->energy_every = k;
     return SOP_OK;
 }
@@ -1189,12 +1193,15 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
     const int L = c->p.list_every;
     const long long E = c->energy_every;
     const long long span = (long long)L * std::max(c->graph_steps, 1);
-    // graphs replay whole list periods; energies must fall on graph starts
+    // graphs replay whole list periods and record energies only at their
+    // first step: with an energy interval (a multiple of the span) a graph
+    // starts only on a multiple of the span, so no record step falls inside
     const bool graphs_ok = c->graph_steps > 0 && (E == 0 || E % span == 0);
+    const long long align = E > 0 ? span : L;
     bool base_set = false;
     long long q = 0;
     while (q < n_steps) {
-        if (graphs_ok && c->step % L == 0 && n_steps - q >= span) {
+        if (graphs_ok && c->step % align == 0 && n_steps - q >= span) {
             const int en = (E > 0 && c->step % E == 0) ? 1 : 0;
             if (!c->graphs[c->cur][en]) {
                 st = capture_graph(c, c->cur, en);

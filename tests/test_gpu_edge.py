@@ -6,7 +6,7 @@ chains just below, at and above one 64-residue tile, a trajectory of three
 chains (one of them a single residue, so that natives cross chains and a
 tile starts inside a trajectory), and a 1,024-residue chain, the longest a
 batched workgroup holds. Pair lists must be bit-exact, forces within 1e-5
-(L2), 60-step trajectories (six list rebuilds) within 1e-4 A, and the
+(L2 and residue by residue against the oracle's force scale), 60-step trajectories (six list rebuilds) within 1e-4 A, and the
 energies of the empty trajectories exactly zero.
 """
 import sys
@@ -16,6 +16,8 @@ import pytest
 
 from synth import RunParams
 from synth.structures import _system, saw_batch
+
+from parity import assert_energies, assert_forces, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -94,11 +96,9 @@ def test_edge_pairlist_and_forces(P, orc, edge, schedule):
     o = orc.OracleSystem(s, RunParams())
     assert np.array_equal(c.get_pairlist(), o.pairlist(x))
     F, E, _ = c.compute_forces()
-    Fo, Eo, _, st = o.forces(x)
-    assert st == 0
-    err = float(np.linalg.norm(F - Fo) / np.linalg.norm(Fo))
-    log(f"  force rel err {err:.3e}")
-    assert err <= FORCE_TOL
+    Fo, Eo, _, S, Em = oracle_reference(o, x)
+    assert_forces(F, Fo, S, f"edge {schedule}")
+    assert_energies(E, Eo, Em, s.res_offsets, f"edge {schedule}")
     assert np.all(F[s.res_offsets[0]] == 0.0)  # the single residue feels nothing
     empty = np.nonzero(np.diff(s.res_offsets) == 0)[0]
     assert np.all(E[empty] == 0.0) and np.all(Eo[empty] == 0.0)
@@ -112,7 +112,10 @@ def test_edge_trajectory_60_steps(P, orc, edge, schedule):
     c.step(60)
     xg = c.get_coordinates()
     Eg, estep = c.get_energies()
-    xo, Eo, _, st = orc.OracleSystem(s, p).run(x, 60, energy_every=20)
+    o = orc.OracleSystem(s, p)
+    x40, _, _, st = o.run(x, 40)
+    assert st == 0
+    xo, Eo, _, st = o.run(x40, 20, step0=40, energy_every=20)
     assert st == 0
     d = np.linalg.norm(xg - xo, axis=1)
     log(f"  {schedule}: 60-step max |dx| {d.max():.3e} A")
@@ -120,7 +123,5 @@ def test_edge_trajectory_60_steps(P, orc, edge, schedule):
     assert estep == 40
     empty = np.nonzero(np.diff(s.res_offsets) == 0)[0]
     assert np.all(Eg[empty] == 0.0)
-    n = np.maximum(np.diff(s.res_offsets), 1)
-    for t in range(s.n_traj):
-        for k in range(4):
-            assert abs(Eg[t, k] - Eo[-1][t, k]) <= FORCE_TOL * max(abs(Eo[-1][t, k]), n[t] * p.kBT)
+    _, Em = o.force_scale(x40, step=40)
+    assert_energies(Eg, Eo[0], Em, s.res_offsets, f"edge {schedule} step 40")

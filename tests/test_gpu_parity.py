@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Bars: Philox words and pair lists bit-exact; forces within a relative L2
-error of 1e-5; 200-step trajectories within 1e-4 A per residue; graph
-replays, repeated runs and checkpoint/resume bit-identical.
+error of 1e-5 and, residue by residue, within 1e-5 of the oracle's force
+scale S_i (tests/parity.py); energies term by term within 1e-5 of the
+oracle's magnitude sums; 200-step trajectories within 1e-4 A per residue;
+graph replays, repeated runs and checkpoint/resume bit-identical.
 """
 import math
 import sys
@@ -12,6 +14,8 @@ import pytest
 
 from synth import RunParams, make_config
 from synth.structures import Tip
+
+from parity import assert_energies, assert_forces, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -64,10 +68,6 @@ def perturbed(s, sd=0.15, seed=1):
     every FENE bond of the largest workload well inside |r - r0| < R0."""
     rng = np.random.default_rng(seed)
     return s.x + sd * rng.standard_normal(s.x.shape)
-
-
-def rel_l2(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def ctx_for(P, s, p=None, x=None, **kw):
@@ -156,33 +156,22 @@ def test_pairlist_after_dynamics(P, orc):
 # forces and energies
 # --------------------------------------------------------------------------
 
-def _energy_close(Eg, Eo, n_res, kBT=RunParams().kBT):
-    """Each recorded term within FORCE_TOL of the oracle, relative to the term
-    or to the thermal scale N kBT, whichever is larger: a sum with heavy
-    cancellation (the virial of a strained configuration) carries the single-
-    precision rounding of its O(N) contributions, not of its net value."""
-    floor = n_res * kBT
-    for k in range(5):
-        assert abs(Eg[k] - Eo[k]) <= FORCE_TOL * max(abs(Eo[k]), floor), (k, Eg[k], Eo[k])
-
-
+@pytest.mark.parametrize("start", ["perturbed", "native"])
 @pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3s", "c4"])
-def test_forces_and_energies(P, orc, name):
+def test_forces_and_energies(P, orc, name, start):
+    """At a perturbed start and at the generated (native) structure, where the
+    bonded and native terms vanish and the list pairs carry the force."""
     s = cfg(name)
-    x = perturbed(s)
-    log(f"forces {name} n={s.n_res}")
+    x = perturbed(s) if start == "perturbed" else s.x.copy()
+    log(f"forces {name} ({start}) n={s.n_res}")
     c = ctx_for(P, s, x=x)
     c.set_step(1234)
     F, E, fe = c.compute_forces()
     o = orc.OracleSystem(s, RunParams())
-    Fo, Eo, feo, st = o.forces(x, step=1234)
-    assert st == 0
-    err = rel_l2(F, Fo)
-    log(f"  force rel err {err:.3e}")
-    assert err <= FORCE_TOL
-    for t in range(s.n_traj):
-        _energy_close(E[t], Eo[t], s.res_offsets[t + 1] - s.res_offsets[t])
-    assert np.allclose(fe, feo, rtol=1e-5, atol=1e-6)
+    Fo, Eo, feo, S, Em = oracle_reference(o, x, step=1234)
+    assert_forces(F, Fo, S, f"{name} {start}")
+    assert_energies(E, Eo, Em, s.res_offsets, f"{name} {start}")
+    assert np.allclose(fe, feo, rtol=1e-5, atol=1e-9)
 
 
 @pytest.mark.parametrize("tile", [64, 128, 256])
@@ -191,9 +180,9 @@ def test_forces_all_tile_sizes(P, orc, tile):
     x = perturbed(s, seed=2)
     c = ctx_for(P, s, x=x, tile=tile)
     F, E, _ = c.compute_forces()
-    Fo, Eo, _, _ = orc.OracleSystem(s, RunParams()).forces(x)
-    assert rel_l2(F, Fo) <= FORCE_TOL
-    _energy_close(E[0], Eo[0], s.n_res)
+    Fo, Eo, _, S, Em = oracle_reference(orc.OracleSystem(s, RunParams()), x)
+    assert_forces(F, Fo, S, f"tile {tile}")
+    assert_energies(E, Eo, Em, s.res_offsets, f"tile {tile}")
 
 
 def test_newton_third_law_on_gpu(P):
@@ -220,13 +209,16 @@ def test_trajectory_200_steps(P, orc, name):
     xg = c.get_coordinates()
     Eg, estep = c.get_energies()
     o = orc.OracleSystem(s, p)
-    xo, Eo, _, st = o.run(s.x, 200, energy_every=10)
+    x190, _, _, st = o.run(s.x, 190)
+    assert st == 0
+    xo, Eo, _, st = o.run(x190, 10, step0=190, energy_every=10)
     assert st == 0
     d = np.linalg.norm(xg - xo, axis=1).max()
     log(f"  max |dx| {d:.3e} A")
     assert d <= TRAJ_TOL
     assert estep == 190
-    _energy_close(Eg[0], Eo[-1][0], s.n_res)
+    _, Em = o.force_scale(x190, step=190)
+    assert_energies(Eg, Eo[0], Em, s.res_offsets, f"{name} step 190")
 
 
 @pytest.mark.parametrize("tile", [128, 256])
@@ -238,14 +230,18 @@ def test_trajectory_other_tile_sizes(P, orc, tile):
     p = RunParams()
     c = ctx_for(P, s, p, tile=tile, energy_every=10)
     c.step(100)
-    xo, Eo, _, st = orc.OracleSystem(s, p).run(s.x, 100, energy_every=10)
+    o = orc.OracleSystem(s, p)
+    x90, _, _, st = o.run(s.x, 90)
+    assert st == 0
+    xo, Eo, _, st = o.run(x90, 10, step0=90, energy_every=10)
     assert st == 0
     d = float(np.linalg.norm(c.get_coordinates() - xo, axis=1).max())
     log(f"  tile {tile}: 100-step max |dx| {d:.3e} A")
     assert d <= TRAJ_TOL
     Eg, estep = c.get_energies()
     assert estep == 90
-    _energy_close(Eg[0], Eo[-1][0], s.n_res)
+    _, Em = o.force_scale(x90, step=90)
+    assert_energies(Eg, Eo[0], Em, s.res_offsets, f"tile {tile} step 90")
 
 
 def test_graph_replay_equals_direct_launches(P):
@@ -259,6 +255,28 @@ def test_graph_replay_equals_direct_launches(P):
     Ea, sa = a.get_energies()
     Eb, sb = b.get_energies()
     assert sa == sb == 40
+    assert np.array_equal(Ea, Eb)
+
+
+def test_graph_span_change_and_energy_alignment(P):
+    """Changing the graph span drops the captured graphs, and a graph never
+    starts where a record step would fall inside it: with 2-period graphs and
+    energies every 20 steps, steps [10, 40] from 0 record step 40, exactly as
+    kernel-by-kernel launches do."""
+    s = cfg("c1")
+    a = ctx_for(P, s, graph_steps=1, energy_every=20)
+    b = ctx_for(P, s, graph_steps=0, energy_every=20)
+    a.step(20)
+    b.step(20)
+    a.set_graph_steps(2)
+    for n in [10, 40]:
+        a.step(n)
+        b.step(n)
+    assert a.get_step() == b.get_step() == 70
+    assert np.array_equal(a.get_coordinates(), b.get_coordinates())
+    Ea, sa = a.get_energies()
+    Eb, sb = b.get_energies()
+    assert sa == sb == 60
     assert np.array_equal(Ea, Eb)
 
 

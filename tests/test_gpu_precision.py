@@ -15,6 +15,8 @@ import pytest
 
 from synth import RunParams, make_config
 
+from parity import force_errors
+
 pytestmark = pytest.mark.gpu
 
 FORCE_TOL = 1e-5
@@ -62,14 +64,17 @@ def test_fibre_end_force_error_and_drift(P, orc):
         assert st == 0
         xg = c.get_coordinates()
         F, _, _ = c.compute_forces()
-        Fo, _, _, st = o.forces(xg, step=100 * k)
+        pairs = o.pairlist(xg)
+        Fo, _, _, st = o.forces(xg, step=100 * k, pairs=pairs)
         assert st == 0
-        ferr = float(np.linalg.norm(F - Fo) / np.linalg.norm(Fo))
+        S, _ = o.force_scale(xg, step=100 * k, pairs=pairs)
+        ferr, ew, _, zero_ok = force_errors(F, Fo, S)
+        assert zero_ok
         d = np.linalg.norm(xg - xo, axis=1)
-        rows.append((100 * k, ferr, float(np.sqrt((d * d).mean())), float(d.max())))
-    log("step  force_rel_err  rms_dx_A  max_dx_A")
+        rows.append((100 * k, ferr, ew, float(np.sqrt((d * d).mean())), float(d.max())))
+    log("step  force_rel_err  max_res_err/S  rms_dx_A  max_dx_A")
     for r in rows:
-        log(f"{r[0]:5d}  {r[1]:.3e}  {r[2]:.3e}  {r[3]:.3e}")
-    assert all(r[1] <= FORCE_TOL for r in rows)
-    assert rows[1][3] <= TRAJ_TOL          # 200 steps
-    assert rows[-1][3] <= 10 * TRAJ_TOL    # 1,000 steps: still far below the FP32 spacing
+        log(f"{r[0]:5d}  {r[1]:.3e}  {r[2]:.3e}  {r[3]:.3e}  {r[4]:.3e}")
+    assert all(r[1] <= FORCE_TOL and r[2] <= FORCE_TOL for r in rows)
+    assert rows[1][4] <= TRAJ_TOL          # 200 steps
+    assert rows[-1][4] <= 10 * TRAJ_TOL    # 1,000 steps: still far below the FP32 spacing
