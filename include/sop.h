@@ -243,12 +243,48 @@ sop_status sop_get_step(const sop_ctx *ctx, int64_t *step);
  */
 sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
 
+/* Force evaluation of the plain schedule. */
+enum {
+    SOP_FORCES_PARTICLE = 0, /* each residue sums its own rows (Algorithms 1-2): every pair is
+                                evaluated in both rows, with no write conflicts; deterministic */
+    SOP_FORCES_PAIR = 1      /* each pair once (Algorithm 4), +df / -df added to both residues
+                                with hardware float atomics and gathered in the update kernel
+                                (Algorithm 5); reproducible to rounding only */
+};
+
+/*
+ * Choose the plain schedule's force evaluation (SOP_FORCES_*; default
+ * particle-based).  Both evaluate the same list and the same terms.
+ * sop_autotune tries both.  SOP_E_ARG for an unknown mode.
+ */
+sop_status sop_set_force_mode(sop_ctx *ctx, int32_t mode);
+sop_status sop_get_force_mode(const sop_ctx *ctx, int32_t *mode);
+
+/*
+ * Verlet skin of the plain schedule (Section III.A keeps a list of the pairs
+ * closer than r_list and rebuilds it every list_every steps).  The cell-grid
+ * search runs at r_list + skin and is repeated only when some residue has
+ * moved more than skin/2 (less 0.01) since the last search; every rebuild
+ * filters those rows with the list predicate at r_list, which gives exactly
+ * the list a search over all pairs would give.  skin = 0 searches at every
+ * rebuild.  Default 4 (the caller's length unit).  SOP_E_ARG for a negative
+ * or non-finite skin or one above 4 r_list.  Takes effect at the next
+ * rebuild.
+ */
+sop_status sop_set_list_skin(sop_ctx *ctx, double skin);
+
+/* Rebuilds of the list and cell-grid searches of the skin since the
+ * workspace was bound (plain schedule).  Synchronizes. */
+sop_status sop_get_list_stats(sop_ctx *ctx, int64_t *rebuilds, int64_t *skin_builds);
+
 /*
  * Kernel timing (measurement only).  Plain schedule: the fused step kernel
  * and, separately, the list rebuild (all its kernels) are each captured
  * n_steps times back to back in one HIP graph and timed with a pair of HIP
  * events on the context's stream around the graph launch; ms_out[0] = mean
- * step-kernel duration, ms_out[1] = mean rebuild duration, ms_out[2] = 1.
+ * step-kernel duration, ms_out[1] = mean rebuild duration with the skin's
+ * cell-grid search, ms_out[2] = mean rebuild duration that only filters the
+ * skin rows.
  * The step launches reuse the current list, so the coordinates and the list
  * are restored afterwards (the step counter does not move).  Batched schedule:
  * n_steps steps in persistent launches, each timed with events and waited
@@ -332,6 +368,74 @@ sop_status sop_peak_force(const double *f, int64_t n, int32_t w, double *peak, i
  */
 sop_status sop_virial_temperature(const double *virial, int64_t n_records, int64_t n_res, double kB,
                                   double *T);
+
+/* ---- accuracy of the integrators (Section IV.C) ------------------------------ */
+
+/*
+ * The exactly solvable model the paper uses to measure integrator accuracy:
+ * independent Brownian particles X in a one-dimensional harmonic well
+ * V = k_sp X^2 / 2, pulled by the force ramp f = rf t, with friction xi
+ * (tau = xi / k_sp).  Step k (t_k = k h) moves each particle by
+ *   order 1:  c (rf t_k - k_sp X),         c = h / xi,
+ *   order 2:  c (rf t_k - k_sp X),         c = (h / xi)(1 - h / (2 tau)),
+ * plus sqrt(2 kBT h / xi) g, so that the ensemble mean obeys Eq. 4 (order 1)
+ * or Eq. 5 (order 2) exactly and approaches Eq. 3.  g is the first Box-Muller
+ * Gaussian of Philox4x32-10 with key = seed and counter = (particle index,
+ * stream, k low word, k high word), the same map as sop_sample_noise's axis 0.
+ * kBT = 0 runs the noise-free recursions.  The ramp force is formed in double
+ * precision, the rest in single precision.
+ */
+typedef struct sop_ramp_params {
+    double rf;          /* ramp rate of the force (force / time) */
+    double xi;          /* friction, > 0 */
+    double k_sp;        /* spring constant of the well, >= 0 */
+    double kBT;         /* thermal energy, >= 0 (0: no noise) */
+    double h;           /* time step, > 0 */
+    uint64_t seed;      /* Philox key */
+    uint32_t stream;    /* second Philox counter word */
+    int32_t order;      /* 1 or 2 */
+    int32_t compensated;/* 1: X = hi + lo updated by TwoSum; 0: X = hi in plain single precision */
+    int32_t pad;
+} sop_ramp_params;
+
+/* Device bytes sop_ramp_run needs for the moment reduction of n_particles. */
+sop_status sop_ramp_workspace_size(int64_t n_particles, size_t *bytes);
+
+/*
+ * Advance n_particles particles from step step0 by n_steps steps, then (when
+ * moments is not NULL) write the ensemble mean and population variance of
+ * X = hi + lo, summed in double precision in a fixed order, to moments.
+ *   x          device float[2*n_particles], {hi, lo} per particle, read and
+ *              written in place (lo is ignored and left unchanged when
+ *              compensated = 0);
+ *   workspace  device scratch of at least sop_ramp_workspace_size bytes,
+ *              8-byte aligned, owned by the caller (unused when moments is
+ *              NULL);
+ *   moments    device double[2] or NULL;
+ *   hip_stream the stream to run on (NULL: the default stream).
+ * Asynchronous.  SOP_E_ARG for a null rp or x, n_particles outside
+ * [1, 2^31 - 1], negative step0 or n_steps, an order other than 1 or 2, or
+ * xi <= 0, k_sp < 0, kBT < 0, h <= 0 or a non-finite rf; SOP_E_WORKSPACE for a
+ * missing, misaligned or short workspace; SOP_E_HIP for a launch failure.
+ */
+sop_status sop_ramp_run(const sop_ramp_params *rp, int64_t n_particles, float *x, int64_t step0,
+                        int64_t n_steps, void *workspace, size_t workspace_bytes, double *moments,
+                        void *hip_stream);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid it): sop_ramp_run without a
+ * workspace.  The moment reduction's block sums live in a fixed library
+ * array of 2 * 1024 doubles (16 KiB) per GPU, held until the process ends;
+ * the reduction uses at most 1024 blocks, so every n_particles the call
+ * accepts fits.  Same arguments, results and errors as sop_ramp_run (the
+ * workspace errors aside); SOP_E_HIP if the array's device address cannot
+ * be found.  Calls no allocating routine.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams or host
+ * threads) race, so the caller serializes them.
+ */
+sop_status sop_ramp_run_static(const sop_ramp_params *rp, int64_t n_particles, float *x, int64_t step0,
+                               int64_t n_steps, double *moments, void *hip_stream);
 
 /* ---- synchronization and errors ----------------------------------------------- */
 

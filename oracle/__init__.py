@@ -87,6 +87,15 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_force_scale.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
         L.orc_force_scale.restype = C.c_int
+        L.orc_force_stiffness.argtypes = [vp, vp, vp, i64, vp, i64, vp]
+        L.orc_force_stiffness.restype = C.c_int
+        L.orc_force_stiffness_par.argtypes = [vp, vp, vp, i64, vp, C.c_int]
+        L.orc_force_stiffness_par.restype = C.c_int
+        for nm in ("orc_fene_d2", "orc_native_d2", "orc_repulsive_d2"):
+            getattr(L, nm).restype = C.c_double
+        L.orc_fene_d2.argtypes = [C.c_double] * 4
+        L.orc_native_d2.argtypes = [C.c_double] * 3
+        L.orc_repulsive_d2.argtypes = [C.c_double] * 3
         L.orc_forces_par.argtypes = [vp, vp, vp, i64, vp, vp, vp, C.c_int]
         L.orc_forces_par.restype = C.c_int
         L.orc_run_par.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, i64, vp, C.c_int]
@@ -214,6 +223,33 @@ class OracleSystem:
             raise RuntimeError(f"oracle force_scale status {st}")
         return S, Em
 
+    def force_stiffness(self, x, step=0, pairs=None):
+        """Per-residue stiffness scale K_i: the sum of r |d^2E/dr^2| over the
+        residue's pairs plus its external terms' change per relative change
+        of their distances."""
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if pairs is None:
+            pairs = self.pairlist(x)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+        K = np.zeros(self.sysm.n_res)
+        st = L.orc_force_stiffness(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(pairs),
+                                   len(pairs), _ptr(K))
+        if st != OK:
+            raise RuntimeError(f"oracle force_stiffness status {st}")
+        return K
+
+    def force_stiffness_par(self, x, step=0, threads=0):
+        """Residue-parallel K (list rebuilt at x)."""
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        K = np.zeros(self.sysm.n_res)
+        st = L.orc_force_stiffness_par(C.byref(self.s), C.byref(self.p), _ptr(x), int(step), _ptr(K),
+                                       int(threads or default_threads()))
+        if st != OK:
+            raise RuntimeError(f"oracle force_stiffness_par status {st}")
+        return K
+
     def forces_par(self, x, step=0, threads=0):
         """Residue-parallel forces with the list rebuilt at x; (F, E, f_ext, status)."""
         L = lib()
@@ -335,6 +371,18 @@ def gauss3(seed, local, stream, step):
     g = np.zeros(3)
     lib().orc_gauss3(int(seed), int(local), int(stream), int(step), _ptr(g))
     return g
+
+
+def fene_d2(r, r0, k, R0):
+    return lib().orc_fene_d2(float(r), float(r0), float(k), float(R0))
+
+
+def native_d2(r, r0, eps):
+    return lib().orc_native_d2(float(r), float(r0), float(eps))
+
+
+def repulsive_d2(r, sigma, eps):
+    return lib().orc_repulsive_d2(float(r), float(sigma), float(eps))
 
 
 def fene(r, r0, k, R0):

@@ -189,6 +189,27 @@ double orc_repulsive(double r, double sigma, double eps, double *dEdr)
     return eps * q;
 }
 
+/* Second derivatives d^2E/dr^2 of the three pair terms (the derivatives of
+ * the dE/dr above): they set how much a pair's force moves when its distance
+ * is perturbed, which is what rounding the distance does. */
+double orc_fene_d2(double r, double r0, double k, double R0)
+{
+    double d = r - r0, u = (d * d) / (R0 * R0), x = 1.0 - u;
+    return x > 0.0 ? k * (1.0 + u) / (x * x) : 0.0;
+}
+
+double orc_native_d2(double r, double r0, double eps)
+{
+    double q = pow(r0 / r, 6.0);
+    return 12.0 * eps * (13.0 * q * q - 7.0 * q) / (r * r);
+}
+
+double orc_repulsive_d2(double r, double sigma, double eps)
+{
+    double q = pow(sigma / r, 6.0);
+    return 42.0 * eps * q / (r * r);
+}
+
 /* ------------------------------------------------------------------------ */
 /* helpers: trajectory of a residue and the sorted bonded/native partners    */
 /* ------------------------------------------------------------------------ */
@@ -782,6 +803,68 @@ int orc_force_scale(const orc_system *s, const orc_params *p, const double *x, i
     return broken ? ORC_E_FENE : ORC_OK;
 }
 
+/*
+ * The stiffness scale: K[i] = the sum over the bonded, native and listed
+ * pairs containing i of r |d^2E/dr^2|, plus, for every external term on i,
+ * its force's change per relative change of its own distance (the
+ * cantilever: kappa |A - x_i|, the magnitude of its force; the tip:
+ * |d^2E/ds^2| |x_i - T| for the gap s = |x_i - T| - R).  A relative error
+ * eta in every distance moves F_i by at most about eta K[i], which S[i]
+ * cannot bound where the pair forces vanish (at r = r0 both the FENE and the
+ * native terms of Eq. 1 are at their minima: dE/dr = 0 but d^2E/dr^2 > 0).
+ */
+int orc_force_stiffness(const orc_system *s, const orc_params *p, const double *x, int64_t step,
+                        const int32_t *list_ij, int64_t n_list, double *K)
+{
+    memset(K, 0, (size_t)s->n_res * sizeof(double));
+    for (int64_t b = 0; b < s->n_bonds; ++b) {
+        int64_t i = s->bonds[2 * b], j = s->bonds[2 * b + 1];
+        double r = dist(x, i, j);
+        double v = r * fabs(orc_fene_d2(r, s->bond_r0[b], p->k_fene, p->R0));
+        K[i] += v;
+        K[j] += v;
+    }
+    for (int64_t b = 0; b < s->n_native; ++b) {
+        int64_t i = s->natives[2 * b], j = s->natives[2 * b + 1];
+        double r = dist(x, i, j);
+        double v = r * fabs(orc_native_d2(r, s->native_r0[b], p->eps_h));
+        K[i] += v;
+        K[j] += v;
+    }
+    for (int64_t b = 0; b < n_list; ++b) {
+        int64_t i = list_ij[2 * b], j = list_ij[2 * b + 1];
+        double r = dist(x, i, j);
+        double v = r * fabs(orc_repulsive_d2(r, p->sigma, p->eps_l));
+        K[i] += v;
+        K[j] += v;
+    }
+    double tn = (double)step * p->h;
+    for (int64_t t = 0; t < s->n_traj; ++t)
+        for (int64_t i = s->res_offsets[t]; i < s->res_offsets[t + 1]; ++i) {
+            for (int32_t k = 0; k < s->n_pull; ++k) {
+                if (s->pull_traj[k] != t || s->pull_res[k] != i)
+                    continue;
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double d = s->pull_anchor0[3 * k + a] + s->pull_v[3 * k + a] * tn - x[3 * i + a];
+                    d2 += d * d;
+                }
+                K[i] += s->pull_kappa[k] * sqrt(d2);
+            }
+            if (s->has_tip) {
+                double r2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double d = x[3 * i + a] - (s->tip_c0[a] + s->tip_v[a] * tn);
+                    r2 += d * d;
+                }
+                double rr = sqrt(r2), gap = rr - s->tip_radius;
+                if (gap > 0.0)
+                    K[i] += rr * orc_repulsive_d2(gap, s->tip_sigma, s->tip_eps);
+            }
+        }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The same dynamics, residue-parallel (OpenMP): each residue's force is    */
 /* gathered from its own partners (the particle-based form of Algorithm 2)  */
@@ -1195,6 +1278,64 @@ int orc_force_scale_par(const orc_system *s, const orc_params *p, const double *
         }
         if (broken)
             st = ORC_E_FENE;
+    }
+    free(r.ptr);
+    free(r.col);
+    topo_rows_free(&tr);
+    excl_free(&e);
+    return st;
+}
+
+/* Residue-parallel form of orc_force_stiffness (list rebuilt at x). */
+int orc_force_stiffness_par(const orc_system *s, const orc_params *p, const double *x, int64_t step,
+                            double *K, int nthreads)
+{
+    excl_t e;
+    topo_rows_t tr;
+    rows_t r = {NULL, NULL};
+    if (nthreads <= 0)
+        nthreads = 1;
+    if (excl_build(s, &e) != ORC_OK || topo_rows_build(s, &tr) != ORC_OK)
+        return ORC_E_ARG;
+    int st = rows_build(s, p, &e, x, &r, nthreads);
+    if (st == ORC_OK) {
+        double tn = (double)step * p->h;
+#pragma omp parallel for schedule(dynamic, 512) num_threads(nthreads)
+        for (int64_t i = 0; i < s->n_res; ++i) {
+            double sum = 0.0;
+            for (int64_t k = tr.ptr[i]; k < tr.ptr[i + 1]; ++k) {
+                double rr = dist(x, i, tr.col[k]);
+                double d2 = k - tr.ptr[i] < tr.nb[i] ? orc_fene_d2(rr, tr.r0[k], p->k_fene, p->R0)
+                                                      : orc_native_d2(rr, tr.r0[k], p->eps_h);
+                sum += rr * fabs(d2);
+            }
+            for (int64_t k = r.ptr[i]; k < r.ptr[i + 1]; ++k) {
+                double rr = dist(x, i, r.col[k]);
+                sum += rr * fabs(orc_repulsive_d2(rr, p->sigma, p->eps_l));
+            }
+            int64_t t = traj_of(s, i);
+            for (int32_t q = 0; q < s->n_pull; ++q) {
+                if (s->pull_traj[q] != t || s->pull_res[q] != i)
+                    continue;
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double d = s->pull_anchor0[3 * q + a] + s->pull_v[3 * q + a] * tn - x[3 * i + a];
+                    d2 += d * d;
+                }
+                sum += s->pull_kappa[q] * sqrt(d2);
+            }
+            if (s->has_tip) {
+                double r2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double d = x[3 * i + a] - (s->tip_c0[a] + s->tip_v[a] * tn);
+                    r2 += d * d;
+                }
+                double rr = sqrt(r2), gap = rr - s->tip_radius;
+                if (gap > 0.0)
+                    sum += rr * orc_repulsive_d2(gap, s->tip_sigma, s->tip_eps);
+            }
+            K[i] = sum;
+        }
     }
     free(r.ptr);
     free(r.col);

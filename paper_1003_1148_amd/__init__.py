@@ -6,6 +6,8 @@ binding.
 """
 from ._sop import (  # noqa: F401
     Context,
+    FORCES_PAIR,
+    FORCES_PARTICLE,
     SopError,
     NTERMS,
     SCHEDULE_BATCHED,
@@ -16,6 +18,10 @@ from ._sop import (  # noqa: F401
     from_system,
     lib,
     peak_force,
+    ramp_params,
+    ramp_run,
+    ramp_run_static,
+    RampParams,
     running_average,
     status_string,
     virial_temperature,

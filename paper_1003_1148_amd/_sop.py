@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "sop.h")
 
 NTERMS = 5
 SCHEDULE_PLAIN, SCHEDULE_BATCHED = 0, 1
+FORCES_PARTICLE, FORCES_PAIR = 0, 1
 TERM_NAMES = ("fene", "native", "repulsive", "external", "virial")
 STATUS = {0: "SOP_OK", -1: "SOP_E_ARG", -2: "SOP_E_STATE", -3: "SOP_E_WORKSPACE",
           -4: "SOP_E_HIP", -5: "SOP_E_FENE", -6: "SOP_E_LIST_OVERFLOW",
@@ -85,9 +86,16 @@ def lib():
             "sop_synchronize": [vp],
             "sop_sample_noise": [vp, i64, vp, vp],
             "sop_step_timed": [vp, i64, vp],
+            "sop_set_list_skin": [vp, dbl],
+            "sop_set_force_mode": [vp, i32],
+            "sop_get_force_mode": [vp, vp],
+            "sop_get_list_stats": [vp, vp, vp],
             "sop_running_average": [vp, i64, i32, vp],
             "sop_peak_force": [vp, i64, i32, vp, vp],
             "sop_virial_temperature": [vp, i64, i64, dbl, vp],
+            "sop_ramp_workspace_size": [i64, vp],
+            "sop_ramp_run": [vp, i64, vp, i64, i64, vp, C.c_size_t, vp, vp],
+            "sop_ramp_run_static": [vp, i64, vp, i64, i64, vp, vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -201,6 +209,25 @@ class Context:
         self._check(lib().sop_get_tile(self.h, C.byref(v)))
         return v.value
 
+    def set_force_mode(self, mode):
+        """"particle" (default) or "pair" (SOP_FORCES_*)."""
+        m = {"particle": FORCES_PARTICLE, "pair": FORCES_PAIR}.get(mode, mode)
+        self._check(lib().sop_set_force_mode(self.h, int(m)))
+
+    def get_force_mode(self):
+        v = C.c_int32(0)
+        self._check(lib().sop_get_force_mode(self.h, C.byref(v)))
+        return "pair" if v.value == FORCES_PAIR else "particle"
+
+    def set_list_skin(self, skin):
+        self._check(lib().sop_set_list_skin(self.h, float(skin)))
+
+    def get_list_stats(self):
+        """(list rebuilds, skin cell-grid searches) since binding."""
+        a, b = C.c_int64(0), C.c_int64(0)
+        self._check(lib().sop_get_list_stats(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def set_graph_steps(self, k):
         self._check(lib().sop_set_graph_steps(self.h, int(k)))
 
@@ -247,8 +274,10 @@ class Context:
 
     def step_timed(self, n):
         """Kernel timing. Plain schedule: n back-to-back launches of the step
-        kernel, then n of the list rebuild, each timed as one graph; returns
-        (mean step-kernel ms, mean rebuild ms, 1) and leaves the state as it
+        kernel, then n of the list rebuild with the skin's cell-grid search,
+        then n of the rebuild that only filters the skin rows, each timed as
+        one graph; returns (mean step-kernel ms, mean search-and-filter
+        rebuild ms, mean filter-only rebuild ms) and leaves the state as it
         was. Batched: advances n steps; (mean persistent-launch ms, 0, steps
         per launch)."""
         ms = np.zeros(3)
@@ -330,6 +359,54 @@ def virial_temperature(virial, n_res, kB):
     _check_host(lib().sop_virial_temperature(_p(v), len(v), int(n_res), float(kB), C.byref(T)),
                 "virial temperature")
     return T.value
+
+
+class RampParams(C.Structure):
+    """sop_ramp_params: the harmonic Brownian particle under a force ramp."""
+    _fields_ = [(n, C.c_double) for n in ("rf", "xi", "k_sp", "kBT", "h")] + [
+        ("seed", C.c_uint64), ("stream", C.c_uint32), ("order", C.c_int32),
+        ("compensated", C.c_int32), ("pad", C.c_int32)]
+
+
+def ramp_params(rf, xi, k_sp, kBT, h, order=1, seed=0, stream=0, compensated=True):
+    return RampParams(float(rf), float(xi), float(k_sp), float(kBT), float(h), int(seed),
+                      int(stream), int(order), 1 if compensated else 0, 0)
+
+
+def ramp_run(rp, x, step0, n_steps, moments=True, stream=None):
+    """Advance the particles x (a torch float32 CUDA tensor of shape (M, 2):
+    hi, lo) in place by n_steps steps from step0 (sop_ramp_run).  With
+    moments, returns (mean, variance) of hi + lo after synchronizing."""
+    import torch
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape[-1] == 2
+    M = x.numel() // 2
+    nbytes = C.c_size_t(0)
+    _check_host(lib().sop_ramp_workspace_size(M, C.byref(nbytes)), "ramp workspace size")
+    ws = torch.empty(max(nbytes.value, 8), dtype=torch.uint8, device=x.device) if moments else None
+    mom = torch.zeros(2, dtype=torch.float64, device=x.device) if moments else None
+    s = _stream_handle(stream if stream is not None else torch.cuda.current_stream())
+    _check_host(lib().sop_ramp_run(C.byref(rp), M, x.data_ptr(), int(step0), int(n_steps),
+                                   ws.data_ptr() if moments else None, nbytes.value,
+                                   mom.data_ptr() if moments else None, s), "sop_ramp_run")
+    if not moments:
+        return None
+    m = mom.cpu().numpy()
+    return float(m[0]), float(m[1])
+
+
+def ramp_run_static(rp, x, step0, n_steps, moments_out=None, stream=None):
+    """sop_ramp_run_static: like ramp_run, allocating nothing.  moments_out
+    is a caller-owned float64 CUDA tensor of 2 elements (or None); the call
+    is asynchronous on the stream."""
+    import torch
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape[-1] == 2
+    if moments_out is not None:
+        assert moments_out.is_cuda and moments_out.dtype == torch.float64 and moments_out.numel() >= 2
+    s = _stream_handle(stream if stream is not None else torch.cuda.current_stream())
+    _check_host(lib().sop_ramp_run_static(C.byref(rp), x.numel() // 2, x.data_ptr(), int(step0),
+                                          int(n_steps),
+                                          None if moments_out is None else moments_out.data_ptr(), s),
+                "sop_ramp_run_static")
 
 
 def from_system(system, params, stream=None, tile=0, graph_steps=1, energy_every=0,

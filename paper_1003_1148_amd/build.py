@@ -6,7 +6,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsop.so")
-SOURCES = ["sop_api.hip", "sop_kernels.hip", "sop_observables.hip"]
+SOURCES = ["sop_api.hip", "sop_kernels.hip", "sop_observables.hip", "sop_ramp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -37,7 +37,14 @@ struct sop_ctx {
 
     // schedule: plain (kernel per step) or batched (persistent packs)
     int schedule = SOP_SCHEDULE_PLAIN;
-    int tile_req = 0, tile = 128, cap = 256;
+    int tile_req = 0, tile = 128, cap = 256, cap_req = 0;
+    // plain: the Verlet skin.  Rows of pairs within r_list + skin are built
+    // on the cell grid only when some residue has moved more than skin/2
+    // since the last such build; every rebuild filters them to r_list.
+    double skin = 4.0;
+    int force_mode = SOP_FORCES_PARTICLE;  // plain: particle- or pair-based force evaluation
+    long long skin_checked = -1;     // step at which the skin was last known valid
+    std::vector<double> xyz_set;     // the coordinates the grid was laid out for
     int graph_steps = 1;
     long long energy_every = 0;
     int batch_wg_req = 0, batch_wg = 1024, batch_steps = 100;
@@ -118,6 +125,15 @@ const char *bits_message(unsigned bits)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Row capacity: the requested one, else 512 entries for the plain schedule
+// (its skin rows hold the partners within r_list + skin) and 256 for the
+// batched one; a multiple of 16.
+int list_cap(const sop_ctx *c)
+{
+    const int cap = c->cap_req ? c->cap_req : (c->schedule == SOP_SCHEDULE_PLAIN ? 512 : 256);
+    return ((cap + 15) / 16) * 16;
+}
+
 // Workspace layout: returns total bytes; fills pointers when base != null.
 size_t layout(const sop_ctx *c, char *base, DevBufs *b)
 {
@@ -151,6 +167,14 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.tent = (float2 *)take(c->tent.size() * sizeof(float2));
     d.list_cnt = (int *)take(n * sizeof(int));
     d.list16 = (unsigned short *)take(list16_elems * sizeof(unsigned short));
+    d.fcnt = (int *)take((plain ? n : 0) * sizeof(int));
+    d.flist16 = (unsigned short *)take((plain ? list16_elems : 0) * sizeof(unsigned short));
+    d.hi_skin = (float4 *)take((plain ? n : 0) * sizeof(float4));
+    d.skin_flag = (unsigned *)take(sizeof(unsigned));
+    d.list_stats = (unsigned long long *)take(2 * sizeof(unsigned long long));
+    d.tile_ord = (unsigned char *)take(plain ? n_tiles_max * 256 : 0);
+    d.facc = (float4 *)take((plain ? n : 0) * sizeof(float4));
+    d.eacc = (double4 *)take((plain ? n : 0) * sizeof(double4));
     d.topo2 = (uint2 *)take(topo2_elems * sizeof(uint2));
     d.stage = (int *)take(stage_elems * sizeof(int));
     d.stage_cnt = (int *)take(n_tiles_max * sizeof(int));
@@ -296,10 +320,27 @@ StepConsts step_consts(const sop_ctx *c)
 
 float list_rc2(const sop_ctx *c) { return (float)(c->p.r_list * c->p.r_list); }
 
-// Cell edge slightly above the cutoff so that any pair passing the
+// The plain schedule's skin build radius r_list + skin (the batched schedule
+// builds its list directly).
+double skin_radius(const sop_ctx *c)
+{
+    return c->p.r_list + (c->schedule == SOP_SCHEDULE_PLAIN ? c->skin : 0.0);
+}
+float skin_rs2(const sop_ctx *c) { return (float)(skin_radius(c) * skin_radius(c)); }
+
+// Largest displacement since the skin build that keeps the skin valid
+// (squared; 0 = rebuild the skin at every rebuild): skin/2 less a margin
+// far above the rounding of the single-precision distances.
+float skin_check_thr2(const sop_ctx *c)
+{
+    const double thr = 0.5 * c->skin - 0.01;
+    return (c->schedule == SOP_SCHEDULE_PLAIN && thr > 0.0) ? (float)(thr * thr) : 0.0f;
+}
+
+// Cell edge slightly above the skin radius so that any pair passing the
 // single-precision predicate lies in adjacent cells despite rounding of the
 // cell index.
-float cell_edge(const sop_ctx *c) { return (float)(c->p.r_list * 1.002 + 0.05); }
+float cell_edge(const sop_ctx *c) { return (float)(skin_radius(c) * 1.002 + 0.05); }
 
 // Grid for the list rebuild.  Each trajectory's cells are shifted to its own
 // block of a lattice of trajectory boxes so that independent trajectories
@@ -385,16 +426,26 @@ sop_status need_ready(sop_ctx *c)
     return SOP_OK;
 }
 
-void rebuild(sop_ctx *c, hipStream_t s, bool advance)
+// Plain-schedule list rebuild at step c->step.  The skin is rebuilt first
+// unless the displacement check of the step before left it valid (graph
+// replays capture rebuilds that rely on that check: `captured`).
+void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false)
 {
-    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), c->n_traj > 1 ? 1 : 0, s, advance,
-                   c->p.list_every);
+    if (!captured && (c->skin_checked != c->step || skin_check_thr2(c) <= 0.0f))
+        launch_force_skin(c->b, s);
+    launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), skin_rs2(c),
+                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every);
 }
 
-void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy)
+// Whether step `step` is the last of a list period: its kernel checks the
+// displacements against the skin.
+bool checks_skin(const sop_ctx *c, long long step) { return (step + 1) % c->p.list_every == 0; }
+
+void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy, bool check)
 {
     launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
-                c->pulls.empty() ? 0 : 1, energy, 0, base, off, s);
+                c->pulls.empty() ? 0 : 1, energy, 0, base, off, check ? skin_check_thr2(c) : 0.0f, s,
+                c->force_mode);
     if (energy)
         launch_reduce_energy(c->b, c->n_traj, s);
 }
@@ -454,9 +505,10 @@ sop_status capture_graph(sop_ctx *c, int par, int energy)
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
     for (int q = 0; q < c->graph_steps; ++q) {
-        rebuild(c, c->cap_stream, true);
+        rebuild(c, c->cap_stream, true, true);
         for (int k = 0; k < c->p.list_every; ++k) {
-            one_step(c, c->cap_stream, c->b.step_base, k, energy && q == 0 && k == 0);
+            one_step(c, c->cap_stream, c->b.step_base, k, energy && q == 0 && k == 0,
+                     k == c->p.list_every - 1);
             c->cur ^= 1;
         }
     }
@@ -517,8 +569,8 @@ sop_status sop_create(const sop_params *params, void *hip_stream, sop_ctx **out)
         return SOP_E_ARG;
     c->p = p;
     c->stream = (hipStream_t)hip_stream;
-    int cap = p.list_capacity ? p.list_capacity : 256;
-    c->cap = ((cap + 15) / 16) * 16;
+    c->cap_req = p.list_capacity;
+    c->cap = list_cap(c);
     *out = c;
     return SOP_OK;
 }
@@ -766,6 +818,7 @@ sop_status sop_set_tile(sop_ctx *c, int32_t tile)
         if (nt != c->tile) {
             c->tile = nt;
             c->list_valid = false;  // the list layout follows the tile size
+            c->skin_checked = -1;
             destroy_graphs(c);
         }
     }
@@ -791,6 +844,7 @@ sop_status sop_set_schedule(sop_ctx *c, int32_t schedule)
     if (c->bound)
         return fail(c, SOP_E_STATE, "set the schedule before binding the workspace");
     c->schedule = schedule;
+    c->cap = list_cap(c);
     return SOP_OK;
 }
 
@@ -830,6 +884,58 @@ sop_status sop_get_batch(const sop_ctx *c, int32_t *wg, int32_t *steps, int32_t 
         *steps = c->batch_steps;
     if (np)
         *np = c->bound ? n_packs(c) : 0;
+    return SOP_OK;
+}
+
+sop_status sop_set_force_mode(sop_ctx *c, int32_t mode)
+{
+    if (!c || (mode != SOP_FORCES_PARTICLE && mode != SOP_FORCES_PAIR))
+        return SOP_E_ARG;
+    if (mode != c->force_mode) {
+        c->force_mode = mode;
+        destroy_graphs(c);  // the graphs hold the kernels of the old mode
+    }
+    return SOP_OK;
+}
+
+sop_status sop_get_force_mode(const sop_ctx *c, int32_t *mode)
+{
+    if (!c || !mode)
+        return SOP_E_ARG;
+    *mode = c->force_mode;
+    return SOP_OK;
+}
+
+sop_status sop_set_list_skin(sop_ctx *c, double skin)
+{
+    if (!c || !(skin >= 0.0) || !std::isfinite(skin) || skin > 4.0 * c->p.r_list)
+        return SOP_E_ARG;
+    if (skin == c->skin)
+        return SOP_OK;
+    c->skin = skin;
+    c->list_valid = false;
+    c->skin_checked = -1;
+    destroy_graphs(c);  // the radius, the cell grid and the check are kernel arguments
+    if (c->coords)
+        set_grid(c, c->xyz_set.data());  // the cell edge follows the skin radius
+    if (c->bound && c->coords)
+        HIP_TRY(c, hipMemcpyAsync(c->b.traj_cell, c->traj_cell.data(), c->n_traj * sizeof(int4),
+                                  hipMemcpyHostToDevice, c->stream));
+    return SOP_OK;
+}
+
+sop_status sop_get_list_stats(sop_ctx *c, int64_t *rebuilds, int64_t *skin_builds)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    unsigned long long v[2] = {0, 0};
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(v, c->b.list_stats, sizeof(v), hipMemcpyDeviceToHost));
+    if (rebuilds)
+        *rebuilds = (int64_t)v[0];
+    if (skin_builds)
+        *skin_builds = (int64_t)v[1];
     return SOP_OK;
 }
 
@@ -929,6 +1035,12 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
                                       hipMemcpyHostToDevice, s));
         }
         HIP_TRY(c, hipMemsetAsync(b.list16, 0, n_pad * c->cap * sizeof(unsigned short), s));
+        HIP_TRY(c, hipMemsetAsync(b.flist16, 0, n_pad * c->cap * sizeof(unsigned short), s));
+        HIP_TRY(c, hipMemsetAsync(b.fcnt, 0, n * sizeof(int), s));
+        HIP_TRY(c, hipMemsetAsync(b.cell_count, 0, (size_t)c->n_cells_cap * sizeof(int), s));
+        HIP_TRY(c, hipMemsetAsync(b.facc, 0, n * sizeof(float4), s));
+        HIP_TRY(c, hipMemsetAsync(b.tile_ord, 0, n_tiles_max * 256, s));
+        HIP_TRY(c, hipMemsetAsync(b.eacc, 0, n * sizeof(double4), s));
         HIP_TRY(c, hipMemsetAsync(b.topo2, 0, topo2_elems * sizeof(uint2), s));
         HIP_TRY(c, hipMemsetAsync(b.stage_cnt, 0, n_tiles_max * sizeof(int), s));
     }
@@ -940,7 +1052,10 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
     HIP_TRY(c, hipMemsetAsync(b.energy, 0, (size_t)c->n_traj * SOP_NTERMS * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.f_ext, 0, (size_t)c->n_traj * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(b.err, 0, sizeof(unsigned), s));
+    HIP_TRY(c, hipMemsetAsync(b.skin_flag, 0, sizeof(unsigned), s));
+    HIP_TRY(c, hipMemsetAsync(b.list_stats, 0, 2 * sizeof(unsigned long long), s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    c->skin_checked = -1;
     c->bound = true;
     c->sticky = 0;
     c->energy_step = -1;
@@ -972,6 +1087,7 @@ sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
         pv[2 * i] = float4{h[0], h[1], h[2], tw};
         pv[2 * i + 1] = float4{l[0], l[1], l[2], lw};
     }
+    c->xyz_set.assign(xyz, xyz + 3 * n);
     set_grid(c, xyz);
     destroy_graphs(c);  // the grid is a kernel argument of captured rebuilds
     hipStream_t s = c->stream;
@@ -985,6 +1101,7 @@ sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
     c->sticky = 0;
     c->coords = true;
     c->list_valid = false;
+    c->skin_checked = -1;
     c->last_error.clear();
     return SOP_OK;
 }
@@ -1014,6 +1131,7 @@ sop_status sop_set_step(sop_ctx *c, int64_t step)
         return SOP_E_ARG;
     c->step = step;
     c->list_valid = false;
+    c->skin_checked = -1;
     return SOP_OK;
 }
 
@@ -1081,8 +1199,9 @@ sop_status sop_get_pairlist(sop_ctx *c, int64_t cap, int32_t *ij, int64_t *n_pai
         const size_t n_tiles = tl.size() - 1;
         std::vector<unsigned short> list((size_t)n * c->cap);
         std::vector<int> stage(n_tiles * (size_t)SM), stage_cnt(n_tiles);
-        HIP_TRY(c, hipMemcpy(list.data(), c->b.list16, list.size() * sizeof(unsigned short),
+        HIP_TRY(c, hipMemcpy(list.data(), c->b.flist16, list.size() * sizeof(unsigned short),
                              hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(cnt.data(), c->b.fcnt, n * sizeof(int), hipMemcpyDeviceToHost));
         HIP_TRY(c, hipMemcpy(stage.data(), c->b.stage, stage.size() * sizeof(int), hipMemcpyDeviceToHost));
         HIP_TRY(c, hipMemcpy(stage_cnt.data(), c->b.stage_cnt, n_tiles * sizeof(int), hipMemcpyDeviceToHost));
         size_t tile = 0;
@@ -1122,7 +1241,7 @@ sop_status sop_compute_forces(sop_ctx *c, double *f, double *energies, double *f
         if (stale)
             rebuild(c, c->stream, false);
         launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
-                    c->pulls.empty() ? 0 : 1, true, 1, nullptr, c->step, c->stream);
+                    c->pulls.empty() ? 0 : 1, true, 1, nullptr, c->step, 0.0f, c->stream, c->force_mode);
         launch_reduce_energy(c->b, c->n_traj, c->stream);
     }
     c->list_valid = true;
@@ -1212,11 +1331,14 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
                 launch_set_step(c->b.step_next, c->step, c->stream);
                 base_set = true;
             }
+            if (c->skin_checked != c->step || skin_check_thr2(c) <= 0.0f)
+                launch_force_skin(c->b, c->stream);  // the graph's first rebuild builds the skin
             HIP_TRY(c, hipGraphLaunch(c->graphs[c->cur][en], c->stream));
             if (en)
                 c->energy_step = c->step;
             c->list_valid = true;
             c->step += span;
+            c->skin_checked = c->step;
             if (span & 1)
                 c->cur ^= 1;
             q += span;
@@ -1227,11 +1349,14 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
             c->list_valid = true;
         }
         const bool en = E > 0 && c->step % E == 0;
-        one_step(c, c->stream, nullptr, c->step, en);
+        const bool chk = checks_skin(c, c->step);
+        one_step(c, c->stream, nullptr, c->step, en, chk);
         if (en)
             c->energy_step = c->step;
         c->cur ^= 1;
         ++c->step;
+        if (chk)
+            c->skin_checked = c->step;
         ++q;
         base_set = false;
     }
@@ -1296,8 +1421,7 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
     for (auto &e : ev)
         (void)hipEventDestroy(e);
     const long long K = n_steps;
-    ms_out[0] = ms_out[1] = 0.0;
-    ms_out[2] = 1.0;
+    ms_out[0] = ms_out[1] = ms_out[2] = 0.0;
     if (K == 0)
         return SOP_OK;
     const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
@@ -1316,7 +1440,10 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     sop_status out = SOP_OK;
-    for (int kind = 0; kind < 2 && out == SOP_OK; ++kind) {
+    // kind 0: step kernels; 1: rebuilds with the skin build; 2: rebuilds
+    // that only filter the skin rows (the skin stays valid in between)
+    const int kinds = c->schedule == SOP_SCHEDULE_PLAIN ? 3 : 2;
+    for (int kind = 0; kind < kinds && out == SOP_OK; ++kind) {
         const int saved = c->cur;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
@@ -1327,10 +1454,13 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
         for (long long q = 0; q < K; ++q) {
             if (kind == 0) {
                 launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
-                            c->pulls.empty() ? 0 : 1, false, 0, nullptr, c->step + q, c->cap_stream);
+                            c->pulls.empty() ? 0 : 1, false, 0, nullptr, c->step + q, 0.0f,
+                            c->cap_stream, c->force_mode);
                 c->cur ^= 1;
             } else {
-                rebuild(c, c->cap_stream, false);
+                if (kind == 1)
+                    launch_force_skin(c->b, c->cap_stream);
+                rebuild(c, c->cap_stream, false, true);
             }
         }
         e = hipStreamEndCapture(c->cap_stream, &g);
@@ -1365,9 +1495,11 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
         // back to the saved positions; the next list is built from them
         HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, s));
         if (kind == 0) {
+            c->skin_checked = -1;
             rebuild(c, s, false);
         }
     }
+    c->skin_checked = -1;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->list_valid = false;
@@ -1471,7 +1603,8 @@ std::string cache_key(const sop_ctx *c)
     return buf;
 }
 
-// Cache lines: <key> <a> <b>   (plain schedule: a = tile, b = 0; batched: a = wg, b = steps)
+// Cache lines: <key> <a> <b>   (plain schedule: a = tile, b = force mode; batched: a = wg,
+// b = steps)
 bool cache_lookup(const char *path, const std::string &key, int *a, int *b)
 {
     if (!path)
@@ -1510,6 +1643,7 @@ sop_status trial(sop_ctx *c, long long steps, double *rate)
     HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
     const long long step0 = c->step;
     c->list_valid = false;
+    c->skin_checked = -1;
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
@@ -1529,6 +1663,7 @@ sop_status trial(sop_ctx *c, long long steps, double *rate)
     HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
     c->step = step0;
     c->list_valid = false;
+    c->skin_checked = -1;
     return st;
 }
 
@@ -1548,7 +1683,8 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
     if (cache_lookup(cache_path, key, &a, &b)) {
         if (c->schedule == SOP_SCHEDULE_BATCHED)
             return sop_set_batch(c, a, b);
-        return sop_set_tile(c, a);
+        const sop_status s1 = sop_set_tile(c, a);
+        return s1 != SOP_OK ? s1 : sop_set_force_mode(c, b);
     }
     const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
     HIP_TRY(c, hipMemcpyAsync(c->b.pos_save, c->b.pos[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1560,8 +1696,9 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
                 for (int k : {20, 50, 100, 200})
                     cand.push_back({wg, k});
     } else {
-        for (int tl : {64, 128, 256})
-            cand.push_back({tl, 0});
+        for (int mode : {SOP_FORCES_PARTICLE, SOP_FORCES_PAIR})
+            for (int tl : {64, 128, 256})
+                cand.push_back({tl, mode});
     }
     // steps per trial from the budget, using the current schedule's speed as a guide
     double rate0 = 0.0;
@@ -1576,10 +1713,13 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
     double best = -1.0;
     std::pair<int, int> pick = cand.front();
     for (const auto &cd : cand) {
-        if (c->schedule == SOP_SCHEDULE_BATCHED)
+        if (c->schedule == SOP_SCHEDULE_BATCHED) {
             st = sop_set_batch(c, cd.first, cd.second);
-        else
+        } else {
             st = sop_set_tile(c, cd.first);
+            if (st == SOP_OK)
+                st = sop_set_force_mode(c, cd.second);
+        }
         if (st != SOP_OK)
             return st;
         double rate = 0.0;
@@ -1591,8 +1731,13 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
             pick = cd;
         }
     }
-    st = c->schedule == SOP_SCHEDULE_BATCHED ? sop_set_batch(c, pick.first, pick.second)
-                                             : sop_set_tile(c, pick.first);
+    if (c->schedule == SOP_SCHEDULE_BATCHED) {
+        st = sop_set_batch(c, pick.first, pick.second);
+    } else {
+        st = sop_set_tile(c, pick.first);
+        if (st == SOP_OK)
+            st = sop_set_force_mode(c, pick.second);
+    }
     if (st != SOP_OK)
         return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -69,8 +69,18 @@ struct DevBufs {
     float4 *pos[2];
     int2 *trow;       // per residue: {first entry, n_bond | n_native << 12}
     float2 *tent;     // {partner id bits, r0}: bonds first, then natives
-    int *list_cnt;    // partners per residue
-    unsigned short *list16;  // rows by residue (cap entries): plain, slots of its tile; batched, local slots of its pack
+    int *list_cnt;    // partners per residue (plain: of the skin rows)
+    unsigned short *list16;  // rows by residue (cap entries): plain, skin rows (pairs within
+                             // r_list + skin at the last skin build) as slots of its tile;
+                             // batched, the list as local slots of its pack
+    int *fcnt;               // plain: list partners per residue (the skin rows filtered at r_list)
+    unsigned short *flist16; // plain: the list rows (cap entries), slots of the residue's tile
+    float4 *hi_skin;         // plain: high parts of the positions at the last skin build
+    unsigned *skin_flag;     // plain: nonzero when the next rebuild must rebuild the skin
+    unsigned long long *list_stats;  // plain: {rebuilds, skin builds} since binding
+    unsigned char *tile_ord; // plain: per tile (tile * T + rank), its residues by decreasing list length
+    float4 *facc;            // plain, pair-based forces: per-residue force accumulator
+    double4 *eacc;           // plain, pair-based forces: per-residue energy accumulator
     uint2 *topo2;            // plain: {slot, r0 bits} of bonded/native partners, (i/T)*TOPO_CAP*T + e*T + i%T
     int *stage;       // plain: per tile, global ids of its slots (stage_max per tile)
     int *stage_cnt;   // plain: slots per tile
@@ -113,12 +123,21 @@ struct StepConsts {
 
 // ---- kernel launchers (sop_kernels.hip) ----------------------------------
 // Plain schedule, tiles of `tile` residues (64, 128 or 256).
+// The skin build (cell binning and the per-tile rows within sqrt(rs2)) runs
+// only when the device skin flag is set; the filter to rc2 always runs.
 void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int tile, const GridDev &g,
-                    float rc2, int multi, hipStream_t s, bool advance_step_base, int list_every);
-// mode: 0 = step, 1 = forces only
+                    float rc2, float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every);
+// Sets the skin flag so that the next rebuild rebuilds the skin.
+void launch_force_skin(const DevBufs &b, hipStream_t s);
+// mode: 0 = step, 1 = forces only.  check_thr2 > 0: after the update, a
+// residue that moved more than sqrt(check_thr2) from its position at the
+// last skin build sets the skin flag.
+// force_mode 0: particle-based (each residue sums its own rows); 1:
+// pair-based (each pair once, atomic accumulation, then the update kernel).
 void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode,
-                 const long long *step_base, long long step_off, hipStream_t s);
+                 const long long *step_base, long long step_off, float check_thr2, hipStream_t s,
+                 int force_mode = 0);
 // Residues per chunk of the energy reduction (chunks never span trajectories).
 constexpr int ECHUNK = 1024;
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);

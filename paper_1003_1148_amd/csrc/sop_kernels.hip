@@ -6,56 +6,13 @@
 #include <algorithm>
 
 #include "sop_internal.hpp"
+#include "sop_rng.hpp"
 
 namespace sop {
 
 namespace {
 
 constexpr int WG = 256;       // threads per workgroup (4 wave64)
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the Gaussian mapping
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox10(uint4 c, unsigned k0, unsigned k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const unsigned hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        const unsigned hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
-// Uniform in (0,1) from the top 23 bits: exact in single precision.
-__device__ __forceinline__ float unit23(unsigned w)
-{
-    return (static_cast<float>(w >> 9) + 0.5f) * 0x1p-23f;
-}
-
-// Box-Muller: axis 0/1 = radius(u0) * (cos, sin)(2 pi u1), axis 2 =
-// radius(u2) * cos(2 pi u3). The logarithm, sine and cosine are the
-// hardware ones (the sine and cosine take the angle in turns, so they give
-// sin(2 pi u) directly): over all 2^23 uniforms the radius is within 5.7e-7
-// and the sine and cosine within 1.3e-7 of FP64, against 5.7e-7 and 5e-8 for
-// the library's FP32 functions, at a third of the instructions.
-__device__ __forceinline__ float gaussian_axis(const uint4 &w, int axis)
-{
-    const float ur = unit23(axis < 2 ? w.x : w.z);
-    const float ua = unit23(axis < 2 ? w.y : w.w);
-    const float rad = __fsqrt_rn(-2.0f * __logf(ur));
-    return rad * (axis == 1 ? __builtin_amdgcn_sinf(ua) : __builtin_amdgcn_cosf(ua));
-}
-
-// Axes 0 and 1 together (one radius, one angle); equal to gaussian_axis.
-__device__ __forceinline__ float2 gaussian_pair(const uint4 &w)
-{
-    const float rad = __fsqrt_rn(-2.0f * __logf(unit23(w.x)));
-    const float ua = unit23(w.y);
-    return make_float2(rad * __builtin_amdgcn_cosf(ua), rad * __builtin_amdgcn_sinf(ua));
-}
 
 __device__ __forceinline__ float comp(const float4 &v, int a)
 {
@@ -104,13 +61,6 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // Verlet-list rebuild: clear cell counts -> bin into fixed-capacity cells ->
 // one workgroup per cell fills the rows of its residues
 // ---------------------------------------------------------------------------
-__global__ void k_clear(int *__restrict__ a, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        a[i] = 0;
-}
-
 // Cell index of one residue in the wrapped grid (the trajectory's offset
 // keeps independent trajectories in separate cells).
 __device__ __forceinline__ int cell_index(const float4 &p, const int4 &off, const GridDev &g)
@@ -122,10 +72,13 @@ __device__ __forceinline__ int cell_index(const float4 &p, const int4 &off, cons
 }
 
 // Also advances the step counter of graph replays (once per rebuild) when
-// step_base is given.
+// step_base is given.  Bins only when the skin flag is set (the skin build),
+// and then records each residue's high part in hi_skin.
 __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const int4 *__restrict__ traj_cell,
                       int *__restrict__ count, float4 *__restrict__ cells, int *__restrict__ cell_of,
-                      unsigned *__restrict__ err, long long *step_base, long long *step_next, int period)
+                      unsigned *__restrict__ err, long long *step_base, long long *step_next, int period,
+                      const unsigned *__restrict__ skin_flag, float4 *__restrict__ hi_skin,
+                      unsigned long long *__restrict__ stats)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && step_base) {
@@ -133,9 +86,12 @@ __global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const in
         *step_base = nb;
         *step_next = nb + period;
     }
-    if (i >= n)
+    if (i >= n || *skin_flag == 0u)
         return;
+    if (i == 0)
+        ++stats[1];
     const float4 p = pos[2 * i];
+    hi_skin[i] = p;
     if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))
         atomicOr(err, ERR_NONFINITE);
     const int c = cell_index(p, traj_cell[__float_as_int(pos[2 * i + 1].w)], g);
@@ -267,15 +223,6 @@ __device__ __forceinline__ void add_native(Acc &A, const float4 &hi, const float
                                            const float4 &lj, float r0, const PairConsts &k, bool rec)
 {
     add_native_d(A, pair_delta(hi, lo, hj, lj), r0, k, rec);
-}
-
-// The repulsive term from the FP32 coordinates alone (the list pairs of the
-// batched schedule): the dropped low parts are below 2^-24 of the coordinate,
-// far inside the force tolerance for pairs beyond the excluded bonded range.
-__device__ __forceinline__ void add_repulsive_hi(Acc &A, const float4 &hi, const float4 &hj,
-                                                 const PairConsts &k, bool rec)
-{
-    add_repulsive_d(A, make_float3(hi.x - hj.x, hi.y - hj.y, hi.z - hj.z), k, rec);
 }
 
 // Cantilever `pull` (index or -1) and tip on one residue at t_n = step*h.
@@ -421,6 +368,7 @@ struct BuildArgs {
     int *stage;
     int *stage_cnt;
     unsigned *err;
+    const unsigned *skin_flag;
     GridDev g;
     float rc2;
     int n, cap;
@@ -514,6 +462,8 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
     __shared__ int part[NT];
     __shared__ int n_cu, n_extra, bad_cells, n_used_w;
 
+    if (*a.skin_flag == 0u)
+        return;  // the skin rows are still valid (uniform over the grid)
     const int tile = blockIdx.x, t = threadIdx.x;
     const int rho = t % TILE, q = t / TILE;
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
@@ -951,6 +901,224 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
         atomicOr(a.err, ERR_OVERFLOW);
 }
 
+// ---------------------------------------------------------------------------
+// List from the skin rows: every list_every steps each residue's skin row
+// (its partners within r_list + skin at the last skin build, in slot order)
+// is filtered with the single-precision predicate r < r_list of Algorithm 3
+// on the current positions.  The skin build runs again before the filter
+// whenever some residue has moved more than skin/2 since the last one, so
+// every pair within r_list is in the skin rows and the filtered rows equal a
+// rebuild from all pairs, entry for entry in the same order.
+// ---------------------------------------------------------------------------
+struct FilterArgs {
+    const int *tile_first;
+    const float4 *pos;
+    const int *stage;
+    const int *stage_cnt;
+    const unsigned short *skin16;
+    const int *skin_cnt;
+    unsigned short *list16;
+    int *list_cnt;
+    int *cell_count;
+    unsigned *skin_flag;
+    unsigned long long *stats;
+    unsigned char *tile_ord;  // per tile: its residues by decreasing list length
+    float rc2;
+    int cap, n_cells;
+};
+
+template <int TILE>
+__global__ __launch_bounds__(256) void k_filter(FilterArgs a)
+{
+    constexpr int NL = 256 / TILE;  // lanes per residue, adjacent in the wave
+    constexpr int SM = stage_max<TILE>();
+    __shared__ float4 hs[SM];
+    __shared__ int lens[TILE];
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const int rho = t / NL, q = t % NL;
+    // the cell counts are read only by the skin build, which is done: clear
+    // them for the next one; the flag is read only by the skin build too
+    for (int k = tile * 256 + t; k < a.n_cells; k += gridDim.x * 256)
+        a.cell_count[k] = 0;
+    if (tile == 0 && t == 0) {
+        *a.skin_flag = 0u;
+        ++a.stats[0];
+    }
+    const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
+    const int S = a.stage_cnt[tile];
+    const int *st = a.stage + (size_t)tile * SM;
+    for (int sl = t; sl < S; sl += 256)
+        hs[sl] = a.pos[2 * st[sl]];
+    __syncthreads();
+    const bool act = rho < tcnt;
+    const int i = first + (act ? rho : 0);
+    const float4 pi = a.pos[2 * i];
+    const int len = act ? min(a.skin_cnt[i], a.cap) : 0;
+    // the row in 16-byte pieces of 8 entries, piece m NL + q to lane q, so
+    // a residue's lanes read 16 NL contiguous bytes per round
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.skin16 + (size_t)i * a.cap);
+    unsigned short *dst = a.list16 + (size_t)i * a.cap;
+    const int npc = (len + 7) >> 3;
+    int rounds = (npc + NL - 1) / NL;
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1)
+        rounds = max(rounds, __shfl_xor(rounds, off, NL));  // uniform over the residue's lanes
+    int base = 0;
+    for (int m = 0; m < rounds; ++m) {
+        const int pc = m * NL + q;
+        unsigned e[8];
+        unsigned bits = 0u;
+        if (pc < npc) {
+            const uint4 w = src[pc];
+            const unsigned ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                e[u] = (ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
+                if (pc * 8 + u < len && within_cutoff(pi, hs[e[u]], a.rc2))
+                    bits |= 1u << u;
+            }
+        }
+        const int c = __popc(bits);
+        // passing entries before this lane's piece: scan over the residue's lanes
+        int v = c;
+#pragma unroll
+        for (int off = 1; off < NL; off <<= 1) {
+            const int y = __shfl_up(v, off, NL);
+            if (q >= off)
+                v += y;
+        }
+        int o = base + v - c;
+        while (bits) {
+            const int u = __ffs(bits) - 1;
+            bits &= bits - 1u;
+            dst[o++] = (unsigned short)e[u];
+        }
+        base += __shfl(v, NL - 1, NL);
+    }
+    if (act && q == NL - 1) {
+        // pad the row's last chunk of 4 with the empty slot SM
+        for (int k = base; k < ((base + 3) & ~3); ++k)
+            dst[k] = (unsigned short)SM;
+        a.list_cnt[i] = base;
+        lens[rho] = base;
+    }
+    __syncthreads();
+    // the step kernel hands the rows to its waves longest first, so that the
+    // rows a wave sums have about the same length (ties in index order)
+    if (act && q == 0) {
+        int r = 0;
+        for (int u = 0; u < tcnt; ++u)
+            r += (lens[u] > base || (lens[u] == base && u < rho)) ? 1 : 0;
+        a.tile_ord[(size_t)tile * TILE + r] = (unsigned char)rho;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Canonical order after a skin search: a tile's slots are renumbered in the
+// order of their residues' global ids, and every skin row is rewritten in
+// ascending slot order, so each row lists its partners by ascending residue
+// id whatever the cell grid.  The list rows the filter derives keep that
+// order, so the order in which a residue's pair terms are summed depends on
+// its list alone, not on when or with which skin the last search ran.
+// ---------------------------------------------------------------------------
+struct CanonArgs {
+    const int *tile_first;
+    const int2 *trow;
+    int *stage;
+    const int *stage_cnt;
+    unsigned short *skin16;
+    const int *skin_cnt;
+    uint2 *topo2;
+    const unsigned *skin_flag;
+    int cap;
+};
+
+template <int TILE>
+__global__ __launch_bounds__(256) void k_canon(CanonArgs a)
+{
+    constexpr int SM = stage_max<TILE>();
+    constexpr int G = 64;           // residues per pass
+    constexpr int NLG = 256 / G;    // lanes per residue in a pass
+    constexpr int MW = SM / 32;     // mask words per residue
+    __shared__ int sid[SM];
+    __shared__ unsigned short nslot[SM];
+    __shared__ unsigned mask[G * MW];
+    if (*a.skin_flag == 0u)
+        return;  // no search ran (uniform over the grid)
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
+    const int S = min(a.stage_cnt[tile], SM);
+    int *st = a.stage + (size_t)tile * SM;
+    for (int k = t; k < S; k += 256)
+        sid[k] = st[k];
+    __syncthreads();
+    // new slot = rank of the residue id among the tile's slots (ids distinct)
+    for (int k = t; k < S; k += 256) {
+        const int id = sid[k];
+        int r = 0;
+        for (int m = 0; m < S; ++m)
+            r += sid[m] < id ? 1 : 0;
+        nslot[k] = (unsigned short)r;
+    }
+    __syncthreads();
+    for (int k = t; k < S; k += 256)
+        st[nslot[k]] = sid[k];
+    for (int g0 = 0; g0 < tcnt; g0 += G) {
+        const int rho = g0 + t / NLG, q = t % NLG;
+        const bool act = rho < tcnt && t / NLG < G;
+        for (int w = t; w < G * MW; w += 256)
+            mask[w] = 0u;
+        __syncthreads();
+        int len = 0;
+        unsigned short *row = nullptr;
+        if (act) {
+            const int i = first + rho;
+            len = min(a.skin_cnt[i], a.cap);
+            row = a.skin16 + (size_t)i * a.cap;
+            for (int k = q; k < len; k += NLG) {
+                const int ns = nslot[row[k]];
+                atomicOr(&mask[(t / NLG) * MW + (ns >> 5)], 1u << (ns & 31));
+            }
+            // bonded and native entries: renumber in place
+            const int2 rw = a.trow[i];
+            const int ntop = (rw.y & 4095) + (rw.y >> 12);
+            uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
+            for (int e = q; e < ntop; e += NLG) {
+                const unsigned v = tp[(size_t)e * TILE].x;
+                if (v < (unsigned)S)
+                    tp[(size_t)e * TILE].x = nslot[v];
+            }
+        }
+        __syncthreads();
+        // emit: lane q scans words [q MW/NLG, (q+1) MW/NLG) of its residue's mask
+        constexpr int WPL = MW / NLG;
+        int c = 0;
+        if (act)
+            for (int w = q * WPL; w < (q + 1) * WPL; ++w)
+                c += __popc(mask[(t / NLG) * MW + w]);
+        // entries before this lane's words: scan over the residue's lanes (adjacent)
+        int v = c;
+#pragma unroll
+        for (int off = 1; off < NLG; off <<= 1) {
+            const int y = __shfl_up(v, off, NLG);
+            if (q >= off)
+                v += y;
+        }
+        if (act) {
+            int o = v - c;
+            for (int w = q * WPL; w < (q + 1) * WPL; ++w) {
+                unsigned b = mask[(t / NLG) * MW + w];
+                while (b) {
+                    const int kb = __ffs(b) - 1;
+                    b &= b - 1u;
+                    row[o++] = (unsigned short)(32 * w + kb);
+                }
+            }
+        }
+        __syncthreads();  // the masks are reused by the next pass
+    }
+}
+
 struct TileArgs {
     const int *tile_first;  // first residue of each tile, then n
     const float4 *pin;
@@ -970,7 +1138,11 @@ struct TileArgs {
     float4 *fout;
     unsigned *err;
     const long long *step_base;
+    const float4 *hi_skin;
+    unsigned *skin_flag;
+    const unsigned char *tile_ord;
     long long step_off;
+    float check_thr2;
     int n, cap, has_pull, n_tiles;
     StepConsts c;
     TipDev tip;
@@ -1034,204 +1206,124 @@ __device__ __forceinline__ float3 unpack_low(const float4 &s)
     return make_float3(l[0], l[1], l[2]);
 }
 
-// Staged coordinates within this distance of the tile origin let list pairs
-// use the high part alone (separation error below 4e-6 A); wider tiles add
-// the low parts.
-constexpr float NARROW_TILE = 64.0f;
+// A tile whose residues all lie within this distance of its origin has its
+// list partners (within r_list = 20 A of one of them at the rebuild, a few
+// tenths of an Angstrom more after ten steps) within about 64 A of it, so
+// list pairs use the high parts alone (separation error about 8e-6 A at most); other
+// tiles add the low parts.  The test reads the tile's own residues only, so
+// the arithmetic does not depend on which other residues are staged.
+constexpr float NARROW_TILE = 40.0f;
 
-// One workgroup of 256 lanes per tile of TILE residues.
-//  - Bonded/native entries and the noise: NL = 256/TILE lanes per residue;
-//    lane t serves residue t % TILE as part q = t / TILE (entries e = q mod
-//    NL; parts 1 and 2 draw the Gaussian components).
-//  - List partners: the tile's rows, cut into chunks of 4 slots and laid end
-//    to end (residue by residue), are split into 256 equal contiguous ranges,
-//    one per lane, so that every lane evaluates the same number of pairs
-//    whatever the spread of row lengths.  A residue covered by one range gets
-//    its sum directly; otherwise the ranges' partial sums are added in lane
-//    order.
-// Lane 0 of each residue then adds everything in a fixed order, adds the
-// external terms and does the update.
+// The plain step: one workgroup of 256 lanes per tile of TILE consecutive
+// residues, NL = 256/TILE adjacent lanes per residue.
+//  1. The last TILE lanes draw their residue's Gaussians (Philox and
+//     Box-Muller, from the counter words that do not depend on the position)
+//     and evaluate its cantilever and tip terms while every lane stages the
+//     tile's slots: each slot's position relative to the tile origin (its
+//     middle residue) as the exactly rounded high part of a TwoSum split, and
+//     only when some staged position lies 64 A or more from the origin, the
+//     low part too (a 10-bit multiple of the high part's ulp per axis).
+//  2. Lane q of a residue sums the list chunks (4 slots each) q, q + NL, ...
+//     of its row, and its bonded and native entries q, q + NL, ... from the
+//     compensated positions in device memory; the NL partial sums are added
+//     by butterfly shuffles, which give every lane the same bits.
+//  3. After a barrier the last TILE lanes add the external terms and the
+//     noise and take the compensated step.
 template <int TILE, bool ENERGY, int MODE>
 __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_tile_step(TileArgs a)
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
-    constexpr int RPL = TILE / 64;  // residues per lane of wave 0 in the chunk scan
+    constexpr int EPI = 256 - TILE;  // first lane of the update lanes
     __shared__ float4 sl_s[SM + 1];  // {rh.xyz, packed rl}; slot SM: the far-away empty slot
-    __shared__ float4 own_s[TILE];   // own high parts
-    __shared__ int coff[TILE + 1];   // first chunk of each row in the tile's sequence
-    __shared__ float pf[2][3][256];  // partial list sums: first / last residue of a range
-    __shared__ float df[3][TILE];    // list sums of residues inside one range
-    __shared__ float red_f[NL > 1 ? (NL - 1) * 3 * TILE : 1];
-    __shared__ float red_g[(NL > 1 && MODE == 0) ? 3 * TILE : 1];
-    // with four parts, part 3 evaluates the external terms early (force steps)
-    constexpr bool EARLY_X = NL >= 4 && MODE == 0 && !ENERGY;
-    __shared__ float red_x[EARLY_X ? 3 * TILE : 1];
-    __shared__ double red_e[ENERGY ? (NL + 1) * 4 * TILE : 1];   // energies: parts, then list direct
-    __shared__ double pe[ENERGY ? 2 * 2 * 256 : 1];              // list energy partials (e_r, vir)
+    __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
+    __shared__ double e_s[ENERGY ? 4 : 1][ENERGY ? TILE : 1];
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
     const int per = gridDim.x >> 3;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (tile >= a.n_tiles)
         return;  // uniform over the workgroup
     const int t = threadIdx.x;
-    const int rho = t % TILE, q = t / TILE;
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
-    const int i = first + rho;
-    const bool act = rho < tcnt;
     const int S = a.stage_cnt[tile];
     const int *st = a.stage + (size_t)tile * SM;
     const int mid = first + tcnt / 2;
-    // loads that do not depend on the staging first
+    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
+    // this lane's residue in the list phase (the tile's rows longest first),
+    // and in the update phase
+    const int q = t % NL;
+    const bool act = t / NL < tcnt;
+    const int rho = act ? (int)a.tile_ord[(size_t)tile * TILE + t / NL] : 0;
+    const int i = first + rho;
+    const int ue = t - EPI;
+    const bool upd = ue >= 0 && ue < tcnt;
+    const int iu = first + ue;
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
-    constexpr int TPRE = 4;  // this part's first bonded/native entries e = q + k NL
-    const uint2 *tp = a.topo2 + (size_t)tile * TOPO_CAP * TILE + rho;
-    uint2 tv[TPRE];
+    int cnt = 0;
     if (act) {
         hi0 = a.pin[2 * i];
         lo0 = a.pin[2 * i + 1];
         row = a.trow[i];
-#pragma unroll
-        for (int k = 0; k < TPRE; ++k)  // inside the tile's entry block whether or not they exist
-            tv[k] = tp[(size_t)(q + k * NL) * TILE];
-    }
-    int rc[RPL];  // wave 0: chunks of residues RPL*t .. RPL*t + RPL - 1
-    if (t < 64) {
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-            const int rr = RPL * t + u;
-            rc[u] = rr < tcnt ? (min(a.list_cnt[first + rr], a.cap) + 3) >> 2 : 0;
-        }
+        cnt = min(a.list_cnt[i], a.cap);
     }
     const float4 O = a.pin[2 * mid];
-    bool far = false;
-    {
-        constexpr int PER = SM / 256;
-        int ids[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int sl = t + u * 256;
-            ids[u] = sl < S ? st[sl] : -1;
-        }
-        // parts 1 and 2 draw the residue's Gaussians while the gathers are in
-        // flight: part 1 the (x, y) Box-Muller pair, part 2 (or part 1 alone) z
-        if (NL > 1 && MODE == 0 && act && q >= 1 && q <= 2) {
-            const uint2 key = a.noise_key[i];
+    // ---- 1. noise and external terms (update lanes), staging (all lanes) ----
+    float4 hu = make_float4(0.f, 0.f, 0.f, 0.f), lu = hu;
+    float g[3] = {0.0f, 0.0f, 0.0f};
+    Acc X;
+    double e_x = 0.0, f_rep = 0.0;
+    if (upd) {
+        hu = a.pin[2 * iu];
+        lu = a.pin[2 * iu + 1];
+        if (MODE == 0) {
+            const uint2 key = a.noise_key[iu];
             if (!(key.x >> 31)) {
-                const long long step0 = (a.step_base ? *a.step_base : 0) + a.step_off;
-                const uint4 w = noise_words(key.x, key.y, step0, a.c);
-                if (q == 1) {
-                    const float2 gxy = gaussian_pair(w);
-                    red_g[rho] = gxy.x;
-                    red_g[TILE + rho] = gxy.y;
-                }
-                if (q == 2 || NL == 2)
-                    red_g[2 * TILE + rho] = gaussian_axis(w, 2);
+                const uint4 w = noise_words(key.x, key.y, step, a.c);
+                const float2 gxy = gaussian_pair(w);
+                g[0] = gxy.x;
+                g[1] = gxy.y;
+                g[2] = gaussian_axis(w, 2);
             }
         }
-        if (EARLY_X && act && q == 3) {
-            // the cantilever and tip terms from the residue's own position
-            const long long step0 = (a.step_base ? *a.step_base : 0) + a.step_off;
-            Acc X;
-            double e_x = 0.0, f_rep = 0.0;
-            add_external(X, e_x, f_rep, hi0, lo0, step0, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
-                         a.tip, false, a.err);
-            red_x[rho] = X.fx;
-            red_x[TILE + rho] = X.fy;
-            red_x[2 * TILE + rho] = X.fz;
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            if (ids[u] >= 0) {
-                float4 rh, rl;
-                tile_frame(a.pin[2 * ids[u]], a.pin[2 * ids[u] + 1], O, rh, rl);
-                far |= !(fmaxf(fabsf(rh.x), fmaxf(fabsf(rh.y), fabsf(rh.z))) < NARROW_TILE);
-                rh.w = __uint_as_float(pack_low(rh, rl));
-                sl_s[t + u * 256] = rh;
-            }
-        }
-        if (t == 0)
-            sl_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+        add_external(X, e_x, f_rep, hu, lu, step, a.c.h, a.has_pull ? a.pull_slot[iu] : -1, a.pulls,
+                     a.tip, ENERGY, a.err);
     }
+    for (int sl = t; sl < S; sl += 256) {
+        const int id = st[sl];
+        float4 rh, rl;
+        tile_frame(a.pin[2 * id], a.pin[2 * id + 1], O, rh, rl);
+        rh.w = 0.0f;
+        sl_s[sl] = rh;
+    }
+    bool far = false;
+    if (t == 0)
+        sl_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
     float4 rh0, rl0;
     tile_frame(hi0, lo0, O, rh0, rl0);
     if (act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE))
         far = true;
-    if (q == 0) {
-        rh0.w = __uint_as_float(pack_low(rh0, rl0));
-        own_s[rho] = rh0;
-    }
-    if (t < 64) {
-        // chunk offsets of the rows: inclusive scan over wave 0
-        int sum = 0;
-#pragma unroll
-        for (int u = 0; u < RPL; ++u)
-            sum += rc[u];
-        int v = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int y = __shfl_up(v, off, 64);
-            if (t >= off)
-                v += y;
-        }
-        int c = v - sum;
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-            coff[RPL * t + u] = c;
-            c += rc[u];
-        }
-        if (t == 63)
-            coff[TILE] = v;
-    }
-    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
+    if (wide) {
+        // rare: the low parts of the staged positions, packed beside them
+        for (int sl = t; sl < S; sl += 256) {
+            const int id = st[sl];
+            float4 rh, rl;
+            tile_frame(a.pin[2 * id], a.pin[2 * id + 1], O, rh, rl);
+            sl_s[sl].w = __uint_as_float(pack_low(rh, rl));
+        }
+        rh0.w = __uint_as_float(pack_low(rh0, rl0));
+        __syncthreads();
+    }
     const PairConsts k = pair_consts(a.c);
-    // ---- list partners: this lane's range of chunks ----
-    // lane ranges [c0(t), c0(t+1)), c0(t) = t C / 256 (C <= 64 cap: 32-bit products)
-    const int C = coff[TILE];
-    auto cstart = [&](int tt) { return (tt * C) >> 8; };
-    const int c0 = cstart(t), c1 = cstart(t + 1);
-    {
-        auto row_of = [&](int c) {  // the residue whose chunks contain c (last r with coff[r] <= c)
-            int lo = 0, hi = TILE;
-            while (hi - lo > 1) {
-                const int m = (lo + hi) >> 1;
-                if (coff[m] <= c)
-                    lo = m;
-                else
-                    hi = m;
-            }
-            return lo;
-        };
-        const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16) + (size_t)first * (a.cap >> 2);
-        const int capc = a.cap >> 2;
-        int r = c0 < c1 ? row_of(c0) : 0;
-        const int r_first = r;
-        int rend = coff[r + 1];
-        Acc L;
-        float4 ph0 = own_s[r];
-        float3 pl0 = unpack_low(ph0);
-        auto flush = [&]() {
-            if (coff[r] >= c0 && rend <= c1) {  // the whole row is in this range
-                df[0][r] = k.c6 * L.fx;
-                df[1][r] = k.c6 * L.fy;
-                df[2][r] = k.c6 * L.fz;
-                if (ENERGY) {
-                    red_e[(NL * 4 + 0) * TILE + r] = L.e_r;
-                    red_e[(NL * 4 + 1) * TILE + r] = L.vir;
-                }
-            } else {
-                const int s2 = r == r_first ? 0 : 1;
-                pf[s2][0][t] = k.c6 * L.fx;
-                pf[s2][1][t] = k.c6 * L.fy;
-                pf[s2][2][t] = k.c6 * L.fz;
-                if (ENERGY) {
-                    pe[(s2 * 2 + 0) * 256 + t] = L.e_r;
-                    pe[(s2 * 2 + 1) * 256 + t] = L.vir;
-                }
-            }
-            L = Acc();
-        };
+    // ---- 2. list chunks and bonded/native entries of this lane ----
+    Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
+    Acc A;   // bonded and native terms
+    bool broken = false;
+    if (act) {
+        const float3 pl0 = unpack_low(rh0);
+        const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16 + (size_t)i * a.cap);
+        const int nch = (cnt + 3) >> 2;
         auto pairs4 = [&](const uint2 &w) {
             float4 pj[4];
 #pragma unroll
@@ -1240,198 +1332,267 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             if (!wide) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive_u(L, make_float3(ph0.x - pj[u].x, ph0.y - pj[u].y, ph0.z - pj[u].z), k, ENERGY);
+                    add_repulsive_u(L, make_float3(rh0.x - pj[u].x, rh0.y - pj[u].y, rh0.z - pj[u].z), k,
+                                    ENERGY);
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float3 lj = unpack_low(pj[u]);
                     add_repulsive_u(L,
-                                    make_float3((ph0.x - pj[u].x) + (pl0.x - lj.x), (ph0.y - pj[u].y) + (pl0.y - lj.y),
-                                                (ph0.z - pj[u].z) + (pl0.z - lj.z)),
+                                    make_float3((rh0.x - pj[u].x) + (pl0.x - lj.x), (rh0.y - pj[u].y) + (pl0.y - lj.y),
+                                                (rh0.z - pj[u].z) + (pl0.z - lj.z)),
                                     k, ENERGY);
                 }
             }
         };
-        // batches of up to 4 chunks: addresses and loads first, then the pairs
-        constexpr int KB = 4;
-        for (int cb = c0; cb < c1; cb += KB) {
-            uint2 w[KB];
-            int rr[KB];
-            int r2 = r, e2 = rend;
-#pragma unroll
-            for (int u = 0; u < KB; ++u) {
-                const int c = min(cb + u, c1 - 1);
-                while (c >= e2) {  // next non-empty row
-                    ++r2;
-                    e2 = coff[r2 + 1];
-                }
-                rr[u] = r2;
-                w[u] = lp[(size_t)r2 * capc + (c - coff[r2])];
-            }
-#pragma unroll
-            for (int u = 0; u < KB; ++u) {
-                if (cb + u < c1) {
-                    if (rr[u] != r) {
-                        flush();
-                        r = rr[u];
-                        rend = coff[r + 1];
-                        ph0 = own_s[r];
-                        pl0 = unpack_low(ph0);
-                    }
-                    pairs4(w[u]);
-                }
-            }
+        // two chunks in flight per iteration
+        int c = q;
+        for (; c + NL < nch; c += 2 * NL) {
+            const uint2 w0 = lp[c], w1 = lp[c + NL];
+            pairs4(w0);
+            pairs4(w1);
         }
-        if (c0 < c1)
-            flush();
-    }
-    Acc A;
-    bool broken = false;
-    if (act) {
-        // bonded and native partners, entries e = q mod NL
+        if (c < nch)
+            pairs4(lp[c]);
         const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
-        auto entry = [&](int e, const uint2 &v) {
-            const float4 sj = sl_s[v.x];
-            const float3 lj = unpack_low(sj);
-            const float3 d = make_float3((rh0.x - sj.x) + (rl0.x - lj.x), (rh0.y - sj.y) + (rl0.y - lj.y),
-                                         (rh0.z - sj.z) + (rl0.z - lj.z));
+        for (int e = q; e < ntop; e += NL) {
+            const float2 te = a.tent[row.x + e];
+            const int j = __float_as_int(te.x);
+            const float3 d = pair_delta(hi0, lo0, a.pin[2 * j], a.pin[2 * j + 1]);
             if (e < nb)
-                add_fene_d(A, d, __uint_as_float(v.y), k, ENERGY, broken);
+                add_fene_d(A, d, te.y, k, ENERGY, broken);
             else
-                add_native_d(A, d, __uint_as_float(v.y), k, ENERGY);
-        };
-#pragma unroll
-        for (int kk = 0; kk < TPRE; ++kk)
-            if (q + kk * NL < ntop)
-                entry(q + kk * NL, tv[kk]);
-        for (int e = q + TPRE * NL; e < ntop; e += NL)
-            entry(e, tp[(size_t)e * TILE]);
+                add_native_d(A, d, te.y, k, ENERGY);
+        }
         if (broken)
             atomicOr(a.err, ERR_FENE);
     }
-    // parts 1..NL-1 hand their sums and the Gaussian components to part 0
-    if (NL > 1 && q > 0) {
-        float *rf = red_f + (q - 1) * 3 * TILE;
-        rf[rho] = A.fx;
-        rf[TILE + rho] = A.fy;
-        rf[2 * TILE + rho] = A.fz;
+    // the residue's total over its NL lanes (butterfly: every lane gets the same bits)
+    float fx = k.c6 * L.fx + A.fx, fy = k.c6 * L.fy + A.fy, fz = k.c6 * L.fz + A.fz;
+    double eb = A.e_b, en = A.e_n, er = L.e_r, vir = A.vir + L.vir;
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1) {
+        fx += __shfl_xor(fx, off, NL);
+        fy += __shfl_xor(fy, off, NL);
+        fz += __shfl_xor(fz, off, NL);
+        if (ENERGY) {
+            eb += __shfl_xor(eb, off, NL);
+            en += __shfl_xor(en, off, NL);
+            er += __shfl_xor(er, off, NL);
+            vir += __shfl_xor(vir, off, NL);
+        }
     }
-    if (ENERGY) {
-        double *re = red_e + q * 4 * TILE;
-        re[rho] = A.e_b;
-        re[TILE + rho] = A.e_n;
-        re[2 * TILE + rho] = A.e_r;
-        re[3 * TILE + rho] = A.vir;
+    if (act && q == 0) {
+        f_s[0][rho] = fx;
+        f_s[1][rho] = fy;
+        f_s[2][rho] = fz;
+        if (ENERGY) {
+            e_s[0][rho] = eb;
+            e_s[1][rho] = en;
+            e_s[2][rho] = er;
+            e_s[3][rho] = vir;
+        }
     }
     __syncthreads();
-    if (q > 0 || !act)
+    if (!upd)
         return;
-    // list sums of this residue
-    float lx = 0.0f, ly = 0.0f, lz = 0.0f;
-    double ler = 0.0, lvir = 0.0;
-    {
-        const int b0 = coff[rho], b1 = coff[rho + 1];
-        if (b1 > b0) {
-            // the lanes whose ranges hold chunks b0 and b1 - 1: the last t with c0(t) <= c
-            const float invC = 1.0f / (float)C;
-            auto lane_of = [&](int c) {
-                int tt = min(255, (int)((float)(256 * c + 255) * invC));
-                while (tt < 255 && cstart(tt + 1) <= c)
-                    ++tt;
-                while (cstart(tt) > c)
-                    --tt;
-                return tt;
-            };
-            const int ta = lane_of(b0), tb = lane_of(b1 - 1);
-            const int ca = cstart(ta), cb = cstart(ta + 1);
-            if (b0 >= ca && b1 <= cb) {
-                lx = df[0][rho];
-                ly = df[1][rho];
-                lz = df[2][rho];
-                if (ENERGY) {
-                    ler = red_e[(NL * 4 + 0) * TILE + rho];
-                    lvir = red_e[(NL * 4 + 1) * TILE + rho];
-                }
-            } else {
-                const int s0 = b0 > ca ? 1 : 0;
-                lx = pf[s0][0][ta];
-                ly = pf[s0][1][ta];
-                lz = pf[s0][2][ta];
-                if (ENERGY) {
-                    ler = pe[(s0 * 2 + 0) * 256 + ta];
-                    lvir = pe[(s0 * 2 + 1) * 256 + ta];
-                }
-                for (int tt = ta + 1; tt <= tb; ++tt) {
-                    if (cstart(tt) == cstart(tt + 1))
-                        continue;  // an empty range (fewer chunks than lanes)
-                    lx += pf[0][0][tt];
-                    ly += pf[0][1][tt];
-                    lz += pf[0][2][tt];
-                    if (ENERGY) {
-                        ler += pe[0 * 256 + tt];
-                        lvir += pe[1 * 256 + tt];
-                    }
-                }
-            }
-        }
-    }
-    // fixed order: bonded/native parts 0..NL-1, then the list
-#pragma unroll
-    for (int p = 0; p < NL - 1; ++p) {
-        const float *rf = red_f + p * 3 * TILE;
-        A.fx += rf[rho];
-        A.fy += rf[TILE + rho];
-        A.fz += rf[2 * TILE + rho];
-    }
-    A.fx += lx;
-    A.fy += ly;
-    A.fz += lz;
+    // ---- 3. external terms, noise and the compensated update ----
+    Acc F;
+    F.fx = f_s[0][ue] + X.fx;
+    F.fy = f_s[1][ue] + X.fy;
+    F.fz = f_s[2][ue] + X.fz;
     if (ENERGY) {
-        double eb = 0.0, en = 0.0, er = 0.0, vir = 0.0;
-        for (int p = 0; p < NL; ++p) {
-            const double *re = red_e + p * 4 * TILE;
-            eb += re[rho];
-            en += re[TILE + rho];
-            er += re[2 * TILE + rho];
-            vir += re[3 * TILE + rho];
-        }
-        A.e_b = eb;
-        A.e_n = en;
-        A.e_r = er + ler;
-        A.vir = vir + lvir;
-    }
-    double e_x = 0.0, f_rep = 0.0;
-    if (EARLY_X) {
-        A.fx += red_x[rho];
-        A.fy += red_x[TILE + rho];
-        A.fz += red_x[2 * TILE + rho];
-    } else {
-        add_external(A, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
-                     a.tip, ENERGY, a.err);
-    }
-    if (ENERGY) {
-        double *er = a.res_energy + (size_t)i * RES_E;
+        double *er_out = a.res_energy + (size_t)iu * RES_E;
         // each internal pair appears in both partners' rows
-        er[0] = 0.5 * A.e_b;
-        er[1] = 0.5 * A.e_n;
-        er[2] = 0.5 * A.e_r;
+        er_out[0] = 0.5 * e_s[0][ue];
+        er_out[1] = 0.5 * e_s[1][ue];
+        er_out[2] = 0.5 * e_s[2][ue];
+        er_out[3] = e_x;
+        er_out[4] = 0.5 * e_s[3][ue];
+        er_out[5] = f_rep;
+    }
+    if (MODE == 1) {
+        a.fout[iu] = make_float4(F.fx, F.fy, F.fz, 0.0f);
+        return;
+    }
+    float4 hi = hu, lo = lu;
+    update_with_noise(hi, lo, F, g, a.c, a.err);
+    a.pout[2 * iu] = hi;
+    a.pout[2 * iu + 1] = lo;
+    if (a.check_thr2 > 0.0f) {
+        // moved farther than skin/2 from the last skin build: the next
+        // rebuild rebuilds the skin
+        const float4 hs = a.hi_skin[iu];
+        const float dx = hi.x - hs.x, dy = hi.y - hs.y, dz = hi.z - hs.z;
+        if (!(dx * dx + dy * dy + dz * dz <= a.check_thr2))
+            atomicOr(a.skin_flag, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair-based forces (Algorithm 4 with the atomic additions its text proposes
+// for GPUs that have them, Algorithm 5's gathering folded into the update
+// kernel): each unordered pair of the list and of the bonded and native
+// entries is evaluated once, in the row of its lower residue, and +df / -df
+// are added to both residues' force accumulators with hardware float
+// atomics.  The order of those additions is not fixed, so forces and
+// trajectories are reproducible only to rounding.
+// ---------------------------------------------------------------------------
+struct PairArgs {
+    const int *tile_first;
+    const float4 *pin;
+    const int2 *trow;
+    const float2 *tent;
+    const unsigned short *list16;
+    const int *list_cnt;
+    const int *stage;
+    float4 *facc;   // per residue: accumulated force
+    double4 *eacc;  // per residue: accumulated {FENE, native, repulsive, virial} halves
+    unsigned *err;
+    int cap, n_tiles;
+    StepConsts c;
+};
+
+__device__ __forceinline__ void pair_scatter(float4 *facc, double4 *eacc, int i, int j, const Acc &d, bool rec)
+{
+    unsafeAtomicAdd(&facc[i].x, d.fx);
+    unsafeAtomicAdd(&facc[i].y, d.fy);
+    unsafeAtomicAdd(&facc[i].z, d.fz);
+    unsafeAtomicAdd(&facc[j].x, -d.fx);
+    unsafeAtomicAdd(&facc[j].y, -d.fy);
+    unsafeAtomicAdd(&facc[j].z, -d.fz);
+    if (rec) {
+        // each residue's record holds half of its pairs' energies
+        const double hb = 0.5 * d.e_b, hn = 0.5 * d.e_n, hr = 0.5 * d.e_r, hv = 0.5 * d.vir;
+        unsafeAtomicAdd(&eacc[i].x, hb);
+        unsafeAtomicAdd(&eacc[i].y, hn);
+        unsafeAtomicAdd(&eacc[i].z, hr);
+        unsafeAtomicAdd(&eacc[i].w, hv);
+        unsafeAtomicAdd(&eacc[j].x, hb);
+        unsafeAtomicAdd(&eacc[j].y, hn);
+        unsafeAtomicAdd(&eacc[j].z, hr);
+        unsafeAtomicAdd(&eacc[j].w, hv);
+    }
+}
+
+template <int TILE, bool ENERGY>
+__global__ __launch_bounds__(256) void k_pair_forces(PairArgs a)
+{
+    constexpr int NL = 256 / TILE;
+    constexpr int SM = stage_max<TILE>();
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const int rho = t / NL, q = t % NL;
+    const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
+    if (rho >= tcnt)
+        return;
+    const int i = first + rho;
+    const int *st = a.stage + (size_t)tile * SM;
+    const float4 hi = a.pin[2 * i], lo = a.pin[2 * i + 1];
+    const PairConsts k = pair_consts(a.c);
+    const int cnt = min(a.list_cnt[i], a.cap);
+    const unsigned short *row = a.list16 + (size_t)i * a.cap;
+    for (int e = q; e < cnt; e += NL) {
+        const int j = st[row[e]];
+        if (j <= i)
+            continue;  // the pair belongs to the lower residue's row
+        Acc d;
+        add_repulsive_d(d, pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]), k, ENERGY);
+        pair_scatter(a.facc, a.eacc, i, j, d, ENERGY);
+    }
+    const int2 rw = a.trow[i];
+    const int nb = rw.y & 4095, ntop = nb + (rw.y >> 12);
+    bool broken = false;
+    for (int e = q; e < ntop; e += NL) {
+        const float2 te = a.tent[rw.x + e];
+        const int j = __float_as_int(te.x);
+        if (j <= i)
+            continue;
+        Acc d;
+        const float3 dd = pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]);
+        if (e < nb)
+            add_fene_d(d, dd, te.y, k, ENERGY, broken);
+        else
+            add_native_d(d, dd, te.y, k, ENERGY);
+        pair_scatter(a.facc, a.eacc, i, j, d, ENERGY);
+    }
+    if (broken)
+        atomicOr(a.err, ERR_FENE);
+}
+
+struct PairUpdArgs {
+    const float4 *pin;
+    float4 *pout;
+    float4 *facc;
+    double4 *eacc;
+    const uint2 *noise_key;
+    const int *pull_slot;
+    const PullDev *pulls;
+    double *res_energy;
+    float4 *fout;
+    unsigned *err;
+    const long long *step_base;
+    const float4 *hi_skin;
+    unsigned *skin_flag;
+    long long step_off;
+    float check_thr2;
+    int n, has_pull;
+    StepConsts c;
+    TipDev tip;
+};
+
+// Algorithm 5's gathering and the update: the accumulated force (cleared
+// for the next step), the external terms, the noise and the compensated step.
+template <bool ENERGY, int MODE>
+__global__ __launch_bounds__(256) void k_pair_update(PairUpdArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n)
+        return;
+    const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
+    const float4 hi0 = a.pin[2 * i], lo0 = a.pin[2 * i + 1];
+    const float4 f = a.facc[i];
+    a.facc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    Acc F;
+    F.fx = f.x;
+    F.fy = f.y;
+    F.fz = f.z;
+    double e_x = 0.0, f_rep = 0.0;
+    add_external(F, e_x, f_rep, hi0, lo0, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls, a.tip,
+                 ENERGY, a.err);
+    if (ENERGY) {
+        const double4 e = a.eacc[i];
+        a.eacc[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+        double *er = a.res_energy + (size_t)i * RES_E;
+        er[0] = e.x;
+        er[1] = e.y;
+        er[2] = e.z;
         er[3] = e_x;
-        er[4] = 0.5 * A.vir;
+        er[4] = e.w;
         er[5] = f_rep;
     }
     if (MODE == 1) {
-        a.fout[i] = make_float4(A.fx, A.fy, A.fz, 0.0f);
+        a.fout[i] = make_float4(F.fx, F.fy, F.fz, 0.0f);
         return;
     }
-    float4 hi = hi0, lo = lo0;
-    if (NL > 1) {
-        const float g[3] = {red_g[rho], red_g[TILE + rho], red_g[2 * TILE + rho]};
-        update_with_noise(hi, lo, A, g, a.c, a.err);
-    } else {
-        langevin_update(hi, lo, A, step, a.stream_ids[__float_as_int(lo0.w)], a.c, a.err);
+    float g[3] = {0.0f, 0.0f, 0.0f};
+    const uint2 key = a.noise_key[i];
+    if (!(key.x >> 31)) {
+        const uint4 w = noise_words(key.x, key.y, step, a.c);
+        const float2 gxy = gaussian_pair(w);
+        g[0] = gxy.x;
+        g[1] = gxy.y;
+        g[2] = gaussian_axis(w, 2);
     }
+    float4 hi = hi0, lo = lo0;
+    update_with_noise(hi, lo, F, g, a.c, a.err);
     a.pout[2 * i] = hi;
     a.pout[2 * i + 1] = lo;
+    if (a.check_thr2 > 0.0f) {
+        const float4 hs = a.hi_skin[i];
+        const float dx = hi.x - hs.x, dy = hi.y - hs.y, dz = hi.z - hs.z;
+        if (!(dx * dx + dy * dy + dz * dz <= a.check_thr2))
+            atomicOr(a.skin_flag, 1u);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1714,21 +1875,23 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         {
             // ---- list partners (forces) of the row this lane was given ----
             const int r = my & 0xffff, nch = my >> 16;
-            const float4 ph = shh[r];
+            const float4 ph = shh[r], pl = shl[r];
             // rows are read two chunks (16 bytes) at a time, the next pair
             // requested before the current one is used
             const uint4 *rp = reinterpret_cast<const uint4 *>(a.list + (size_t)myg * a.cap);
             const int nc2 = (nch + 1) >> 1;
             Acc L;  // the row's sum, pair by pair in row order
             auto chunk = [&](unsigned wx, unsigned wy) {
-                float4 qh[4];
-                qh[0] = shh[wx & 0xffffu];
-                qh[1] = shh[wx >> 16];
-                qh[2] = shh[wy & 0xffffu];
-                qh[3] = shh[wy >> 16];
+                const unsigned idx[4] = {wx & 0xffffu, wx >> 16, wy & 0xffffu, wy >> 16};
+                float4 qh[4], ql[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    qh[u] = shh[idx[u]];
+                    ql[u] = shl[idx[u]];
+                }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive_u(L, make_float3(ph.x - qh[u].x, ph.y - qh[u].y, ph.z - qh[u].z), kc, false);
+                    add_repulsive_u(L, pair_delta(ph, pl, qh[u], ql[u]), kc, false);
             };
             uint4 w = rp[0];
             for (int c2 = 0; c2 < nc2; ++c2) {
@@ -1781,7 +1944,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 // record steps: the repulsive energy and virial over the own row
                 Acc E;
                 for (int k = 0; k < min(cnt, a.cap); ++k)
-                    add_repulsive_hi(E, hi, shh[lrow16[k]], kc, true);
+                    add_repulsive_d(E, pair_delta(hi, lo, shh[lrow16[k]], shl[lrow16[k]]), kc, true);
                 A.e_r = E.e_r;
                 A.vir += E.vir;
             }
@@ -1905,6 +2068,12 @@ __global__ void k_noise(const float4 *__restrict__ pos, int n, const unsigned *_
     g[i] = make_float4(gaussian_axis(w, 0), gaussian_axis(w, 1), gaussian_axis(w, 2), 0.0f);
 }
 
+__global__ void k_set_flag(unsigned *dst, unsigned v)
+{
+    if (threadIdx.x == 0)
+        *dst = v;
+}
+
 __global__ void k_set_step(long long *dst, long long v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
@@ -1912,6 +2081,44 @@ __global__ void k_set_step(long long *dst, long long v)
 }
 
 inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per); }
+
+template <int TILE>
+void canon_tile(const DevBufs &b, int cap, hipStream_t s)
+{
+    CanonArgs a{};
+    a.tile_first = b.tile_first[tile_index(TILE)];
+    a.trow = b.trow;
+    a.stage = b.stage;
+    a.stage_cnt = b.stage_cnt;
+    a.skin16 = b.list16;
+    a.skin_cnt = b.list_cnt;
+    a.topo2 = b.topo2;
+    a.skin_flag = b.skin_flag;
+    a.cap = cap;
+    hipLaunchKernelGGL((k_canon<TILE>), dim3(b.n_tiles[tile_index(TILE)]), dim3(256), 0, s, a);
+}
+
+template <int TILE>
+void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2, hipStream_t s)
+{
+    FilterArgs a{};
+    a.tile_first = b.tile_first[tile_index(TILE)];
+    a.pos = b.pos[cur];
+    a.stage = b.stage;
+    a.stage_cnt = b.stage_cnt;
+    a.skin16 = b.list16;
+    a.skin_cnt = b.list_cnt;
+    a.list16 = b.flist16;
+    a.list_cnt = b.fcnt;
+    a.cell_count = b.cell_count;
+    a.skin_flag = b.skin_flag;
+    a.stats = b.list_stats;
+    a.tile_ord = b.tile_ord;
+    a.rc2 = rc2;
+    a.cap = cap;
+    a.n_cells = g.n_cells;
+    hipLaunchKernelGGL((k_filter<TILE>), dim3(b.n_tiles[tile_index(TILE)]), dim3(256), 0, s, a);
+}
 
 template <int TILE>
 void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, float rc2, int multi,
@@ -1934,6 +2141,7 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
     a.stage = b.stage;
     a.stage_cnt = b.stage_cnt;
     a.err = b.err;
+    a.skin_flag = b.skin_flag;
     a.g = g;
     a.rc2 = rc2;
     a.n = n;
@@ -1966,33 +2174,126 @@ void tile_dispatch(int tile, const TileArgs &a, hipStream_t s)
 }  // namespace
 
 void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int tile, const GridDev &g, float rc2,
-                    int multi, hipStream_t s, bool advance_step_base, int list_every)
+                    float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every)
 {
-    hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells);
+    // the cell counts are zero here: cleared at binding and by every filter
     hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, WG)), dim3(WG), 0, s, b.pos[cur], n, g, b.traj_cell,
                        b.cell_count, b.cells, b.cell_of, b.err,
-                       advance_step_base ? b.step_base : nullptr, b.step_next, list_every);
+                       advance_step_base ? b.step_base : nullptr, b.step_next, list_every,
+                       b.skin_flag, b.hi_skin, b.list_stats);
     switch (tile) {
-    case 64: rebuild_tile<64>(b, cur, n, cap, g, rc2, multi, s); break;
-    case 128: rebuild_tile<128>(b, cur, n, cap, g, rc2, multi, s); break;
-    default: rebuild_tile<256>(b, cur, n, cap, g, rc2, multi, s); break;
+    case 64:
+        rebuild_tile<64>(b, cur, n, cap, g, rs2, multi, s);
+        canon_tile<64>(b, cap, s);
+        filter_tile<64>(b, cur, cap, g, rc2, s);
+        break;
+    case 128:
+        rebuild_tile<128>(b, cur, n, cap, g, rs2, multi, s);
+        canon_tile<128>(b, cap, s);
+        filter_tile<128>(b, cur, cap, g, rc2, s);
+        break;
+    default:
+        rebuild_tile<256>(b, cur, n, cap, g, rs2, multi, s);
+        canon_tile<256>(b, cap, s);
+        filter_tile<256>(b, cur, cap, g, rc2, s);
+        break;
+    }
+}
+
+void launch_force_skin(const DevBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, s, b.skin_flag, 1u);
+}
+
+template <int TILE>
+void pair_forces(const PairArgs &a, bool energy, hipStream_t s)
+{
+    if (energy)
+        hipLaunchKernelGGL((k_pair_forces<TILE, true>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pair_forces<TILE, false>), dim3(a.n_tiles), dim3(256), 0, s, a);
+}
+
+void launch_pair_step(const DevBufs &b, int cur, int n, int cap, int tile, const StepConsts &c,
+                      const TipDev &tip, int has_pull, bool energy, int mode, const long long *step_base,
+                      long long step_off, float check_thr2, hipStream_t s)
+{
+    PairArgs a{};
+    a.tile_first = b.tile_first[tile_index(tile)];
+    a.n_tiles = b.n_tiles[tile_index(tile)];
+    a.pin = b.pos[cur];
+    a.trow = b.trow;
+    a.tent = b.tent;
+    a.list16 = b.flist16;
+    a.list_cnt = b.fcnt;
+    a.stage = b.stage;
+    a.facc = b.facc;
+    a.eacc = b.eacc;
+    a.err = b.err;
+    a.cap = cap;
+    a.c = c;
+    switch (tile) {
+    case 64: pair_forces<64>(a, energy, s); break;
+    case 128: pair_forces<128>(a, energy, s); break;
+    default: pair_forces<256>(a, energy, s); break;
+    }
+    PairUpdArgs u{};
+    u.pin = b.pos[cur];
+    u.pout = b.pos[cur ^ 1];
+    u.facc = b.facc;
+    u.eacc = b.eacc;
+    u.noise_key = b.noise_key;
+    u.pull_slot = b.pull_slot;
+    u.pulls = b.pulls;
+    u.res_energy = b.res_energy;
+    u.fout = b.fout;
+    u.err = b.err;
+    u.step_base = step_base;
+    u.hi_skin = b.hi_skin;
+    u.skin_flag = b.skin_flag;
+    u.step_off = step_off;
+    u.check_thr2 = mode == 0 ? check_thr2 : 0.0f;
+    u.n = n;
+    u.has_pull = has_pull;
+    u.c = c;
+    u.tip = tip;
+    const dim3 g(blocks_for(n, WG));
+    if (mode == 1) {
+        if (energy)
+            hipLaunchKernelGGL((k_pair_update<true, 1>), g, dim3(WG), 0, s, u);
+        else
+            hipLaunchKernelGGL((k_pair_update<false, 1>), g, dim3(WG), 0, s, u);
+    } else {
+        if (energy)
+            hipLaunchKernelGGL((k_pair_update<true, 0>), g, dim3(WG), 0, s, u);
+        else
+            hipLaunchKernelGGL((k_pair_update<false, 0>), g, dim3(WG), 0, s, u);
     }
 }
 
 void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode, const long long *step_base,
-                 long long step_off, hipStream_t s)
+                 long long step_off, float check_thr2, hipStream_t s, int force_mode)
 {
+    if (force_mode == 1) {
+        launch_pair_step(b, cur, n, cap, tile, c, tip, has_pull, energy, mode, step_base, step_off,
+                         check_thr2, s);
+        return;
+    }
     TileArgs a{};
+    a.tile_ord = b.tile_ord;
+    a.hi_skin = b.hi_skin;
+    a.skin_flag = b.skin_flag;
+    a.check_thr2 = mode == 0 ? check_thr2 : 0.0f;
     a.tile_first = b.tile_first[tile_index(tile)];
     a.n_tiles = b.n_tiles[tile_index(tile)];
     a.pin = b.pos[cur];
     a.pout = b.pos[cur ^ 1];
     a.trow = b.trow;
     a.tent = b.tent;
-    a.list16 = b.list16;
+    a.list16 = b.flist16;
     a.topo2 = b.topo2;
-    a.list_cnt = b.list_cnt;
+    a.list_cnt = b.fcnt;
     a.stage = b.stage;
     a.stage_cnt = b.stage_cnt;
     a.stream_ids = b.stream_ids;

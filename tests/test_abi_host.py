@@ -77,7 +77,7 @@ def test_workspace_size_and_bind_checks(lib):
     s = make_config("c1")
     c = _ctx(s)
     n1 = c.workspace_size()
-    c2 = P.Context(RunParams(list_capacity=512))
+    c2 = P.Context(RunParams(list_capacity=1024))  # above the default 512 of the plain schedule
     c2.load_topology(s.res_offsets, s.bonds, s.bond_r0, s.natives, s.native_r0)
     n2 = c2.workspace_size()
     assert n2 > n1 > s.n_res * 64

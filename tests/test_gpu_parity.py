@@ -374,8 +374,8 @@ def test_step_timing_leaves_the_state(P):
     a = ctx_for(P, s)
     a.step(20)
     x0 = a.get_coordinates()
-    k_ms, rb_ms, one = a.step_timed(40)
-    assert k_ms > 0.0 and rb_ms > 0.0 and one == 1.0
+    k_ms, search_ms, filter_ms = a.step_timed(40)
+    assert k_ms > 0.0 and search_ms > filter_ms > 0.0
     assert a.get_step() == 20
     assert np.array_equal(a.get_coordinates(), x0)
     a.step(10)

@@ -15,7 +15,7 @@ import pytest
 
 from synth import RunParams, make_config
 
-from parity import force_errors
+from parity import force_errors, force_gate_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -67,12 +67,12 @@ def test_fibre_end_force_error_and_drift(P, orc):
         pairs = o.pairlist(xg)
         Fo, _, _, st = o.forces(xg, step=100 * k, pairs=pairs)
         assert st == 0
-        S, _ = o.force_scale(xg, step=100 * k, pairs=pairs)
+        S = force_gate_scale(o, xg, step=100 * k, pairs=pairs)
         ferr, ew, _, zero_ok = force_errors(F, Fo, S)
         assert zero_ok
         d = np.linalg.norm(xg - xo, axis=1)
         rows.append((100 * k, ferr, ew, float(np.sqrt((d * d).mean())), float(d.max())))
-    log("step  force_rel_err  max_res_err/S  rms_dx_A  max_dx_A")
+    log("step  force_rel_err  max_res_err/(S+0.05K)  rms_dx_A  max_dx_A")
     for r in rows:
         log(f"{r[0]:5d}  {r[1]:.3e}  {r[2]:.3e}  {r[3]:.3e}  {r[4]:.3e}")
     assert all(r[1] <= FORCE_TOL and r[2] <= FORCE_TOL for r in rows)

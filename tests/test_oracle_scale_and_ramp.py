@@ -138,6 +138,105 @@ def test_elementwise_check_passes_rounding(orc):
 
 
 # --------------------------------------------------------------------------
+# stiffness scale: r |d^2E/dr^2| per pair
+# --------------------------------------------------------------------------
+
+STIFF_ETA = 0.05  # the gate's allowance per pair: a distance error of 5e-7 r
+
+
+@pytest.mark.parametrize("r", [3.0, 3.8, 4.5, 6.3, 9.0, 15.0])
+def test_second_derivatives_match_finite_differences(orc, r):
+    p = RunParams()
+    h = 1e-5 * r
+    def fd(fn):
+        return (fn(r + h) - fn(r - h)) / (2 * h)
+    r0b = r + 0.3  # a bond stretched inside the FENE range
+    assert orc.fene_d2(r, r0b, p.k_fene, p.R0) == pytest.approx(
+        fd(lambda u: orc.fene(u, r0b, p.k_fene, p.R0)[1]), rel=1e-7)
+    for r0 in (5.0, 6.5):
+        assert orc.native_d2(r, r0, p.eps_h) == pytest.approx(
+            fd(lambda u: orc.native(u, r0, p.eps_h)[1]), rel=1e-6, abs=1e-12)
+    assert orc.repulsive_d2(r, p.sigma, p.eps_l) == pytest.approx(
+        fd(lambda u: orc.repulsive(u, p.sigma, p.eps_l)[1]), rel=1e-7)
+
+
+def test_second_derivatives_at_the_minima(orc):
+    """At r = r0 the FENE and native forces vanish and their curvatures are
+    k and 72 eps / r0^2; the repulsion's at r = sigma is 42 eps / sigma^2."""
+    p = RunParams()
+    assert orc.fene(3.8, 3.8, p.k_fene, p.R0)[1] == 0.0
+    assert orc.fene_d2(3.8, 3.8, p.k_fene, p.R0) == pytest.approx(p.k_fene, rel=1e-15)
+    assert orc.native(5.5, 5.5, 1.3)[1] == pytest.approx(0.0, abs=1e-15)
+    assert orc.native_d2(5.5, 5.5, 1.3) == pytest.approx(72 * 1.3 / 5.5 ** 2, rel=1e-14)
+    assert orc.repulsive_d2(3.8, 3.8, 0.7) == pytest.approx(42 * 0.7 / 3.8 ** 2, rel=1e-14)
+
+
+def test_stiffness_of_a_single_bond(orc):
+    s = tiny(np.array([[0.0, 0.0, 0.0], [4.1, 0.0, 0.0]]), bonds=[(0, 1)])
+    s.bond_r0[:] = 3.8
+    o = orc.OracleSystem(s, RunParams())
+    K = o.force_stiffness(s.x)
+    p = RunParams()
+    assert K[0] == K[1] == pytest.approx(4.1 * orc.fene_d2(4.1, 3.8, p.k_fene, p.R0), rel=1e-14)
+
+
+def test_stiffness_bounds_the_force_change_of_a_displacement(orc):
+    """Moving residue i by delta changes each of its pair distances by at
+    most |delta| and each pair direction by at most |delta|/r, so to first
+    order |dF_i| <= (|delta| / r_min) (K_i + S_i)."""
+    s = make_config("c0")
+    rng = np.random.default_rng(9)
+    x = s.x + 0.2 * rng.standard_normal(s.x.shape)
+    o = orc.OracleSystem(s, RunParams())
+    pairs = o.pairlist(x)
+    F, _, _, _ = o.forces(x, pairs=pairs)
+    K = o.force_stiffness(x, pairs=pairs)
+    S, _ = o.force_scale(x, pairs=pairs)
+    dlen = 1e-6
+    for i in (0, 17, 40, 55):
+        rmin = np.linalg.norm(x[i] - np.delete(x, i, axis=0), axis=1).min()
+        for ax in range(3):
+            y = x.copy()
+            y[i, ax] += dlen
+            Fy, _, _, _ = o.forces(y, pairs=pairs)
+            assert np.linalg.norm(Fy[i] - F[i]) <= 1.01 * (dlen / rmin) * (K[i] + S[i])
+
+
+def test_parallel_stiffness_equals_the_pair_loop(orc):
+    s = with_externals(make_config("c1"))
+    rng = np.random.default_rng(6)
+    x = s.x + 0.2 * rng.standard_normal(s.x.shape)
+    o = orc.OracleSystem(s, RunParams())
+    K = o.force_stiffness(x, step=3)
+    Kp = o.force_stiffness_par(x, step=3, threads=4)
+    assert np.allclose(Kp, K, rtol=1e-12, atol=0.0)
+
+
+def test_gate_with_stiffness_still_flags_a_dropped_pair(orc):
+    """The scale S_i + 0.05 K_i of the GPU parity tests: a dropped 10 A list
+    pair still fails it."""
+    from synth.structures import System as Sys
+    s = make_config("c2")
+    n = 80 * 250
+    keep_b = (s.bonds < n).all(1)
+    keep_n = (s.natives < n).all(1)
+    s = Sys("c2-first", s.x[:n].copy(), np.array([0, n], np.int64), s.stream_ids.copy(),
+            s.chain_id[:n].copy(), s.bonds[keep_b], s.bond_r0[keep_b], s.natives[keep_n],
+            s.native_r0[keep_n])
+    rng = np.random.default_rng(1)
+    x = s.x + 0.15 * rng.standard_normal(s.x.shape)
+    o = orc.OracleSystem(s, RunParams())
+    pairs = o.pairlist(x)
+    d = np.linalg.norm(x[pairs[:, 0]] - x[pairs[:, 1]], axis=1)
+    k = int(np.argmin(np.abs(d - 10.0)))
+    F, _, _, _ = o.forces(x, pairs=pairs)
+    Fd, _, _, _ = o.forces(x, pairs=np.delete(pairs, k, axis=0))
+    S, _ = o.force_scale(x, pairs=pairs)
+    K = o.force_stiffness(x, pairs=pairs)
+    assert elementwise(Fd, F, S + STIFF_ETA * K) > 1e-5
+
+
+# --------------------------------------------------------------------------
 # residue-parallel oracle
 # --------------------------------------------------------------------------
 
