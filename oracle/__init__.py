@@ -87,6 +87,8 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_force_scale.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
         L.orc_force_scale.restype = C.c_int
+        L.orc_run_underdamped.argtypes = [vp, vp, C.c_double, vp, vp, i64, i64]
+        L.orc_run_underdamped.restype = C.c_int
         L.orc_force_stiffness.argtypes = [vp, vp, vp, i64, vp, i64, vp]
         L.orc_force_stiffness.restype = C.c_int
         L.orc_force_stiffness_par.argtypes = [vp, vp, vp, i64, vp, C.c_int]
@@ -284,6 +286,14 @@ class OracleSystem:
                            int(energy_every), _ptr(E), _ptr(fe), nrec_max, C.byref(nrec),
                            int(threads or default_threads()))
         return x, E[:nrec.value], fe[:nrec.value], st
+
+    def run_underdamped(self, x, v, n_steps, mass, step0=0):
+        """BAOAB underdamped Langevin steps; returns (x, v, status) at the end."""
+        x = np.array(x, dtype=np.float64, copy=True, order="C")
+        v = np.array(v, dtype=np.float64, copy=True, order="C")
+        st = lib().orc_run_underdamped(C.byref(self.s), C.byref(self.p), float(mass), _ptr(x), _ptr(v),
+                                       int(step0), int(n_steps))
+        return x, v, st
 
     def end_to_end(self, x):
         """|x_last - x_first| of every trajectory."""

@@ -697,6 +697,74 @@ int orc_run(const orc_system *s, const orc_params *p, double *x, int64_t step0, 
     return status;
 }
 
+/*
+ * Underdamped Langevin dynamics, m dv = F dt - zeta v dt + sqrt(2 zeta kB T) dW
+ * and dx = v dt, with the SOP forces of Eq. 1 and the list rules of orc_run
+ * (the paper's conclusion names this limit as an extension of its
+ * first-order integration kernel and gives no scheme).  Each step is the
+ * BAOAB splitting of Leimkuhler and Matthews (Appl. Math. Res. Express,
+ * 2013): with gamma = zeta/m, c1 = exp(-gamma h), c2 = sqrt((1 - c1^2) kB T/m)
+ * and the residue's Gaussians g of step n (orc_gauss3, the same counters as
+ * the overdamped noise),
+ *   B: v += (h/2m) F(x_n);   A: x += (h/2) v;   O: v = c1 v + c2 g;
+ *   A: x += (h/2) v;          B: v += (h/2m) F(x_{n+1}),
+ * F(x_{n+1}) being the force of step n+1 (its list rebuilt when
+ * (n+1) % list_every == 0).  Fixed residues neither move nor carry a
+ * velocity.  x and v (3*n_res each) are the positions and velocities at
+ * t_step0 on entry and at t_(step0+n_steps) on return.
+ */
+int orc_run_underdamped(const orc_system *s, const orc_params *p, double mass, double *x, double *v,
+                        int64_t step0, int64_t n_steps)
+{
+    int64_t n = s->n_res;
+    if (!(mass > 0.0))
+        return ORC_E_ARG;
+    double *F = (double *)malloc((size_t)n * 3 * sizeof(double));
+    int32_t *list = NULL;
+    int64_t n_list = 0;
+    int status = ORC_OK;
+    double h = p->h, kick = 0.5 * h / mass;
+    double c1 = exp(-p->zeta / mass * h);
+    double c2 = sqrt((1.0 - c1 * c1) * p->kBT / mass);
+    for (int64_t q = 0; q <= n_steps && status == ORC_OK; ++q) {
+        int64_t step = step0 + q;
+        if (q == 0 || step % p->list_every == 0) {
+            int64_t m = orc_pairlist(s, p, x, NULL, 0);
+            free(list);
+            list = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * 2 * sizeof(int32_t));
+            n_list = orc_pairlist(s, p, x, list, m);
+        }
+        status = orc_forces(s, p, x, step, list, n_list, F, NULL, NULL);
+        if (status != ORC_OK)
+            break;
+        for (int64_t t = 0; t < s->n_traj; ++t) {
+            for (int64_t i = s->res_offsets[t]; i < s->res_offsets[t + 1]; ++i) {
+                if (s->fixed && s->fixed[i]) {
+                    v[3 * i] = v[3 * i + 1] = v[3 * i + 2] = 0.0;
+                    continue;
+                }
+                if (q > 0)  /* the last B of the previous step */
+                    for (int a = 0; a < 3; ++a)
+                        v[3 * i + a] += kick * F[3 * i + a];
+                if (q == n_steps)
+                    continue;
+                double g[3];
+                orc_gauss3(p->seed, (uint32_t)(i - s->res_offsets[t]), s->stream_ids[t], step, g);
+                for (int a = 0; a < 3; ++a) {
+                    double w = v[3 * i + a] + kick * F[3 * i + a];  /* B */
+                    x[3 * i + a] += 0.5 * h * w;                    /* A */
+                    w = c1 * w + c2 * g[a];                         /* O */
+                    x[3 * i + a] += 0.5 * h * w;                    /* A */
+                    v[3 * i + a] = w;
+                }
+            }
+        }
+    }
+    free(F);
+    free(list);
+    return status;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Rounding scale of each residue's force and each energy term              */
 /* ------------------------------------------------------------------------ */
