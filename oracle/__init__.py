@@ -87,6 +87,8 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_force_scale.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
         L.orc_force_scale.restype = C.c_int
+        L.orc_run_tempered.argtypes = [vp, vp, vp, i64, i64, C.c_int32, vp, i64, vp, vp, vp]
+        L.orc_run_tempered.restype = C.c_int
         L.orc_run_underdamped.argtypes = [vp, vp, C.c_double, vp, vp, i64, i64]
         L.orc_run_underdamped.restype = C.c_int
         L.orc_force_stiffness.argtypes = [vp, vp, vp, i64, vp, i64, vp]
@@ -294,6 +296,19 @@ class OracleSystem:
         st = lib().orc_run_underdamped(C.byref(self.s), C.byref(self.p), float(mass), _ptr(x), _ptr(v),
                                        int(step0), int(n_steps))
         return x, v, st
+
+    def run_tempered(self, x, n_steps, kbt, exchange_every, tidx, step0=0):
+        """Replica exchange over groups of len(kbt) consecutive trajectories;
+        returns (x, tidx, accepted, attempted, status)."""
+        x = np.array(x, dtype=np.float64, copy=True, order="C")
+        kbt = np.ascontiguousarray(kbt, dtype=np.float64)
+        tidx = np.array(tidx, dtype=np.int32, copy=True, order="C")
+        acc = np.zeros(max(len(kbt) - 1, 1), dtype=np.int64)
+        att = np.zeros(max(len(kbt) - 1, 1), dtype=np.int64)
+        st = lib().orc_run_tempered(C.byref(self.s), C.byref(self.p), _ptr(x), int(step0), int(n_steps),
+                                    len(kbt), _ptr(kbt), int(exchange_every), _ptr(tidx), _ptr(acc),
+                                    _ptr(att))
+        return x, tidx, acc[:len(kbt) - 1], att[:len(kbt) - 1], st
 
     def end_to_end(self, x):
         """|x_last - x_first| of every trajectory."""

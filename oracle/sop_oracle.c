@@ -765,6 +765,99 @@ int orc_run_underdamped(const orc_system *s, const orc_params *p, double mass, d
     return status;
 }
 
+/*
+ * Replica exchange (parallel tempering) over an ensemble of independent
+ * trajectories, the use of the many-runs-per-GPU approach the paper's
+ * conclusion proposes.  The n_traj trajectories form groups of n_rep
+ * consecutive ones (n_traj a multiple of n_rep); each group's members carry
+ * the temperatures kbt[0 .. n_rep-1] as a permutation: tidx[t] is the
+ * temperature index of trajectory t.  Each step is orc_run's first-order
+ * step with the residue's noise amplitude sqrt(2 kbt[tidx[t]] h / zeta).
+ * At every step n with n % exchange_every == 0, before its update, round
+ * r = n / exchange_every attempts, in every group, the swaps of the
+ * trajectories at temperatures k and k+1 for k = r mod 2, r mod 2 + 2, ...:
+ * with E the potential energy of x(t_n) (FENE + native + repulsive +
+ * external) and d = (1/kbt[k] - 1/kbt[k+1]) (E_k - E_(k+1)), the swap is
+ * accepted when d >= 0 or u < exp(d) (Metropolis), u = orc_uniform of the
+ * first Philox4x32-10 word for counter (group, k, r low, r high) and key
+ * (seed low ^ 0x52455843, seed high) (a key of its own, so that these draws
+ * never repeat a noise draw).  Accepted swaps exchange the two temperature
+ * indices.  accepted[k] and attempted[k] (n_rep - 1 each, may be NULL) are
+ * incremented.
+ */
+int orc_run_tempered(const orc_system *s, const orc_params *p, double *x, int64_t step0,
+                     int64_t n_steps, int32_t n_rep, const double *kbt, int64_t exchange_every,
+                     int32_t *tidx, int64_t *accepted, int64_t *attempted)
+{
+    int64_t n = s->n_res;
+    if (n_rep < 1 || s->n_traj % n_rep != 0 || exchange_every < 0)
+        return ORC_E_ARG;
+    double *F = (double *)malloc((size_t)n * 3 * sizeof(double));
+    double *E = (double *)malloc((size_t)s->n_traj * ORC_NTERMS * sizeof(double));
+    int32_t *at = (int32_t *)malloc((size_t)s->n_traj * sizeof(int32_t));
+    int32_t *list = NULL;
+    int64_t n_list = 0;
+    int status = ORC_OK;
+    double drift = p->h / p->zeta;
+    int64_t n_groups = s->n_traj / n_rep;
+    for (int64_t q = 0; q < n_steps && status == ORC_OK; ++q) {
+        int64_t step = step0 + q;
+        if (q == 0 || step % p->list_every == 0) {
+            int64_t m = orc_pairlist(s, p, x, NULL, 0);
+            free(list);
+            list = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * 2 * sizeof(int32_t));
+            n_list = orc_pairlist(s, p, x, list, m);
+        }
+        status = orc_forces(s, p, x, step, list, n_list, F, E, NULL);
+        if (status != ORC_OK)
+            break;
+        if (exchange_every > 0 && step % exchange_every == 0 && n_rep > 1) {
+            int64_t r = step / exchange_every;
+            uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu) ^ 0x52455843u, (uint32_t)(p->seed >> 32)};
+            for (int64_t g = 0; g < n_groups; ++g) {
+                for (int32_t k = 0; k < n_rep; ++k)  /* the trajectory at each temperature */
+                    at[g * n_rep + tidx[g * n_rep + k]] = (int32_t)(g * n_rep + k);
+                for (int32_t k = (int32_t)(r % 2); k + 1 < n_rep; k += 2) {
+                    int32_t a = at[g * n_rep + k], b = at[g * n_rep + k + 1];
+                    double Ea = 0.0, Eb = 0.0;
+                    for (int term = 0; term < 4; ++term) {
+                        Ea += E[a * ORC_NTERMS + term];
+                        Eb += E[b * ORC_NTERMS + term];
+                    }
+                    double d = (1.0 / kbt[k] - 1.0 / kbt[k + 1]) * (Ea - Eb);
+                    uint32_t ctr[4] = {(uint32_t)g, (uint32_t)k, (uint32_t)r, (uint32_t)((uint64_t)r >> 32)};
+                    uint32_t w[4];
+                    orc_philox4x32_10(ctr, key, w);
+                    if (attempted)
+                        ++attempted[k];
+                    if (d >= 0.0 || orc_uniform(w[0]) < exp(d)) {
+                        tidx[a] = k + 1;
+                        tidx[b] = k;
+                        if (accepted)
+                            ++accepted[k];
+                    }
+                }
+            }
+        }
+        for (int64_t t = 0; t < s->n_traj; ++t) {
+            double noise = sqrt(2.0 * kbt[tidx[t]] * p->h / p->zeta);
+            for (int64_t i = s->res_offsets[t]; i < s->res_offsets[t + 1]; ++i) {
+                if (s->fixed && s->fixed[i])
+                    continue;
+                double g[3];
+                orc_gauss3(p->seed, (uint32_t)(i - s->res_offsets[t]), s->stream_ids[t], step, g);
+                for (int a = 0; a < 3; ++a)
+                    x[3 * i + a] += drift * F[3 * i + a] + noise * g[a];
+            }
+        }
+    }
+    free(F);
+    free(E);
+    free(at);
+    free(list);
+    return status;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Rounding scale of each residue's force and each energy term              */
 /* ------------------------------------------------------------------------ */
