@@ -243,6 +243,65 @@ sop_status sop_get_step(const sop_ctx *ctx, int64_t *step);
  */
 sop_status sop_step(sop_ctx *ctx, int64_t n_steps);
 
+/* Integrators of the plain schedule. */
+enum {
+    SOP_INTEGRATOR_OVERDAMPED = 0, /* the first-order scheme of Eq. 2 / Algorithm 7 (default) */
+    SOP_INTEGRATOR_UNDERDAMPED = 1 /* Langevin dynamics with inertia (see sop_set_integrator) */
+};
+
+/*
+ * Choose the plain schedule's integrator.  The paper's conclusion names the
+ * underdamped limit as an extension of its integration kernel without
+ * giving a scheme; SOP_INTEGRATOR_UNDERDAMPED integrates
+ * m dv = F dt - zeta v dt + sqrt(2 zeta kB T) dW, dx = v dt with every
+ * residue of mass `mass` (zeta, kB T and h from sop_params) by the BAOAB
+ * splitting of Leimkuhler and Matthews (2013): with c1 = exp(-zeta h/m) and
+ * c2 = sqrt((1 - c1^2) kB T/m), each step is v += (h/2m) F(x_n),
+ * x += (h/2) v, v = c1 v + c2 g, x += (h/2) v, v += (h/2m) F(x_(n+1)), with
+ * the same per-residue Gaussians g as the overdamped noise.  Positions stay
+ * compensated; velocities are single precision.  Fixed residues keep zero
+ * velocity.  sop_set_coordinates zeroes the velocities.  `mass` is ignored
+ * for the overdamped integrator.  SOP_E_ARG for an unknown kind or a
+ * non-positive mass; SOP_E_STATE on the batched schedule.
+ */
+sop_status sop_set_integrator(sop_ctx *ctx, int32_t kind, double mass);
+
+/* Velocities at the current step, double[3*n_res] (host), single precision
+ * on the device.  SOP_E_STATE on the batched schedule. */
+sop_status sop_set_velocities(sop_ctx *ctx, const double *v_host);
+/* Evaluates this step's forces when the stored velocities still lack their
+ * last half kick.  Synchronizes. */
+sop_status sop_get_velocities(sop_ctx *ctx, double *v_host);
+
+/*
+ * Replica exchange (parallel tempering) over the batched ensemble, the use of
+ * the many-runs-per-GPU approach the paper's conclusion proposes.  The
+ * trajectories form groups of n_rep consecutive ones (n_rep must divide the
+ * trajectory count), normally copies of one system; trajectory t runs at
+ * kB T = kbt[tidx[t]] (its noise amplitude sqrt(2 kbt h / zeta)), tidx being a
+ * permutation of 0 .. n_rep-1 within each group (NULL: t mod n_rep).  At
+ * every step n with n % exchange_every == 0 (0: never), before that step's
+ * update, round r = n / exchange_every attempts in every group the swaps of
+ * the trajectories at temperatures k and k+1 for k = r mod 2, r mod 2 + 2,
+ * ...: with E the potential energy (FENE + native + repulsive + external)
+ * at step n and d = (1/kbt[k] - 1/kbt[k+1]) (E_k - E_(k+1)), a swap is
+ * accepted when d >= 0 or u < exp(d), u being the first word of Philox4x32-10
+ * with counter (group, k, r low, r high) and key (seed low ^ 0x52455843, seed
+ * high) mapped to (0,1) as the noise's uniforms are; an accepted swap
+ * exchanges the two temperatures.  The energies of the exchange steps are
+ * recorded (sop_get_energies).  Host arrays are copied.  SOP_E_STATE unless
+ * the schedule is batched and a workspace is bound; SOP_E_ARG for a bad
+ * n_rep, a non-positive temperature, a negative interval or indices that are
+ * not a permutation in every group.
+ */
+sop_status sop_set_tempering(sop_ctx *ctx, int32_t n_rep, const double *kbt_host, int64_t exchange_every,
+                             const int32_t *tidx_host);
+
+/* Current temperature index of every trajectory (int32[n_traj], may be NULL)
+ * and, per ladder pair k (n_rep - 1 entries each, may be NULL), the swaps
+ * accepted and attempted since sop_set_tempering.  Synchronizes. */
+sop_status sop_get_tempering(sop_ctx *ctx, int32_t *tidx_host, int64_t *accepted, int64_t *attempted);
+
 /* Force evaluation of the plain schedule. */
 enum {
     SOP_FORCES_PARTICLE = 0, /* each residue sums its own rows (Algorithms 1-2): every pair is

@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "sop.h")
 NTERMS = 5
 SCHEDULE_PLAIN, SCHEDULE_BATCHED = 0, 1
 FORCES_PARTICLE, FORCES_PAIR = 0, 1
+INTEGRATOR_OVERDAMPED, INTEGRATOR_UNDERDAMPED = 0, 1
 TERM_NAMES = ("fene", "native", "repulsive", "external", "virial")
 STATUS = {0: "SOP_OK", -1: "SOP_E_ARG", -2: "SOP_E_STATE", -3: "SOP_E_WORKSPACE",
           -4: "SOP_E_HIP", -5: "SOP_E_FENE", -6: "SOP_E_LIST_OVERFLOW",
@@ -88,6 +89,11 @@ def lib():
             "sop_step_timed": [vp, i64, vp],
             "sop_set_list_skin": [vp, dbl],
             "sop_set_force_mode": [vp, i32],
+            "sop_set_integrator": [vp, i32, dbl],
+            "sop_set_tempering": [vp, i32, vp, i64, vp],
+            "sop_get_tempering": [vp, vp, vp, vp],
+            "sop_set_velocities": [vp, vp],
+            "sop_get_velocities": [vp, vp],
             "sop_get_force_mode": [vp, vp],
             "sop_get_list_stats": [vp, vp, vp],
             "sop_running_average": [vp, i64, i32, vp],
@@ -218,6 +224,36 @@ class Context:
         v = C.c_int32(0)
         self._check(lib().sop_get_force_mode(self.h, C.byref(v)))
         return "pair" if v.value == FORCES_PAIR else "particle"
+
+    def set_integrator(self, kind, mass=1.0):
+        """"overdamped" (default) or "underdamped" (BAOAB, residue mass `mass`)."""
+        k = {"overdamped": INTEGRATOR_OVERDAMPED, "underdamped": INTEGRATOR_UNDERDAMPED}.get(kind, kind)
+        self._check(lib().sop_set_integrator(self.h, int(k), float(mass)))
+
+    def set_velocities(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+        self._check(lib().sop_set_velocities(self.h, _p(v)))
+
+    def get_velocities(self):
+        v = np.zeros((self.n_res, 3))
+        self._check(lib().sop_get_velocities(self.h, _p(v)))
+        return v
+
+    def set_tempering(self, kbt, exchange_every, tidx=None):
+        """Replica exchange over groups of len(kbt) consecutive trajectories."""
+        kbt = np.ascontiguousarray(kbt, dtype=np.float64)
+        ti = None if tidx is None else np.ascontiguousarray(tidx, dtype=np.int32)
+        self._check(lib().sop_set_tempering(self.h, len(kbt), _p(kbt), int(exchange_every), _p(ti)))
+        self._n_rep = len(kbt)
+
+    def get_tempering(self):
+        """(temperature index per trajectory, accepted, attempted per ladder pair)."""
+        R = getattr(self, "_n_rep", 1)
+        ti = np.zeros(self.n_traj, dtype=np.int32)
+        acc = np.zeros(max(R - 1, 1), dtype=np.int64)
+        att = np.zeros(max(R - 1, 1), dtype=np.int64)
+        self._check(lib().sop_get_tempering(self.h, _p(ti), _p(acc), _p(att)))
+        return ti, acc[:R - 1], att[:R - 1]
 
     def set_list_skin(self, skin):
         self._check(lib().sop_set_list_skin(self.h, float(skin)))

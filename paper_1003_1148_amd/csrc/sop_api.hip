@@ -43,6 +43,13 @@ struct sop_ctx {
     // since the last such build; every rebuild filters them to r_list.
     double skin = 4.0;
     int force_mode = SOP_FORCES_PARTICLE;  // plain: particle- or pair-based force evaluation
+    int integrator = SOP_INTEGRATOR_OVERDAMPED;
+    double mass = 1.0;               // underdamped: mass of a residue
+    // batched: replica exchange over groups of re_rep consecutive trajectories
+    int re_rep = 0;
+    std::vector<double> re_kbt;
+    long long re_every = 0, re_last = -1;
+    bool ud_half = true;             // underdamped: the stored velocities are at the current step
     long long skin_checked = -1;     // step at which the skin was last known valid
     std::vector<double> xyz_set;     // the coordinates the grid was laid out for
     int graph_steps = 1;
@@ -173,7 +180,12 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.skin_flag = (unsigned *)take(sizeof(unsigned));
     d.list_stats = (unsigned long long *)take(2 * sizeof(unsigned long long));
     d.tile_ord = (unsigned char *)take(plain ? n_tiles_max * 256 : 0);
+    d.vel = (float4 *)take((plain ? n : 0) * sizeof(float4));
     d.facc = (float4 *)take((plain ? n : 0) * sizeof(float4));
+    d.re_kbt = (double *)take((plain ? 0 : T) * sizeof(double));
+    d.re_tidx = (int *)take((plain ? 0 : T) * sizeof(int));
+    d.re_tscale = (float *)take((plain ? 0 : T) * sizeof(float));
+    d.re_stats = (unsigned long long *)take((plain ? 0 : 2 * T) * sizeof(unsigned long long));
     d.eacc = (double4 *)take((plain ? n : 0) * sizeof(double4));
     d.topo2 = (uint2 *)take(topo2_elems * sizeof(uint2));
     d.stage = (int *)take(stage_elems * sizeof(int));
@@ -312,10 +324,22 @@ StepConsts step_consts(const sop_ctx *c)
     k.sigma2 = (float)(c->p.sigma * c->p.sigma);
     k.c_drift = (float)(c->p.h / c->p.zeta);
     k.c_noise = (float)std::sqrt(2.0 * c->p.kBT * c->p.h / c->p.zeta);
+    const double c1 = std::exp(-c->p.zeta / c->mass * c->p.h);
+    k.ud_c1 = (float)c1;
+    k.ud_c2 = (float)std::sqrt((1.0 - c1 * c1) * c->p.kBT / c->mass);
     k.key0 = (unsigned)(c->p.seed & 0xffffffffu);
     k.key1 = (unsigned)(c->p.seed >> 32);
     k.h = c->p.h;
     return k;
+}
+
+// Underdamped integrator: the kick of the next step (h/2m right after the
+// velocities were set, else h/m); 0 selects the overdamped update.
+float ud_kick(const sop_ctx *c)
+{
+    if (c->integrator != SOP_INTEGRATOR_UNDERDAMPED)
+        return 0.0f;
+    return (float)((c->ud_half ? 0.5 : 1.0) * c->p.h / c->mass);
 }
 
 float list_rc2(const sop_ctx *c) { return (float)(c->p.r_list * c->p.r_list); }
@@ -427,25 +451,31 @@ sop_status need_ready(sop_ctx *c)
 }
 
 // Plain-schedule list rebuild at step c->step.  The skin is rebuilt first
-// unless the displacement check of the step before left it valid (graph
-// replays capture rebuilds that rely on that check: `captured`).
+// when there is no skin, or unless the displacement check of the step before
+// left it valid (graph replays capture rebuilds that rely on that check:
+// `captured`).
 void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false)
 {
-    if (!captured && (c->skin_checked != c->step || skin_check_thr2(c) <= 0.0f))
+    // in cadence: the step before was a period's last step, which binned its
+    // positions and checked their displacements
+    const bool in_cadence = captured || c->skin_checked == c->step;
+    if (skin_check_thr2(c) <= 0.0f || !in_cadence)
         launch_force_skin(c->b, s);
     launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), skin_rs2(c),
-                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every);
+                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every, in_cadence);
 }
 
 // Whether step `step` is the last of a list period: its kernel checks the
 // displacements against the skin.
 bool checks_skin(const sop_ctx *c, long long step) { return (step + 1) % c->p.list_every == 0; }
 
+// `check`: the last step of a list period, which bins its new positions for
+// the next skin search and checks their displacements.
 void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy, bool check)
 {
     launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                 c->pulls.empty() ? 0 : 1, energy, 0, base, off, check ? skin_check_thr2(c) : 0.0f, s,
-                c->force_mode);
+                c->force_mode, ud_kick(c), check ? &c->grid : nullptr);
     if (energy)
         launch_reduce_energy(c->b, c->n_traj, s);
 }
@@ -455,7 +485,7 @@ void batch_launch(sop_ctx *c, hipStream_t s, int n_steps, int stale, int mode, c
 {
     launch_batch(c->b, c->cur, n_packs(c), c->batch_wg, c->cap, step_consts(c), c->tip,
                  c->pulls.empty() ? 0 : 1, list_rc2(c), c->p.list_every, c->energy_every, n_steps,
-                 stale, mode, base, off, s);
+                 stale, mode, base, off, s, c->re_rep > 0 ? c->b.re_tscale : nullptr);
 }
 
 // Last step in [first, first + n) whose energies are recorded, or -1.
@@ -504,6 +534,8 @@ sop_status capture_graph(sop_ctx *c, int par, int energy)
     c->cur = par;
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    const bool half_saved = c->ud_half;
+    c->ud_half = false;  // graphs start only after the first (half-kick) step
     for (int q = 0; q < c->graph_steps; ++q) {
         rebuild(c, c->cap_stream, true, true);
         for (int k = 0; k < c->p.list_every; ++k) {
@@ -514,6 +546,7 @@ sop_status capture_graph(sop_ctx *c, int par, int energy)
     }
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     c->cur = saved;
+    c->ud_half = half_saved;
     if (e != hipSuccess)
         return hip_fail(c, e, "hipStreamEndCapture");
     hipGraphExec_t ex = nullptr;
@@ -906,6 +939,148 @@ sop_status sop_get_force_mode(const sop_ctx *c, int32_t *mode)
     return SOP_OK;
 }
 
+sop_status sop_set_integrator(sop_ctx *c, int32_t kind, double mass)
+{
+    if (!c || (kind != SOP_INTEGRATOR_OVERDAMPED && kind != SOP_INTEGRATOR_UNDERDAMPED))
+        return SOP_E_ARG;
+    if (kind == SOP_INTEGRATOR_UNDERDAMPED && !(mass > 0.0 && std::isfinite(mass)))
+        return fail(c, SOP_E_ARG, "the mass must be positive and finite");
+    if (kind == SOP_INTEGRATOR_UNDERDAMPED && c->schedule != SOP_SCHEDULE_PLAIN)
+        return fail(c, SOP_E_STATE, "the underdamped integrator runs on the plain schedule");
+    c->integrator = kind;
+    if (kind == SOP_INTEGRATOR_UNDERDAMPED)
+        c->mass = mass;
+    c->ud_half = true;
+    destroy_graphs(c);  // the integrator's constants are kernel arguments
+    return SOP_OK;
+}
+
+sop_status sop_set_velocities(sop_ctx *c, const double *v)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (!v)
+        return fail(c, SOP_E_ARG, "null velocities");
+    if (c->schedule != SOP_SCHEDULE_PLAIN)
+        return fail(c, SOP_E_STATE, "velocities belong to the plain schedule");
+    const long long n = c->n_res;
+    std::vector<float4> vv(n);
+    for (long long i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(v[3 * i + a]))
+                return fail(c, SOP_E_ARG, "non-finite velocity");
+        vv[i] = c->fixed[i] ? float4{0.f, 0.f, 0.f, 0.f}
+                            : float4{(float)v[3 * i], (float)v[3 * i + 1], (float)v[3 * i + 2], 0.f};
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->b.vel, vv.data(), n * sizeof(float4), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->ud_half = true;
+    return SOP_OK;
+}
+
+sop_status sop_get_velocities(sop_ctx *c, double *v)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (!v)
+        return fail(c, SOP_E_ARG, "null output");
+    if (c->schedule != SOP_SCHEDULE_PLAIN)
+        return fail(c, SOP_E_STATE, "velocities belong to the plain schedule");
+    const long long n = c->n_res;
+    std::vector<float4> fo(n, float4{0.f, 0.f, 0.f, 0.f}), vv(n);
+    const bool add_kick = c->integrator == SOP_INTEGRATOR_UNDERDAMPED && !c->ud_half;
+    if (add_kick) {
+        // the stored velocities lack the last half kick, whose force is this step's
+        if (!c->list_valid || c->step % c->p.list_every == 0)
+            rebuild(c, c->stream, false);
+        c->list_valid = true;
+        launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
+                    c->pulls.empty() ? 0 : 1, false, 1, nullptr, c->step, 0.0f, c->stream, c->force_mode);
+        HIP_TRY(c, hipGetLastError());
+        st = check_device_errors(c);
+        if (st != SOP_OK)
+            return st;
+        HIP_TRY(c, hipMemcpy(fo.data(), c->b.fout, n * sizeof(float4), hipMemcpyDeviceToHost));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(vv.data(), c->b.vel, n * sizeof(float4), hipMemcpyDeviceToHost));
+    const double hk = 0.5 * c->p.h / c->mass;
+    for (long long i = 0; i < n; ++i) {
+        const bool fx = c->fixed[i] != 0;
+        v[3 * i] = fx ? 0.0 : (double)vv[i].x + (add_kick ? hk * (double)fo[i].x : 0.0);
+        v[3 * i + 1] = fx ? 0.0 : (double)vv[i].y + (add_kick ? hk * (double)fo[i].y : 0.0);
+        v[3 * i + 2] = fx ? 0.0 : (double)vv[i].z + (add_kick ? hk * (double)fo[i].z : 0.0);
+    }
+    return check_device_errors(c);
+}
+
+sop_status sop_set_tempering(sop_ctx *c, int32_t n_rep, const double *kbt, int64_t exchange_every,
+                             const int32_t *tidx)
+{
+    if (!c)
+        return SOP_E_ARG;
+    if (c->schedule != SOP_SCHEDULE_BATCHED || !c->bound)
+        return fail(c, SOP_E_STATE, "replica exchange runs on a bound batched schedule");
+    if (n_rep < 1 || !kbt || exchange_every < 0 || c->n_traj % n_rep != 0)
+        return fail(c, SOP_E_ARG, "n_rep must divide the trajectory count; exchange_every >= 0");
+    for (int k = 0; k < n_rep; ++k)
+        if (!(kbt[k] > 0.0) || !std::isfinite(kbt[k]))
+            return fail(c, SOP_E_ARG, "temperatures must be positive");
+    const int T = c->n_traj;
+    std::vector<int> ti(T);
+    std::vector<float> ts(T);
+    for (int t = 0; t < T; ++t)
+        ti[t] = tidx ? tidx[t] : t % n_rep;
+    for (int g = 0; g < T / n_rep; ++g) {  // each group a permutation of 0..n_rep-1
+        std::vector<char> seen(n_rep, 0);
+        for (int m = 0; m < n_rep; ++m) {
+            const int v = ti[g * n_rep + m];
+            if (v < 0 || v >= n_rep || seen[v])
+                return fail(c, SOP_E_ARG, "temperature indices are not a permutation in each group");
+            seen[v] = 1;
+        }
+    }
+    for (int t = 0; t < T; ++t)
+        ts[t] = (float)std::sqrt(kbt[ti[t]] / c->p.kBT);
+    c->re_rep = n_rep;
+    c->re_kbt.assign(kbt, kbt + n_rep);
+    c->re_every = exchange_every;
+    c->re_last = -1;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, hipMemcpyAsync(c->b.re_kbt, kbt, n_rep * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->b.re_tidx, ti.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->b.re_tscale, ts.data(), T * sizeof(float), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(c->b.re_stats, 0, 2 * (size_t)T * sizeof(unsigned long long), s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    destroy_graphs(c);
+    return SOP_OK;
+}
+
+sop_status sop_get_tempering(sop_ctx *c, int32_t *tidx, int64_t *accepted, int64_t *attempted)
+{
+    sop_status st = need_ready(c);
+    if (st != SOP_OK)
+        return st;
+    if (c->re_rep < 1)
+        return fail(c, SOP_E_STATE, "no replica exchange set");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int T = c->n_traj, R = c->re_rep;
+    if (tidx)
+        HIP_TRY(c, hipMemcpy(tidx, c->b.re_tidx, T * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> stv(2 * (size_t)T);
+    HIP_TRY(c, hipMemcpy(stv.data(), c->b.re_stats, stv.size() * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost));
+    for (int k = 0; k + 1 < R; ++k) {
+        if (accepted)
+            accepted[k] = (int64_t)stv[2 * k];
+        if (attempted)
+            attempted[k] = (int64_t)stv[2 * k + 1];
+    }
+    return check_device_errors(c);
+}
+
 sop_status sop_set_list_skin(sop_ctx *c, double skin)
 {
     if (!c || !(skin >= 0.0) || !std::isfinite(skin) || skin > 4.0 * c->p.r_list)
@@ -1039,6 +1214,7 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
         HIP_TRY(c, hipMemsetAsync(b.fcnt, 0, n * sizeof(int), s));
         HIP_TRY(c, hipMemsetAsync(b.cell_count, 0, (size_t)c->n_cells_cap * sizeof(int), s));
         HIP_TRY(c, hipMemsetAsync(b.facc, 0, n * sizeof(float4), s));
+        HIP_TRY(c, hipMemsetAsync(b.vel, 0, n * sizeof(float4), s));
         HIP_TRY(c, hipMemsetAsync(b.tile_ord, 0, n_tiles_max * 256, s));
         HIP_TRY(c, hipMemsetAsync(b.eacc, 0, n * sizeof(double4), s));
         HIP_TRY(c, hipMemsetAsync(b.topo2, 0, topo2_elems * sizeof(uint2), s));
@@ -1096,7 +1272,10 @@ sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
     HIP_TRY(c, hipMemcpyAsync(c->b.traj_cell, c->traj_cell.data(), c->n_traj * sizeof(int4),
                               hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(c->b.err, 0, sizeof(unsigned), s));
+    if (c->schedule == SOP_SCHEDULE_PLAIN)
+        HIP_TRY(c, hipMemsetAsync(c->b.vel, 0, n * sizeof(float4), s));  // new coordinates, zero velocities
     HIP_TRY(c, hipStreamSynchronize(s));
+    c->ud_half = true;
     c->cur = 0;
     c->sticky = 0;
     c->coords = true;
@@ -1279,12 +1458,26 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
         return fail(c, status_from_bits(c->sticky), bits_message(c->sticky));
     if (c->schedule == SOP_SCHEDULE_BATCHED) {
         const long long K = c->batch_steps;
+        const long long X = c->re_rep > 1 ? c->re_every : 0;
         bool base_set = false;
         long long q = 0;
         while (q < n_steps) {
-            const long long k = std::min<long long>(K, n_steps - q);
+            if (X > 0 && c->step % X == 0 && c->re_last != c->step) {
+                // replica exchange before this step's update: energies of
+                // the current positions, then one round of swaps
+                batch_launch(c, c->stream, 1, c->list_valid ? 0 : 1, 1, nullptr, c->step);
+                c->list_valid = true;
+                c->energy_step = c->step;
+                launch_exchange(c->b, c->re_rep, (int)(c->n_traj / c->re_rep), c->p.kBT, c->step / X,
+                                (unsigned)(c->p.seed & 0xffffffffu), (unsigned)(c->p.seed >> 32), c->stream);
+                c->re_last = c->step;
+                base_set = false;
+            }
+            long long k = std::min<long long>(K, n_steps - q);
+            if (X > 0)
+                k = std::min<long long>(k, X - c->step % X);  // stop at the next exchange
             const long long rec = last_record(c, c->step, k);
-            if (c->graph_steps > 0 && c->list_valid && k == K) {
+            if (c->graph_steps > 0 && c->list_valid && k == K && X == 0) {
                 if (!c->bgraphs[c->cur]) {
                     st = capture_batch_graph(c, c->cur);
                     if (st != SOP_OK)
@@ -1320,7 +1513,8 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
     bool base_set = false;
     long long q = 0;
     while (q < n_steps) {
-        if (graphs_ok && c->step % align == 0 && n_steps - q >= span) {
+        if (graphs_ok && c->step % align == 0 && n_steps - q >= span &&
+            !(c->integrator == SOP_INTEGRATOR_UNDERDAMPED && c->ud_half)) {
             const int en = (E > 0 && c->step % E == 0) ? 1 : 0;
             if (!c->graphs[c->cur][en]) {
                 st = capture_graph(c, c->cur, en);
@@ -1331,8 +1525,11 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
                 launch_set_step(c->b.step_next, c->step, c->stream);
                 base_set = true;
             }
-            if (c->skin_checked != c->step || skin_check_thr2(c) <= 0.0f)
-                launch_force_skin(c->b, c->stream);  // the graph's first rebuild builds the skin
+            if (c->skin_checked != c->step) {
+                // the graph's first rebuild searches, from freshly binned positions
+                launch_bin_all(c->b, c->cur, (int)c->n_res, c->grid, c->stream);
+                launch_force_skin(c->b, c->stream);
+            }
             HIP_TRY(c, hipGraphLaunch(c->graphs[c->cur][en], c->stream));
             if (en)
                 c->energy_step = c->step;
@@ -1351,6 +1548,7 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
         const bool en = E > 0 && c->step % E == 0;
         const bool chk = checks_skin(c, c->step);
         one_step(c, c->stream, nullptr, c->step, en, chk);
+        c->ud_half = false;
         if (en)
             c->energy_step = c->step;
         c->cur ^= 1;
@@ -1455,12 +1653,13 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
             if (kind == 0) {
                 launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                             c->pulls.empty() ? 0 : 1, false, 0, nullptr, c->step + q, 0.0f,
-                            c->cap_stream, c->force_mode);
+                            c->cap_stream, c->force_mode, 0.0f);
                 c->cur ^= 1;
             } else {
-                if (kind == 1)
-                    launch_force_skin(c->b, c->cap_stream);
-                rebuild(c, c->cap_stream, false, true);
+                // kind 1: a search from freshly binned positions; kind 2:
+                // the filter alone (the skin stays valid)
+                c->skin_checked = -1;
+                rebuild(c, c->cap_stream, false, kind == 2);
             }
         }
         e = hipStreamEndCapture(c->cap_stream, &g);
@@ -1637,7 +1836,9 @@ void cache_store(const char *path, const std::string &key, int a, int b)
 }
 
 // Residue-steps per second of `steps` steps from the saved state.
-sop_status trial(sop_ctx *c, long long steps, double *rate)
+// A candidate slower than a third of `best` (residue-steps/s; 0: none yet)
+// is stopped after the first eighth of its steps.
+sop_status trial(sop_ctx *c, long long steps, double *rate, double best = 0.0)
 {
     const size_t bytes = 2 * (size_t)c->n_res * sizeof(float4);
     HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1648,15 +1849,27 @@ sop_status trial(sop_ctx *c, long long steps, double *rate)
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     sop_status st = sop_step(c, 2 * c->p.list_every);  // warm up: capture graphs, touch caches
-    if (st == SOP_OK) {
-        (void)hipEventRecord(e0, c->stream);
-        st = sop_step(c, steps);
-        (void)hipEventRecord(e1, c->stream);
-    }
+    const long long L2 = 2 * c->p.list_every;
+    const long long chunk = std::max<long long>(L2, (steps / 8 / L2) * L2);
+    long long done = 0;
     float ms = 0.0f;
-    if (st == SOP_OK && hipEventSynchronize(e1) == hipSuccess &&
-        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-        *rate = ms > 0 ? (double)c->n_res * (double)steps / (1e-3 * ms) : 0.0;
+    if (st == SOP_OK)
+        (void)hipEventRecord(e0, c->stream);
+    while (st == SOP_OK && done < steps) {
+        const long long k = std::min(chunk, steps - done);
+        st = sop_step(c, k);
+        done += k;
+        (void)hipEventRecord(e1, c->stream);
+        if (st != SOP_OK || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            ms = 0.0f;
+            break;
+        }
+        const double r = ms > 0 ? (double)c->n_res * (double)done / (1e-3 * ms) : 0.0;
+        if (best > 0.0 && r < best / 3.0)
+            break;  // clearly slower: no need for the rest
+    }
+    *rate = ms > 0 ? (double)c->n_res * (double)done / (1e-3 * ms) : 0.0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // back to the saved state (the trial advanced the layer parity too)
@@ -1723,7 +1936,7 @@ sop_status sop_autotune(sop_ctx *c, double budget_ms, const char *cache_path)
         if (st != SOP_OK)
             return st;
         double rate = 0.0;
-        st = trial(c, steps, &rate);
+        st = trial(c, steps, &rate, best);
         if (st != SOP_OK)
             return st;
         if (rate > best) {

@@ -79,6 +79,11 @@ struct DevBufs {
     unsigned *skin_flag;     // plain: nonzero when the next rebuild must rebuild the skin
     unsigned long long *list_stats;  // plain: {rebuilds, skin builds} since binding
     unsigned char *tile_ord; // plain: per tile (tile * T + rank), its residues by decreasing list length
+    float4 *vel;             // plain, underdamped: per-residue velocity before its last half kick
+    double *re_kbt;          // batched, replica exchange: the temperature ladder (kB T)
+    int *re_tidx;            // batched, replica exchange: temperature index of each trajectory
+    float *re_tscale;        // batched, replica exchange: sqrt(kB T / kB T of the parameters)
+    unsigned long long *re_stats;  // batched, replica exchange: {accepted, attempted} per ladder pair
     float4 *facc;            // plain, pair-based forces: per-residue force accumulator
     double4 *eacc;           // plain, pair-based forces: per-residue energy accumulator
     uint2 *topo2;            // plain: {slot, r0 bits} of bonded/native partners, (i/T)*TOPO_CAP*T + e*T + i%T
@@ -117,18 +122,25 @@ struct DevBufs {
 struct StepConsts {
     float k_fene, R0sq, inv_R0sq, eps_h, eps_l, sigma2;
     float c_drift, c_noise;
+    float ud_c1, ud_c2;  // underdamped: exp(-zeta h/m), sqrt((1 - c1^2) kB T/m)
     unsigned key0, key1;
     double h;
 };
 
 // ---- kernel launchers (sop_kernels.hip) ----------------------------------
 // Plain schedule, tiles of `tile` residues (64, 128 or 256).
-// The skin build (cell binning and the per-tile rows within sqrt(rs2)) runs
-// only when the device skin flag is set; the filter to rc2 always runs.
+// The skin search (the per-tile rows within sqrt(rs2) from the cell grid,
+// renumbered by residue id) runs only when the device skin flag is set; the
+// filter to rc2 always runs.  `binned`: the cells already hold the current
+// positions (binned by the last step kernel of the period); otherwise they
+// are cleared and filled first.
 void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int tile, const GridDev &g,
-                    float rc2, float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every);
+                    float rc2, float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every,
+                    bool binned);
 // Sets the skin flag so that the next rebuild rebuilds the skin.
 void launch_force_skin(const DevBufs &b, hipStream_t s);
+// Clears the cells and bins every residue at its current position.
+void launch_bin_all(const DevBufs &b, int cur, int n_res, const GridDev &g, hipStream_t s);
 // mode: 0 = step, 1 = forces only.  check_thr2 > 0: after the update, a
 // residue that moved more than sqrt(check_thr2) from its position at the
 // last skin build sets the skin flag.
@@ -137,7 +149,7 @@ void launch_force_skin(const DevBufs &b, hipStream_t s);
 void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode,
                  const long long *step_base, long long step_off, float check_thr2, hipStream_t s,
-                 int force_mode = 0);
+                 int force_mode = 0, float ud_kick = 0.0f, const GridDev *bin_grid = nullptr);
 // Residues per chunk of the energy reduction (chunks never span trajectories).
 constexpr int ECHUNK = 1024;
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
@@ -146,7 +158,11 @@ void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
 void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const StepConsts &c,
                   const TipDev &tip, int has_pull, float rc2, int list_every, long long energy_every,
                   int n_steps, int stale, int mode, const long long *step_base, long long step_off,
-                  hipStream_t s);
+                  hipStream_t s, const float *tscale = nullptr);
+// Replica exchange: the swaps of one round from the energies recorded in
+// b.energy (see k_exchange).
+void launch_exchange(const DevBufs &b, int n_rep, int n_groups, double kbt_ref, long long round,
+                     unsigned key0, unsigned key1, hipStream_t s);
 void launch_add_step(long long *base, long long k, hipStream_t s);
 void launch_set_step(long long *dst, long long value, hipStream_t s);
 void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long long step, uint4 *words,

@@ -71,36 +71,44 @@ __device__ __forceinline__ int cell_index(const float4 &p, const int4 &off, cons
     return cx + g.gx * (cy + g.gy * cz);
 }
 
-// Also advances the step counter of graph replays (once per rebuild) when
-// step_base is given.  Bins only when the skin flag is set (the skin build),
-// and then records each residue's high part in hi_skin.
-__global__ void k_bin(const float4 *__restrict__ pos, int n, GridDev g, const int4 *__restrict__ traj_cell,
-                      int *__restrict__ count, float4 *__restrict__ cells, int *__restrict__ cell_of,
-                      unsigned *__restrict__ err, long long *step_base, long long *step_next, int period,
-                      const unsigned *__restrict__ skin_flag, float4 *__restrict__ hi_skin,
-                      unsigned long long *__restrict__ stats)
+// Bin one residue at high part p into the grid of the next skin search:
+// its cell, a slot in that cell, and a copy of p there.
+__device__ __forceinline__ void bin_one(const float4 &p, int i, int traj, const GridDev &g,
+                                        const int4 *__restrict__ traj_cell, int *__restrict__ count,
+                                        float4 *__restrict__ cells, int *__restrict__ cell_of,
+                                        unsigned *__restrict__ err)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && step_base) {
-        const long long nb = *step_next;
-        *step_base = nb;
-        *step_next = nb + period;
-    }
-    if (i >= n || *skin_flag == 0u)
-        return;
-    if (i == 0)
-        ++stats[1];
-    const float4 p = pos[2 * i];
-    hi_skin[i] = p;
-    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))
-        atomicOr(err, ERR_NONFINITE);
-    const int c = cell_index(p, traj_cell[__float_as_int(pos[2 * i + 1].w)], g);
+    const int c = cell_index(p, traj_cell[traj], g);
     cell_of[i] = c;
     const int slot = atomicAdd(&count[c], 1);
     if (slot < CELL_CAP)
         cells[(size_t)c * CELL_CAP + slot] = make_float4(p.x, p.y, p.z, __int_as_float(i));
     else
         atomicOr(err, ERR_CELL);
+}
+
+__global__ void k_clear(int *__restrict__ a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        a[i] = 0;
+}
+
+// Every residue binned at its current position.  The last step kernel of
+// each list period bins the positions it writes; this kernel serves the
+// rebuilds that do not follow such a step (after new coordinates, a new
+// step count or a new tile size), after k_clear.
+__global__ void k_bin_all(const float4 *__restrict__ pos, int n, GridDev g, const int4 *__restrict__ traj_cell,
+                          int *__restrict__ count, float4 *__restrict__ cells, int *__restrict__ cell_of,
+                          unsigned *__restrict__ err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float4 p = pos[2 * i];
+    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z))
+        atomicOr(err, ERR_NONFINITE);
+    bin_one(p, i, __float_as_int(pos[2 * i + 1].w), g, traj_cell, count, cells, cell_of, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,6 +323,46 @@ __device__ __forceinline__ void update_with_noise(float4 &hi, float4 &lo, const 
     lo = make_float4(nl[0], nl[1], nl[2], lo.w);
 }
 
+// Underdamped Langevin step (BAOAB): the velocity v stored between steps is
+// the one before the last half kick of the previous step, so one kick of
+// `kick` (h/m, or h/2m on the first step after velocities were set) with
+// the force of this step covers that half kick and this step's first one;
+// then x += (h/2) w, w = c1 w + c2 g, x += (h/2) w (compensated), v = w.
+struct UdConsts {
+    float kick, c1, c2, half_h;
+};
+
+__device__ __forceinline__ void underdamped_update(float4 &hi, float4 &lo, float4 &v, const Acc &A,
+                                                   const float g[3], const UdConsts &u, unsigned *err)
+{
+    if (__float_as_uint(hi.w) >> 31) {
+        v = make_float4(0.f, 0.f, 0.f, 0.f);  // fixed residue
+        return;
+    }
+    float nh[3], nl[3], nv[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const float f = ax == 0 ? A.fx : (ax == 1 ? A.fy : A.fz);
+        const float w0 = comp(v, ax) + u.kick * f;
+        const float w1 = u.c1 * w0 + u.c2 * g[ax];
+        const float delta = u.half_h * w0 + u.half_h * w1;
+        const float h0 = comp(hi, ax), l0 = comp(lo, ax);
+        const float y = delta + l0;
+        const float t = h0 + y;
+        const float bp = t - h0;
+        const float ap = t - bp;
+        nl[ax] = (h0 - ap) + (y - bp);
+        nh[ax] = t;
+        nv[ax] = w1;
+    }
+    if (!isfinite(nh[0]) || !isfinite(nh[1]) || !isfinite(nh[2]) || !isfinite(nv[0]) ||
+        !isfinite(nv[1]) || !isfinite(nv[2]))
+        atomicOr(err, ERR_NONFINITE);
+    hi = make_float4(nh[0], nh[1], nh[2], hi.w);
+    lo = make_float4(nl[0], nl[1], nl[2], lo.w);
+    v = make_float4(nv[0], nv[1], nv[2], 0.0f);
+}
+
 // Noise (Section III.C) and the first-order update (Eq. 2 / Algorithm 7)
 // with compensated positions.
 __device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Acc &A, long long step,
@@ -369,6 +417,8 @@ struct BuildArgs {
     int *stage_cnt;
     unsigned *err;
     const unsigned *skin_flag;
+    float4 *hi_skin;
+    unsigned long long *stats;
     GridDev g;
     float rc2;
     int n, cap;
@@ -471,6 +521,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
     const bool act = rho < tcnt;
     const bool lead = act && q == 0;  // writes the residue's count and padding
     const GridDev g = a.g;
+    if (tile == 0 && t == 0)
+        ++a.stats[1];
+    if (lead)
+        a.hi_skin[i] = a.pos[2 * i];  // the displacement check's reference
     for (int h = t; h < CHASH; h += NT)
         hkey[h] = -1;
     if (t < TILE)
@@ -923,8 +977,10 @@ struct FilterArgs {
     unsigned *skin_flag;
     unsigned long long *stats;
     unsigned char *tile_ord;  // per tile: its residues by decreasing list length
+    long long *step_base;     // graph replays: advanced once per rebuild, or NULL
+    long long *step_next;
     float rc2;
-    int cap, n_cells;
+    int cap, n_cells, period;
 };
 
 template <int TILE>
@@ -932,8 +988,10 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
 {
     constexpr int NL = 256 / TILE;  // lanes per residue, adjacent in the wave
     constexpr int SM = stage_max<TILE>();
+    constexpr int OUTW = 16384 / TILE;  // filtered entries of a residue gathered in LDS (32 KB in all)
     __shared__ float4 hs[SM];
     __shared__ int lens[TILE];
+    __shared__ __align__(16) unsigned short out_s[TILE * OUTW];
     const int tile = blockIdx.x, t = threadIdx.x;
     const int rho = t / NL, q = t % NL;
     // the cell counts are read only by the skin build, which is done: clear
@@ -943,6 +1001,12 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
     if (tile == 0 && t == 0) {
         *a.skin_flag = 0u;
         ++a.stats[0];
+        if (a.step_base) {
+            // graph replays: this rebuild starts the next list period
+            const long long nb = *a.step_next;
+            *a.step_base = nb;
+            *a.step_next = nb + a.period;
+        }
     }
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
     const int S = a.stage_cnt[tile];
@@ -958,18 +1022,36 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
     // a residue's lanes read 16 NL contiguous bytes per round
     const uint4 *src = reinterpret_cast<const uint4 *>(a.skin16 + (size_t)i * a.cap);
     unsigned short *dst = a.list16 + (size_t)i * a.cap;
+    // rows that fit are gathered in LDS and written out in 16-byte pieces
+    const bool in_lds = len <= OUTW - 8;
+    unsigned short *ob = in_lds ? out_s + rho * OUTW : dst;
     const int npc = (len + 7) >> 3;
     int rounds = (npc + NL - 1) / NL;
 #pragma unroll
     for (int off = 1; off < NL; off <<= 1)
         rounds = max(rounds, __shfl_xor(rounds, off, NL));  // uniform over the residue's lanes
+    // the first PF pieces of this lane are loaded up front, so their
+    // latencies overlap
+    constexpr int PF = 8;
+    uint4 pre[PF];
+#pragma unroll
+    for (int m = 0; m < PF; ++m)
+        pre[m] = m * NL + q < npc ? src[m * NL + q] : make_uint4(0u, 0u, 0u, 0u);
     int base = 0;
     for (int m = 0; m < rounds; ++m) {
         const int pc = m * NL + q;
         unsigned e[8];
         unsigned bits = 0u;
         if (pc < npc) {
-            const uint4 w = src[pc];
+            uint4 w;
+            if (m < PF) {
+#pragma unroll
+                for (int mm = 0; mm < PF; ++mm)
+                    if (mm == m)
+                        w = pre[mm];
+            } else {
+                w = src[pc];
+            }
             const unsigned ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -991,18 +1073,24 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
         while (bits) {
             const int u = __ffs(bits) - 1;
             bits &= bits - 1u;
-            dst[o++] = (unsigned short)e[u];
+            ob[o++] = (unsigned short)e[u];
         }
         base += __shfl(v, NL - 1, NL);
     }
     if (act && q == NL - 1) {
-        // pad the row's last chunk of 4 with the empty slot SM
-        for (int k = base; k < ((base + 3) & ~3); ++k)
-            dst[k] = (unsigned short)SM;
+        // pad the row to a multiple of 8 entries with the empty slot SM
+        for (int k = base; k < ((base + 7) & ~7); ++k)
+            ob[k] = (unsigned short)SM;
         a.list_cnt[i] = base;
         lens[rho] = base;
     }
     __syncthreads();
+    if (act && in_lds) {
+        const uint4 *sp = reinterpret_cast<const uint4 *>(out_s + rho * OUTW);
+        uint4 *dp = reinterpret_cast<uint4 *>(dst);
+        for (int pc = q; pc < ((base + 7) >> 3); pc += NL)
+            dp[pc] = sp[pc];
+    }
     // the step kernel hands the rows to its waves longest first, so that the
     // rows a wave sums have about the same length (ties in index order)
     if (act && q == 0) {
@@ -1075,9 +1163,34 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
             const int i = first + rho;
             len = min(a.skin_cnt[i], a.cap);
             row = a.skin16 + (size_t)i * a.cap;
-            for (int k = q; k < len; k += NLG) {
-                const int ns = nslot[row[k]];
-                atomicOr(&mask[(t / NLG) * MW + (ns >> 5)], 1u << (ns & 31));
+            // the row in 16-byte pieces (8 entries), pieces q, q + NLG, ...;
+            // the first CPF of them loaded up front
+            constexpr int CPF = 8;
+            const uint4 *rp = reinterpret_cast<const uint4 *>(row);
+            const int npc = (len + 7) >> 3;
+            uint4 pre[CPF];
+#pragma unroll
+            for (int m = 0; m < CPF; ++m)
+                pre[m] = m * NLG + q < npc ? rp[m * NLG + q] : make_uint4(0u, 0u, 0u, 0u);
+            for (int m = 0; m * NLG + q < npc; ++m) {
+                const int pc = m * NLG + q;
+                uint4 w;
+                if (m < CPF) {
+#pragma unroll
+                    for (int mm = 0; mm < CPF; ++mm)
+                        if (mm == m)
+                            w = pre[mm];
+                } else {
+                    w = rp[pc];
+                }
+                const unsigned ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (pc * 8 + u < len) {
+                        const int ns = nslot[(ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu];
+                        atomicOr(&mask[(t / NLG) * MW + (ns >> 5)], 1u << (ns & 31));
+                    }
+                }
             }
             // bonded and native entries: renumber in place
             const int2 rw = a.trow[i];
@@ -1141,10 +1254,20 @@ struct TileArgs {
     const float4 *hi_skin;
     unsigned *skin_flag;
     const unsigned char *tile_ord;
+    float4 *vel;          // underdamped: per-residue velocity (NULL: overdamped)
+    // the last step of a list period bins its new positions for the next
+    // skin search (do_bin)
+    const int4 *traj_cell;
+    int *cell_count;
+    float4 *cells;
+    int *cell_of;
+    GridDev g;
+    int do_bin;
     long long step_off;
     float check_thr2;
     int n, cap, has_pull, n_tiles;
     StepConsts c;
+    UdConsts ud;
     TipDev tip;
 };
 
@@ -1215,26 +1338,36 @@ __device__ __forceinline__ float3 unpack_low(const float4 &s)
 constexpr float NARROW_TILE = 40.0f;
 
 // The plain step: one workgroup of 256 lanes per tile of TILE consecutive
-// residues, NL = 256/TILE adjacent lanes per residue.
-//  1. The last TILE lanes draw their residue's Gaussians (Philox and
-//     Box-Muller, from the counter words that do not depend on the position)
-//     and evaluate its cantilever and tip terms while every lane stages the
-//     tile's slots: each slot's position relative to the tile origin (its
-//     middle residue) as the exactly rounded high part of a TwoSum split, and
-//     only when some staged position lies 64 A or more from the origin, the
-//     low part too (a 10-bit multiple of the high part's ulp per axis).
-//  2. Lane q of a residue sums the list chunks (4 slots each) q, q + NL, ...
-//     of its row, and its bonded and native entries q, q + NL, ... from the
-//     compensated positions in device memory; the NL partial sums are added
-//     by butterfly shuffles, which give every lane the same bits.
-//  3. After a barrier the last TILE lanes add the external terms and the
-//     noise and take the compensated step.
+// residues, NL = 256/TILE adjacent lanes per residue, the tile's residues
+// handed to the lanes longest list row first.
+//  1. Every load that does not need the staging is issued first: the
+//     residue's own position and row, its first PRE list chunks (4 slots
+//     each: chunks q, q + NL, ... for lane q), its first bonded/native
+//     entries and their partners' compensated positions, and the tile's
+//     slot ids.
+//  2. The last TILE lanes draw their residue's Gaussians (Philox and
+//     Box-Muller, from the counter words that do not depend on the
+//     position) and evaluate its cantilever and tip terms; every lane stages
+//     slots (each position relative to the tile origin, its middle residue,
+//     as the exactly rounded high part of a TwoSum split) and evaluates its
+//     bonded and native entries from the compensated positions.
+//  3. After the barrier the list chunks are summed from the staged
+//     positions: high parts only when every residue of the tile lies within
+//     NARROW_TILE of the origin, else high and low parts (the low parts, a
+//     10-bit multiple of the high part's ulp per axis, are staged then).
+//     The NL partial sums of a residue are added by butterfly shuffles,
+//     which give every lane the same bits.
+//  4. After a second barrier the last TILE lanes add the external terms and
+//     the noise and take the compensated step (first-order, or BAOAB).
 template <int TILE, bool ENERGY, int MODE>
 __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_tile_step(TileArgs a)
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
+    constexpr int PER = SM / 256;    // staging slots per lane
     constexpr int EPI = 256 - TILE;  // first lane of the update lanes
+    constexpr int PRE = 6;           // list chunks per lane loaded before the staging
+    constexpr int TPRE = 3;          // bonded/native entries per lane loaded before the staging
     __shared__ float4 sl_s[SM + 1];  // {rh.xyz, packed rl}; slot SM: the far-away empty slot
     __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
     __shared__ double e_s[ENERGY ? 4 : 1][ENERGY ? TILE : 1];
@@ -1249,8 +1382,6 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     const int *st = a.stage + (size_t)tile * SM;
     const int mid = first + tcnt / 2;
     const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
-    // this lane's residue in the list phase (the tile's rows longest first),
-    // and in the update phase
     const int q = t % NL;
     const bool act = t / NL < tcnt;
     const int rho = act ? (int)a.tile_ord[(size_t)tile * TILE + t / NL] : 0;
@@ -1258,6 +1389,11 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     const int ue = t - EPI;
     const bool upd = ue >= 0 && ue < tcnt;
     const int iu = first + ue;
+    // ---- 1. loads ----
+    int ids[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        ids[u] = t + u * 256 < S ? st[t + u * 256] : -1;
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
     int cnt = 0;
@@ -1268,7 +1404,27 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         cnt = min(a.list_cnt[i], a.cap);
     }
     const float4 O = a.pin[2 * mid];
-    // ---- 1. noise and external terms (update lanes), staging (all lanes) ----
+    const int nch = (cnt + 3) >> 2;
+    const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16 + (size_t)i * a.cap);
+    uint2 lw[PRE];
+#pragma unroll
+    for (int k = 0; k < PRE; ++k)
+        lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
+    const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
+    float2 te[TPRE];
+#pragma unroll
+    for (int k = 0; k < TPRE; ++k)
+        te[k] = q + k * NL < ntop ? a.tent[row.x + q + k * NL] : make_float2(0.f, 0.f);
+    float4 ph[TPRE], pl[TPRE];
+#pragma unroll
+    for (int k = 0; k < TPRE; ++k) {
+        if (q + k * NL < ntop) {
+            const int j = __float_as_int(te[k].x);
+            ph[k] = a.pin[2 * j];
+            pl[k] = a.pin[2 * j + 1];
+        }
+    }
+    // ---- 2. noise and external terms (update lanes), staging, bonded/native ----
     float4 hu = make_float4(0.f, 0.f, 0.f, 0.f), lu = hu;
     float g[3] = {0.0f, 0.0f, 0.0f};
     Acc X;
@@ -1289,41 +1445,65 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         add_external(X, e_x, f_rep, hu, lu, step, a.c.h, a.has_pull ? a.pull_slot[iu] : -1, a.pulls,
                      a.tip, ENERGY, a.err);
     }
-    for (int sl = t; sl < S; sl += 256) {
-        const int id = st[sl];
-        float4 rh, rl;
-        tile_frame(a.pin[2 * id], a.pin[2 * id + 1], O, rh, rl);
-        rh.w = 0.0f;
-        sl_s[sl] = rh;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (ids[u] >= 0) {
+            float4 rh, rl;
+            tile_frame(a.pin[2 * ids[u]], a.pin[2 * ids[u] + 1], O, rh, rl);
+            rh.w = 0.0f;
+            sl_s[t + u * 256] = rh;
+        }
     }
-    bool far = false;
     if (t == 0)
         sl_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+    const PairConsts k = pair_consts(a.c);
+    Acc A;   // bonded and native terms
+    bool broken = false;
+    if (act) {
+#pragma unroll
+        for (int kk = 0; kk < TPRE; ++kk) {
+            const int e = q + kk * NL;
+            if (e < ntop) {
+                const float3 d = pair_delta(hi0, lo0, ph[kk], pl[kk]);
+                if (e < nb)
+                    add_fene_d(A, d, te[kk].y, k, ENERGY, broken);
+                else
+                    add_native_d(A, d, te[kk].y, k, ENERGY);
+            }
+        }
+        for (int e = q + TPRE * NL; e < ntop; e += NL) {
+            const float2 tv = a.tent[row.x + e];
+            const int j = __float_as_int(tv.x);
+            const float3 d = pair_delta(hi0, lo0, a.pin[2 * j], a.pin[2 * j + 1]);
+            if (e < nb)
+                add_fene_d(A, d, tv.y, k, ENERGY, broken);
+            else
+                add_native_d(A, d, tv.y, k, ENERGY);
+        }
+        if (broken)
+            atomicOr(a.err, ERR_FENE);
+    }
     float4 rh0, rl0;
     tile_frame(hi0, lo0, O, rh0, rl0);
-    if (act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE))
-        far = true;
+    const bool far = act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE);
     const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
     if (wide) {
         // rare: the low parts of the staged positions, packed beside them
-        for (int sl = t; sl < S; sl += 256) {
-            const int id = st[sl];
-            float4 rh, rl;
-            tile_frame(a.pin[2 * id], a.pin[2 * id + 1], O, rh, rl);
-            sl_s[sl].w = __uint_as_float(pack_low(rh, rl));
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (ids[u] >= 0) {
+                float4 rh, rl;
+                tile_frame(a.pin[2 * ids[u]], a.pin[2 * ids[u] + 1], O, rh, rl);
+                sl_s[t + u * 256].w = __uint_as_float(pack_low(rh, rl));
+            }
         }
         rh0.w = __uint_as_float(pack_low(rh0, rl0));
         __syncthreads();
     }
-    const PairConsts k = pair_consts(a.c);
-    // ---- 2. list chunks and bonded/native entries of this lane ----
+    // ---- 3. list chunks of this lane ----
     Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
-    Acc A;   // bonded and native terms
-    bool broken = false;
     if (act) {
         const float3 pl0 = unpack_low(rh0);
-        const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16 + (size_t)i * a.cap);
-        const int nch = (cnt + 3) >> 2;
         auto pairs4 = [&](const uint2 &w) {
             float4 pj[4];
 #pragma unroll
@@ -1345,27 +1525,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
                 }
             }
         };
-        // two chunks in flight per iteration
-        int c = q;
-        for (; c + NL < nch; c += 2 * NL) {
-            const uint2 w0 = lp[c], w1 = lp[c + NL];
-            pairs4(w0);
-            pairs4(w1);
-        }
-        if (c < nch)
+#pragma unroll
+        for (int kk = 0; kk < PRE; ++kk)
+            if (q + kk * NL < nch)
+                pairs4(lw[kk]);
+        for (int c = q + PRE * NL; c < nch; c += NL)
             pairs4(lp[c]);
-        const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
-        for (int e = q; e < ntop; e += NL) {
-            const float2 te = a.tent[row.x + e];
-            const int j = __float_as_int(te.x);
-            const float3 d = pair_delta(hi0, lo0, a.pin[2 * j], a.pin[2 * j + 1]);
-            if (e < nb)
-                add_fene_d(A, d, te.y, k, ENERGY, broken);
-            else
-                add_native_d(A, d, te.y, k, ENERGY);
-        }
-        if (broken)
-            atomicOr(a.err, ERR_FENE);
     }
     // the residue's total over its NL lanes (butterfly: every lane gets the same bits)
     float fx = k.c6 * L.fx + A.fx, fy = k.c6 * L.fy + A.fy, fz = k.c6 * L.fz + A.fz;
@@ -1386,7 +1551,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         f_s[0][rho] = fx;
         f_s[1][rho] = fy;
         f_s[2][rho] = fz;
-        if (ENERGY) {
+        if constexpr (ENERGY) {
             e_s[0][rho] = eb;
             e_s[1][rho] = en;
             e_s[2][rho] = er;
@@ -1396,12 +1561,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     __syncthreads();
     if (!upd)
         return;
-    // ---- 3. external terms, noise and the compensated update ----
+    // ---- 4. external terms, noise and the compensated update ----
     Acc F;
     F.fx = f_s[0][ue] + X.fx;
     F.fy = f_s[1][ue] + X.fy;
     F.fz = f_s[2][ue] + X.fz;
-    if (ENERGY) {
+    if constexpr (ENERGY) {
         double *er_out = a.res_energy + (size_t)iu * RES_E;
         // each internal pair appears in both partners' rows
         er_out[0] = 0.5 * e_s[0][ue];
@@ -1416,7 +1581,13 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         return;
     }
     float4 hi = hu, lo = lu;
-    update_with_noise(hi, lo, F, g, a.c, a.err);
+    if (a.vel) {
+        float4 v = a.vel[iu];
+        underdamped_update(hi, lo, v, F, g, a.ud, a.err);
+        a.vel[iu] = v;
+    } else {
+        update_with_noise(hi, lo, F, g, a.c, a.err);
+    }
     a.pout[2 * iu] = hi;
     a.pout[2 * iu + 1] = lo;
     if (a.check_thr2 > 0.0f) {
@@ -1427,6 +1598,8 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         if (!(dx * dx + dy * dy + dz * dz <= a.check_thr2))
             atomicOr(a.skin_flag, 1u);
     }
+    if (a.do_bin)
+        bin_one(hi, iu, __float_as_int(lo.w), a.g, a.traj_cell, a.cell_count, a.cells, a.cell_of, a.err);
 }
 
 // ---------------------------------------------------------------------------
@@ -1446,6 +1619,7 @@ struct PairArgs {
     const unsigned short *list16;
     const int *list_cnt;
     const int *stage;
+    const int *stage_cnt;
     float4 *facc;   // per residue: accumulated force
     double4 *eacc;  // per residue: accumulated {FENE, native, repulsive, virial} halves
     unsigned *err;
@@ -1453,70 +1627,126 @@ struct PairArgs {
     StepConsts c;
 };
 
-__device__ __forceinline__ void pair_scatter(float4 *facc, double4 *eacc, int i, int j, const Acc &d, bool rec)
-{
-    unsafeAtomicAdd(&facc[i].x, d.fx);
-    unsafeAtomicAdd(&facc[i].y, d.fy);
-    unsafeAtomicAdd(&facc[i].z, d.fz);
-    unsafeAtomicAdd(&facc[j].x, -d.fx);
-    unsafeAtomicAdd(&facc[j].y, -d.fy);
-    unsafeAtomicAdd(&facc[j].z, -d.fz);
-    if (rec) {
-        // each residue's record holds half of its pairs' energies
-        const double hb = 0.5 * d.e_b, hn = 0.5 * d.e_n, hr = 0.5 * d.e_r, hv = 0.5 * d.vir;
-        unsafeAtomicAdd(&eacc[i].x, hb);
-        unsafeAtomicAdd(&eacc[i].y, hn);
-        unsafeAtomicAdd(&eacc[i].z, hr);
-        unsafeAtomicAdd(&eacc[i].w, hv);
-        unsafeAtomicAdd(&eacc[j].x, hb);
-        unsafeAtomicAdd(&eacc[j].y, hn);
-        unsafeAtomicAdd(&eacc[j].z, hr);
-        unsafeAtomicAdd(&eacc[j].w, hv);
-    }
-}
-
+// One workgroup per tile.  A list pair (i, j), i < j, is evaluated in
+// residue i's row; +df goes to i's running sum in registers and -df to j's
+// staging slot in LDS (a shared-memory float atomic); at the end each
+// residue's sum and each slot's sum are added to the device-wide
+// accumulators with one hardware float atomic per component.  Bonded and
+// native partners, which need no slot, take device-wide atomics directly.
 template <int TILE, bool ENERGY>
 __global__ __launch_bounds__(256) void k_pair_forces(PairArgs a)
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
+    __shared__ float acc_s[3][SM];
     const int tile = blockIdx.x, t = threadIdx.x;
     const int rho = t / NL, q = t % NL;
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
-    if (rho >= tcnt)
-        return;
-    const int i = first + rho;
+    const int S = a.stage_cnt[tile];
     const int *st = a.stage + (size_t)tile * SM;
-    const float4 hi = a.pin[2 * i], lo = a.pin[2 * i + 1];
+    for (int sl = t; sl < S; sl += 256) {
+        acc_s[0][sl] = 0.0f;
+        acc_s[1][sl] = 0.0f;
+        acc_s[2][sl] = 0.0f;
+    }
+    __syncthreads();
+    const bool act = rho < tcnt;
+    const int i = first + (act ? rho : 0);
     const PairConsts k = pair_consts(a.c);
-    const int cnt = min(a.list_cnt[i], a.cap);
-    const unsigned short *row = a.list16 + (size_t)i * a.cap;
-    for (int e = q; e < cnt; e += NL) {
-        const int j = st[row[e]];
-        if (j <= i)
-            continue;  // the pair belongs to the lower residue's row
-        Acc d;
-        add_repulsive_d(d, pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]), k, ENERGY);
-        pair_scatter(a.facc, a.eacc, i, j, d, ENERGY);
+    Acc own;  // residue i's share of its pairs
+    if (act) {
+        const float4 hi = a.pin[2 * i], lo = a.pin[2 * i + 1];
+        const int cnt = min(a.list_cnt[i], a.cap);
+        const unsigned short *row = a.list16 + (size_t)i * a.cap;
+        for (int e = q; e < cnt; e += NL) {
+            const int sl = row[e];
+            const int j = st[sl];
+            if (j <= i)
+                continue;  // the pair belongs to the lower residue's row
+            Acc d;
+            add_repulsive_d(d, pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]), k, ENERGY);
+            own.fx += d.fx;
+            own.fy += d.fy;
+            own.fz += d.fz;
+            atomicAdd(&acc_s[0][sl], -d.fx);
+            atomicAdd(&acc_s[1][sl], -d.fy);
+            atomicAdd(&acc_s[2][sl], -d.fz);
+            if (ENERGY) {
+                const double he = 0.5 * d.e_r, hv = 0.5 * d.vir;
+                own.e_r += he;
+                own.vir += hv;
+                unsafeAtomicAdd(&a.eacc[j].z, he);
+                unsafeAtomicAdd(&a.eacc[j].w, hv);
+            }
+        }
+        const int2 rw = a.trow[i];
+        const int nb = rw.y & 4095, ntop = nb + (rw.y >> 12);
+        bool broken = false;
+        for (int e = q; e < ntop; e += NL) {
+            const float2 te = a.tent[rw.x + e];
+            const int j = __float_as_int(te.x);
+            if (j <= i)
+                continue;
+            Acc d;
+            const float3 dd = pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]);
+            if (e < nb)
+                add_fene_d(d, dd, te.y, k, ENERGY, broken);
+            else
+                add_native_d(d, dd, te.y, k, ENERGY);
+            own.fx += d.fx;
+            own.fy += d.fy;
+            own.fz += d.fz;
+            unsafeAtomicAdd(&a.facc[j].x, -d.fx);
+            unsafeAtomicAdd(&a.facc[j].y, -d.fy);
+            unsafeAtomicAdd(&a.facc[j].z, -d.fz);
+            if (ENERGY) {
+                const double hb = 0.5 * d.e_b, hn = 0.5 * d.e_n, hv = 0.5 * d.vir;
+                own.e_b += hb;
+                own.e_n += hn;
+                own.vir += hv;
+                unsafeAtomicAdd(&a.eacc[j].x, hb);
+                unsafeAtomicAdd(&a.eacc[j].y, hn);
+                unsafeAtomicAdd(&a.eacc[j].w, hv);
+            }
+        }
+        if (broken)
+            atomicOr(a.err, ERR_FENE);
     }
-    const int2 rw = a.trow[i];
-    const int nb = rw.y & 4095, ntop = nb + (rw.y >> 12);
-    bool broken = false;
-    for (int e = q; e < ntop; e += NL) {
-        const float2 te = a.tent[rw.x + e];
-        const int j = __float_as_int(te.x);
-        if (j <= i)
-            continue;
-        Acc d;
-        const float3 dd = pair_delta(hi, lo, a.pin[2 * j], a.pin[2 * j + 1]);
-        if (e < nb)
-            add_fene_d(d, dd, te.y, k, ENERGY, broken);
-        else
-            add_native_d(d, dd, te.y, k, ENERGY);
-        pair_scatter(a.facc, a.eacc, i, j, d, ENERGY);
+    // residue i: its NL lanes' shares, then one atomic per component
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1) {
+        own.fx += __shfl_xor(own.fx, off, NL);
+        own.fy += __shfl_xor(own.fy, off, NL);
+        own.fz += __shfl_xor(own.fz, off, NL);
+        if (ENERGY) {
+            own.e_b += __shfl_xor(own.e_b, off, NL);
+            own.e_n += __shfl_xor(own.e_n, off, NL);
+            own.e_r += __shfl_xor(own.e_r, off, NL);
+            own.vir += __shfl_xor(own.vir, off, NL);
+        }
     }
-    if (broken)
-        atomicOr(a.err, ERR_FENE);
+    if (act && q == 0) {
+        unsafeAtomicAdd(&a.facc[i].x, own.fx);
+        unsafeAtomicAdd(&a.facc[i].y, own.fy);
+        unsafeAtomicAdd(&a.facc[i].z, own.fz);
+        if (ENERGY) {
+            unsafeAtomicAdd(&a.eacc[i].x, own.e_b);
+            unsafeAtomicAdd(&a.eacc[i].y, own.e_n);
+            unsafeAtomicAdd(&a.eacc[i].z, own.e_r);
+            unsafeAtomicAdd(&a.eacc[i].w, own.vir);
+        }
+    }
+    __syncthreads();
+    // the slots' shares
+    for (int sl = t; sl < S; sl += 256) {
+        const float fx = acc_s[0][sl], fy = acc_s[1][sl], fz = acc_s[2][sl];
+        if (fx != 0.0f || fy != 0.0f || fz != 0.0f) {
+            const int j = st[sl];
+            unsafeAtomicAdd(&a.facc[j].x, fx);
+            unsafeAtomicAdd(&a.facc[j].y, fy);
+            unsafeAtomicAdd(&a.facc[j].z, fz);
+        }
+    }
 }
 
 struct PairUpdArgs {
@@ -1533,10 +1763,18 @@ struct PairUpdArgs {
     const long long *step_base;
     const float4 *hi_skin;
     unsigned *skin_flag;
+    float4 *vel;
+    const int4 *traj_cell;
+    int *cell_count;
+    float4 *cells;
+    int *cell_of;
+    GridDev g;
+    int do_bin;
     long long step_off;
     float check_thr2;
     int n, has_pull;
     StepConsts c;
+    UdConsts ud;
     TipDev tip;
 };
 
@@ -1584,7 +1822,13 @@ __global__ __launch_bounds__(256) void k_pair_update(PairUpdArgs a)
         g[2] = gaussian_axis(w, 2);
     }
     float4 hi = hi0, lo = lo0;
-    update_with_noise(hi, lo, F, g, a.c, a.err);
+    if (a.vel) {
+        float4 v = a.vel[i];
+        underdamped_update(hi, lo, v, F, g, a.ud, a.err);
+        a.vel[i] = v;
+    } else {
+        update_with_noise(hi, lo, F, g, a.c, a.err);
+    }
     a.pout[2 * i] = hi;
     a.pout[2 * i + 1] = lo;
     if (a.check_thr2 > 0.0f) {
@@ -1593,6 +1837,8 @@ __global__ __launch_bounds__(256) void k_pair_update(PairUpdArgs a)
         if (!(dx * dx + dy * dy + dz * dz <= a.check_thr2))
             atomicOr(a.skin_flag, 1u);
     }
+    if (a.do_bin)
+        bin_one(hi, i, __float_as_int(lo.w), a.g, a.traj_cell, a.cell_count, a.cells, a.cell_of, a.err);
 }
 
 // ---------------------------------------------------------------------------
@@ -1619,6 +1865,7 @@ struct BatchArgs {
     float4 *fout;
     unsigned *err;
     const long long *step_base;
+    const float *tscale;      // per trajectory: noise amplitude factor (replica exchange), or NULL
     long long step_off;
     long long energy_every;
     int n_steps, list_every, stale, cap, has_pull;
@@ -1719,6 +1966,10 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     const long long s0 = (a.step_base ? *a.step_base : 0) + a.step_off;
     const PairConsts kc = pair_consts(a.c);
     const int traj = __float_as_int(lo.w);
+    // this trajectory's temperature (fixed within a launch)
+    StepConsts cn = a.c;
+    if (a.tscale && act)
+        cn.c_noise *= a.tscale[traj];
     const unsigned stream = act ? a.stream_ids[traj] : 0u;
 
     // lane -> row assignment: counting sort of the rows by chunk count,
@@ -1975,7 +2226,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             return;
         }
         if (act) {
-            langevin_update(hi, lo, A, step, stream, a.c, a.err);
+            langevin_update(hi, lo, A, step, stream, cn, a.err);
             shh[t] = hi;
             shl[t] = lo;
         }
@@ -1984,6 +2235,50 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
     if (MODE == 0 && act) {
         a.pout[2 * i] = hi;
         a.pout[2 * i + 1] = lo;
+    }
+}
+
+// Replica exchange: one lane per attempted swap of round `round` (the
+// temperatures k, k+1 with k = round mod 2, round mod 2 + 2, ... of every
+// group of n_rep consecutive trajectories), Metropolis on the potential
+// energies recorded at this step, with a Philox draw under a key of its
+// own.  Swaps of one round touch disjoint trajectories.
+__global__ void k_exchange(const double *__restrict__ energy, const double *__restrict__ kbt, int n_rep,
+                           int n_groups, int *__restrict__ tidx, float *__restrict__ tscale, double kbt_ref,
+                           long long round, unsigned key0, unsigned key1, unsigned long long *__restrict__ stats)
+{
+    const int par = (int)(round & 1);
+    const int pairs = (n_rep - par) / 2;  // k = par, par + 2, ... with k + 1 < n_rep
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pairs <= 0 || id >= n_groups * pairs)
+        return;
+    const int g = id / pairs, k = par + 2 * (id % pairs);
+    const int base = g * n_rep;
+    int ta = -1, tb = -1;
+    for (int m = 0; m < n_rep; ++m) {
+        const int v = tidx[base + m];
+        ta = v == k ? base + m : ta;
+        tb = v == k + 1 ? base + m : tb;
+    }
+    if (ta < 0 || tb < 0)
+        return;  // not a permutation (rejected on the host)
+    double Ea = 0.0, Eb = 0.0;
+    for (int term = 0; term < 4; ++term) {
+        Ea += energy[(size_t)ta * SOP_NTERMS + term];
+        Eb += energy[(size_t)tb * SOP_NTERMS + term];
+    }
+    const double d = (1.0 / kbt[k] - 1.0 / kbt[k + 1]) * (Ea - Eb);
+    const uint4 w = philox10(make_uint4((unsigned)g, (unsigned)k, (unsigned)round,
+                                        (unsigned)((unsigned long long)round >> 32)),
+                             key0 ^ 0x52455843u, key1);
+    const double u = ((double)(w.x >> 9) + 0.5) * 0x1p-23;
+    atomicAdd(&stats[2 * k + 1], 1ull);
+    if (d >= 0.0 || u < exp(d)) {
+        atomicAdd(&stats[2 * k], 1ull);
+        tidx[ta] = k + 1;
+        tidx[tb] = k;
+        tscale[ta] = (float)sqrt(kbt[k + 1] / kbt_ref);
+        tscale[tb] = (float)sqrt(kbt[k] / kbt_ref);
     }
 }
 
@@ -2099,9 +2394,13 @@ void canon_tile(const DevBufs &b, int cap, hipStream_t s)
 }
 
 template <int TILE>
-void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2, hipStream_t s)
+void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2, hipStream_t s,
+                 bool advance, int period)
 {
     FilterArgs a{};
+    a.step_base = advance ? b.step_base : nullptr;
+    a.step_next = b.step_next;
+    a.period = period;
     a.tile_first = b.tile_first[tile_index(TILE)];
     a.pos = b.pos[cur];
     a.stage = b.stage;
@@ -2142,6 +2441,8 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
     a.stage_cnt = b.stage_cnt;
     a.err = b.err;
     a.skin_flag = b.skin_flag;
+    a.hi_skin = b.hi_skin;
+    a.stats = b.list_stats;
     a.g = g;
     a.rc2 = rc2;
     a.n = n;
@@ -2174,30 +2475,34 @@ void tile_dispatch(int tile, const TileArgs &a, hipStream_t s)
 }  // namespace
 
 void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int tile, const GridDev &g, float rc2,
-                    float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every)
+                    float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every, bool binned)
 {
-    // the cell counts are zero here: cleared at binding and by every filter
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, WG)), dim3(WG), 0, s, b.pos[cur], n, g, b.traj_cell,
-                       b.cell_count, b.cells, b.cell_of, b.err,
-                       advance_step_base ? b.step_base : nullptr, b.step_next, list_every,
-                       b.skin_flag, b.hi_skin, b.list_stats);
+    if (!binned)
+        launch_bin_all(b, cur, n, g, s);  // not binned by a period's last step kernel
     switch (tile) {
     case 64:
         rebuild_tile<64>(b, cur, n, cap, g, rs2, multi, s);
         canon_tile<64>(b, cap, s);
-        filter_tile<64>(b, cur, cap, g, rc2, s);
+        filter_tile<64>(b, cur, cap, g, rc2, s, advance_step_base, list_every);
         break;
     case 128:
         rebuild_tile<128>(b, cur, n, cap, g, rs2, multi, s);
         canon_tile<128>(b, cap, s);
-        filter_tile<128>(b, cur, cap, g, rc2, s);
+        filter_tile<128>(b, cur, cap, g, rc2, s, advance_step_base, list_every);
         break;
     default:
         rebuild_tile<256>(b, cur, n, cap, g, rs2, multi, s);
         canon_tile<256>(b, cap, s);
-        filter_tile<256>(b, cur, cap, g, rc2, s);
+        filter_tile<256>(b, cur, cap, g, rc2, s, advance_step_base, list_every);
         break;
     }
+}
+
+void launch_bin_all(const DevBufs &b, int cur, int n, const GridDev &g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear, dim3(blocks_for(g.n_cells, WG)), dim3(WG), 0, s, b.cell_count, g.n_cells);
+    hipLaunchKernelGGL(k_bin_all, dim3(blocks_for(n, WG)), dim3(WG), 0, s, b.pos[cur], n, g, b.traj_cell,
+                       b.cell_count, b.cells, b.cell_of, b.err);
 }
 
 void launch_force_skin(const DevBufs &b, hipStream_t s)
@@ -2216,7 +2521,8 @@ void pair_forces(const PairArgs &a, bool energy, hipStream_t s)
 
 void launch_pair_step(const DevBufs &b, int cur, int n, int cap, int tile, const StepConsts &c,
                       const TipDev &tip, int has_pull, bool energy, int mode, const long long *step_base,
-                      long long step_off, float check_thr2, hipStream_t s)
+                      long long step_off, float check_thr2, hipStream_t s, const float4 *vel,
+                      const UdConsts &ud, const GridDev *bin_grid)
 {
     PairArgs a{};
     a.tile_first = b.tile_first[tile_index(tile)];
@@ -2227,6 +2533,7 @@ void launch_pair_step(const DevBufs &b, int cur, int n, int cap, int tile, const
     a.list16 = b.flist16;
     a.list_cnt = b.fcnt;
     a.stage = b.stage;
+    a.stage_cnt = b.stage_cnt;
     a.facc = b.facc;
     a.eacc = b.eacc;
     a.err = b.err;
@@ -2253,6 +2560,15 @@ void launch_pair_step(const DevBufs &b, int cur, int n, int cap, int tile, const
     u.skin_flag = b.skin_flag;
     u.step_off = step_off;
     u.check_thr2 = mode == 0 ? check_thr2 : 0.0f;
+    u.vel = const_cast<float4 *>(vel);
+    u.ud = ud;
+    u.do_bin = (mode == 0 && bin_grid) ? 1 : 0;
+    if (bin_grid)
+        u.g = *bin_grid;
+    u.traj_cell = b.traj_cell;
+    u.cell_count = b.cell_count;
+    u.cells = b.cells;
+    u.cell_of = b.cell_of;
     u.n = n;
     u.has_pull = has_pull;
     u.c = c;
@@ -2273,14 +2589,27 @@ void launch_pair_step(const DevBufs &b, int cur, int n, int cap, int tile, const
 
 void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode, const long long *step_base,
-                 long long step_off, float check_thr2, hipStream_t s, int force_mode)
+                 long long step_off, float check_thr2, hipStream_t s, int force_mode, float ud_kick,
+                 const GridDev *bin_grid)
 {
+    // underdamped when ud_kick > 0 (velocities in b.vel)
+    const float4 *vel = ud_kick > 0.0f ? b.vel : nullptr;
+    UdConsts ud{ud_kick, c.ud_c1, c.ud_c2, (float)(0.5 * c.h)};
     if (force_mode == 1) {
         launch_pair_step(b, cur, n, cap, tile, c, tip, has_pull, energy, mode, step_base, step_off,
-                         check_thr2, s);
+                         check_thr2, s, vel, ud, bin_grid);
         return;
     }
     TileArgs a{};
+    a.vel = const_cast<float4 *>(vel);
+    a.ud = ud;
+    a.do_bin = (mode == 0 && bin_grid) ? 1 : 0;
+    if (bin_grid)
+        a.g = *bin_grid;
+    a.traj_cell = b.traj_cell;
+    a.cell_count = b.cell_count;
+    a.cells = b.cells;
+    a.cell_of = b.cell_of;
     a.tile_ord = b.tile_ord;
     a.hi_skin = b.hi_skin;
     a.skin_flag = b.skin_flag;
@@ -2326,7 +2655,7 @@ void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const Step
 void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const StepConsts &c,
                   const TipDev &tip, int has_pull, float rc2, int list_every, long long energy_every,
                   int n_steps, int stale, int mode, const long long *step_base, long long step_off,
-                  hipStream_t s)
+                  hipStream_t s, const float *tscale)
 {
     BatchArgs a{};
     a.pin = b.pos[cur];
@@ -2357,6 +2686,7 @@ void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const
     a.c = c;
     a.tip = tip;
     a.rc2 = rc2;
+    a.tscale = tscale;
     const dim3 grid(n_packs);
     if (mode == 1) {
         switch (wg) {
@@ -2371,6 +2701,14 @@ void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const
         default: hipLaunchKernelGGL((k_batch<1024, 0>), grid, dim3(1024), 0, s, a); break;
         }
     }
+}
+
+void launch_exchange(const DevBufs &b, int n_rep, int n_groups, double kbt_ref, long long round,
+                     unsigned key0, unsigned key1, hipStream_t s)
+{
+    const int pairs = std::max(n_rep / 2, 1);
+    hipLaunchKernelGGL(k_exchange, dim3(blocks_for((long long)n_groups * pairs, WG)), dim3(WG), 0, s, b.energy,
+                       b.re_kbt, n_rep, n_groups, b.re_tidx, b.re_tscale, kbt_ref, round, key0, key1, b.re_stats);
 }
 
 void launch_add_step(long long *base, long long k, hipStream_t s)

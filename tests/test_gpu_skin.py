@@ -82,12 +82,16 @@ def test_skin_does_not_change_the_dynamics(P, c1):
     b.close()
 
 
-def test_graph_and_direct_paths_search_alike(P, c1):
+@pytest.mark.parametrize("skin", [0.0, 4.0])
+def test_graph_and_direct_paths_search_alike(P, c1, skin):
     """Graph replays rely on the displacement check of each period's last
-    step; step-by-step launches do the same check: bit-identical results."""
+    step (or, without a skin, search at every captured rebuild); step-by-step
+    launches do the same: bit-identical results."""
     p = RunParams()
     a = P.from_system(c1, p, graph_steps=3)
     b = P.from_system(c1, p, graph_steps=0)
+    a.set_list_skin(skin)
+    b.set_list_skin(skin)
     for n in (30, 7, 23, 60, 5, 125):
         a.step(n)
         b.step(n)
