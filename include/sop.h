@@ -78,7 +78,8 @@ typedef struct sop_params {
     double zeta;           /* friction coefficient (xi) */
     double h;              /* time step */
     int32_t list_every;    /* rebuild period in steps (> 0) */
-    int32_t list_capacity; /* list partners per residue; 0 selects 256 */
+    int32_t list_capacity; /* list partners per residue, at most 1024 (else SOP_E_ARG);
+                            0 selects 1024 (plain schedule) or 256 (batched) */
     uint64_t seed;         /* Philox key (low word, high word) */
 } sop_params;
 

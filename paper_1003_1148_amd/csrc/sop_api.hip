@@ -51,6 +51,7 @@ struct sop_ctx {
     long long re_every = 0, re_last = -1;
     bool ud_half = true;             // underdamped: the stored velocities are at the current step
     long long skin_checked = -1;     // step at which the skin was last known valid
+    long long binned_at = -1;        // step whose positions the cells hold (consumed by a rebuild)
     std::vector<double> xyz_set;     // the coordinates the grid was laid out for
     int graph_steps = 1;
     long long energy_every = 0;
@@ -118,7 +119,7 @@ const char *bits_message(unsigned bits)
     if (bits & ERR_OVERFLOW)
         return "a residue has more list partners than the list capacity";
     if (bits & ERR_CELL)
-        return "more than 128 residues fell into one cell of the list-rebuild grid";
+        return "more than 256 residues fell into one cell of the list-rebuild grid";
     if (bits & ERR_STAGE)
         return "a tile of the plain schedule interacts with more residues than its LDS staging holds, or its cell neighbourhood exceeds the rebuild's LDS table";
     if (bits & ERR_FENE)
@@ -132,12 +133,13 @@ const char *bits_message(unsigned bits)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Row capacity: the requested one, else 512 entries for the plain schedule
-// (its skin rows hold the partners within r_list + skin) and 256 for the
+// Row capacity: the requested one, else 1024 entries for the plain schedule
+// (its skin rows hold the partners within r_list + skin: at protein density,
+// about 120 A^3 per residue, up to some 500 within 24 A) and 256 for the
 // batched one; a multiple of 16.
 int list_cap(const sop_ctx *c)
 {
-    const int cap = c->cap_req ? c->cap_req : (c->schedule == SOP_SCHEDULE_PLAIN ? 512 : 256);
+    const int cap = c->cap_req ? c->cap_req : (c->schedule == SOP_SCHEDULE_PLAIN ? 1024 : 256);
     return ((cap + 15) / 16) * 16;
 }
 
@@ -457,12 +459,15 @@ sop_status need_ready(sop_ctx *c)
 void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false)
 {
     // in cadence: the step before was a period's last step, which binned its
-    // positions and checked their displacements
-    const bool in_cadence = captured || c->skin_checked == c->step;
-    if (skin_check_thr2(c) <= 0.0f || !in_cadence)
+    // positions and checked their displacements (a rebuild consumes the bins)
+    const bool checked = captured || c->skin_checked == c->step;
+    const bool binned = captured || c->binned_at == c->step;
+    if (skin_check_thr2(c) <= 0.0f || !checked)
         launch_force_skin(c->b, s);
     launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), skin_rs2(c),
-                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every, in_cadence);
+                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every, binned);
+    if (!captured)
+        c->binned_at = -1;
 }
 
 // Whether step `step` is the last of a list period: its kernel checks the
@@ -594,7 +599,7 @@ sop_status sop_create(const sop_params *params, void *hip_stream, sop_ctx **out)
     const sop_params &p = *params;
     const bool ok = p.k_fene > 0 && p.R0 > 0 && p.eps_h >= 0 && p.eps_l >= 0 && p.sigma > 0 &&
                     p.r_list > 0 && p.kBT >= 0 && p.zeta > 0 && p.h > 0 && p.list_every > 0 &&
-                    p.list_capacity >= 0 && std::isfinite(p.r_list) && std::isfinite(p.h);
+                    p.list_capacity >= 0 && p.list_capacity <= 1024 && std::isfinite(p.r_list) && std::isfinite(p.h);
     if (!ok)
         return SOP_E_ARG;
     sop_ctx *c = new (std::nothrow) sop_ctx();
@@ -851,7 +856,7 @@ sop_status sop_set_tile(sop_ctx *c, int32_t tile)
         if (nt != c->tile) {
             c->tile = nt;
             c->list_valid = false;  // the list layout follows the tile size
-            c->skin_checked = -1;
+            c->skin_checked = c->binned_at = -1;
             destroy_graphs(c);
         }
     }
@@ -1089,7 +1094,7 @@ sop_status sop_set_list_skin(sop_ctx *c, double skin)
         return SOP_OK;
     c->skin = skin;
     c->list_valid = false;
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     destroy_graphs(c);  // the radius, the cell grid and the check are kernel arguments
     if (c->coords)
         set_grid(c, c->xyz_set.data());  // the cell edge follows the skin radius
@@ -1231,7 +1236,7 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
     HIP_TRY(c, hipMemsetAsync(b.skin_flag, 0, sizeof(unsigned), s));
     HIP_TRY(c, hipMemsetAsync(b.list_stats, 0, 2 * sizeof(unsigned long long), s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     c->bound = true;
     c->sticky = 0;
     c->energy_step = -1;
@@ -1280,7 +1285,7 @@ sop_status sop_set_coordinates(sop_ctx *c, const double *xyz)
     c->sticky = 0;
     c->coords = true;
     c->list_valid = false;
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     c->last_error.clear();
     return SOP_OK;
 }
@@ -1310,7 +1315,7 @@ sop_status sop_set_step(sop_ctx *c, int64_t step)
         return SOP_E_ARG;
     c->step = step;
     c->list_valid = false;
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     return SOP_OK;
 }
 
@@ -1525,17 +1530,18 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
                 launch_set_step(c->b.step_next, c->step, c->stream);
                 base_set = true;
             }
-            if (c->skin_checked != c->step) {
-                // the graph's first rebuild searches, from freshly binned positions
+            // the graph's first rebuild relies on the cells holding the
+            // current positions and on the displacement check
+            if (c->binned_at != c->step)
                 launch_bin_all(c->b, c->cur, (int)c->n_res, c->grid, c->stream);
+            if (c->skin_checked != c->step)
                 launch_force_skin(c->b, c->stream);
-            }
             HIP_TRY(c, hipGraphLaunch(c->graphs[c->cur][en], c->stream));
             if (en)
                 c->energy_step = c->step;
             c->list_valid = true;
             c->step += span;
-            c->skin_checked = c->step;
+            c->skin_checked = c->binned_at = c->step;
             if (span & 1)
                 c->cur ^= 1;
             q += span;
@@ -1554,7 +1560,7 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
         c->cur ^= 1;
         ++c->step;
         if (chk)
-            c->skin_checked = c->step;
+            c->skin_checked = c->binned_at = c->step;
         ++q;
         base_set = false;
     }
@@ -1658,7 +1664,7 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
             } else {
                 // kind 1: a search from freshly binned positions; kind 2:
                 // the filter alone (the skin stays valid)
-                c->skin_checked = -1;
+                c->skin_checked = c->binned_at = -1;
                 rebuild(c, c->cap_stream, false, kind == 2);
             }
         }
@@ -1694,11 +1700,11 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
         // back to the saved positions; the next list is built from them
         HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, s));
         if (kind == 0) {
-            c->skin_checked = -1;
+            c->skin_checked = c->binned_at = -1;
             rebuild(c, s, false);
         }
     }
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->list_valid = false;
@@ -1844,7 +1850,7 @@ sop_status trial(sop_ctx *c, long long steps, double *rate, double best = 0.0)
     HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
     const long long step0 = c->step;
     c->list_valid = false;
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
@@ -1876,7 +1882,7 @@ sop_status trial(sop_ctx *c, long long steps, double *rate, double best = 0.0)
     HIP_TRY(c, hipMemcpyAsync(c->b.pos[c->cur], c->b.pos_save, bytes, hipMemcpyDeviceToDevice, c->stream));
     c->step = step0;
     c->list_valid = false;
-    c->skin_checked = -1;
+    c->skin_checked = c->binned_at = -1;
     return st;
 }
 

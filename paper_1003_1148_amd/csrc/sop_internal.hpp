@@ -54,12 +54,15 @@ struct GridDev {
 };
 
 // Residues per cell of the list-rebuild grid (fixed capacity; more is the
-// list-overflow error).
-constexpr int CELL_CAP = 128;
+// list-overflow error).  A cell's edge is the search radius, 24 A by
+// default: at protein density (about 120 A^3 per residue) a cell holds some
+// 115 residues on average, so the capacity leaves room for twice that.
+constexpr int CELL_CAP = 256;
 // Bonded plus native partners per residue (larger is rejected at load).
 constexpr int TOPO_CAP = 64;
-// Largest staging set of a tile of the plain schedule (its LDS footprint).
-constexpr int STAGE_MAX = 2048;
+// Largest staging set of a tile of the plain schedule (slots are 16-bit;
+// the kernels hold 1,024 or 2,048 of them in LDS at once).
+constexpr int STAGE_MAX = 4096;
 
 // Device buffers carved out of the caller's workspace.
 struct DevBufs {
@@ -171,7 +174,7 @@ void launch_noise(const DevBufs &b, int cur, int n, const StepConsts &c, long lo
 // Plain schedule: entry k of residue r's row (a slot of its tile), and the
 // slots a tile of `tile` residues can stage.
 inline size_t list16_index_host(long long r, int k, int cap) { return (size_t)r * cap + (size_t)k; }
-inline int stage_max_host(int tile) { return tile >= 256 ? 2048 : 1024; }
+inline int stage_max_host(int) { return 4096; }
 inline int tile_index(int tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : 2); }
 
 }  // namespace sop

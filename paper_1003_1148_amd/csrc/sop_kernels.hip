@@ -384,7 +384,13 @@ __device__ __forceinline__ void langevin_update(float4 &hi, float4 &lo, const Ac
 // rows are rewritten as 16-bit slots into that set.
 // ---------------------------------------------------------------------------
 template <int TILE>
-constexpr int stage_max() { return TILE >= 256 ? 2048 : 1024; }
+constexpr int stage_max() { return 4096; }
+// Slots held in LDS at once by the kernels that read the staging set; a
+// tile with more slots is taken in windows of this many.
+template <int TILE>
+constexpr int stage_win() { return TILE >= 256 ? 2048 : 1024; }
+// Row padding (and the slot of a bonded/native entry of a failed tile).
+constexpr unsigned short EMPTY_SLOT = 0xffffu;
 
 // Candidate residues (the residues of the cells around a tile) held in LDS
 // at once during a rebuild; more are taken in windows of whole cells.  Small
@@ -605,7 +611,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
         if (lead) {
             a.list_cnt[i] = 0;
             for (int e = 0; e < ntop; ++e)
-                trw[(size_t)e * TILE] = make_uint2((unsigned)SM, __float_as_uint(1.0f));
+                trw[(size_t)e * TILE] = make_uint2((unsigned)EMPTY_SLOT, __float_as_uint(1.0f));
         }
     };
     if (bad_cells) {
@@ -945,11 +951,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
         return;
     for (int e = TREG; e < ntop; ++e)
         trw[(size_t)e * TILE].x = final_slot(trw[(size_t)e * TILE].x);
-    // count; the last chunk padded with the empty slot SM (far away: its
-    // term is exactly 0)
+    // count; the last chunk padded with the empty slot
     const int cnt = rowbase[rho];
     for (int k = cnt; k < ((cnt + 3) & ~3); ++k)
-        row_store(k, (unsigned short)SM);
+        row_store(k, EMPTY_SLOT);
     a.list_cnt[i] = cnt;
     if (cnt > a.cap)
         atomicOr(a.err, ERR_OVERFLOW);
@@ -988,10 +993,14 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
 {
     constexpr int NL = 256 / TILE;  // lanes per residue, adjacent in the wave
     constexpr int SM = stage_max<TILE>();
-    constexpr int OUTW = 16384 / TILE;  // filtered entries of a residue gathered in LDS (32 KB in all)
-    __shared__ float4 hs[SM];
+    constexpr int SW = stage_win<TILE>();
+    constexpr int OUTW = 12288 / TILE;  // filtered entries of a residue gathered in LDS (24 KB in all)
+    constexpr int PF = 8;               // row pieces per lane loaded up front
+    constexpr int MAXP = 128;           // pieces of 8 entries in a row (cap <= 1024)
+    __shared__ float4 hs[SW];
     __shared__ int lens[TILE];
     __shared__ __align__(16) unsigned short out_s[TILE * OUTW];
+    __shared__ unsigned char pbits[TILE * MAXP];  // passing entries of each piece
     const int tile = blockIdx.x, t = threadIdx.x;
     const int rho = t / NL, q = t % NL;
     // the cell counts are read only by the skin build, which is done: clear
@@ -1009,57 +1018,62 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
         }
     }
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
-    const int S = a.stage_cnt[tile];
+    const int S = min(a.stage_cnt[tile], SM);
     const int *st = a.stage + (size_t)tile * SM;
-    for (int sl = t; sl < S; sl += 256)
-        hs[sl] = a.pos[2 * st[sl]];
-    __syncthreads();
     const bool act = rho < tcnt;
     const int i = first + (act ? rho : 0);
-    const float4 pi = a.pos[2 * i];
     const int len = act ? min(a.skin_cnt[i], a.cap) : 0;
     // the row in 16-byte pieces of 8 entries, piece m NL + q to lane q, so
-    // a residue's lanes read 16 NL contiguous bytes per round
+    // a residue's lanes read 16 NL contiguous bytes per round; the first PF
+    // pieces of this lane are loaded before the staging
     const uint4 *src = reinterpret_cast<const uint4 *>(a.skin16 + (size_t)i * a.cap);
-    unsigned short *dst = a.list16 + (size_t)i * a.cap;
-    // rows that fit are gathered in LDS and written out in 16-byte pieces
-    const bool in_lds = len <= OUTW - 8;
-    unsigned short *ob = in_lds ? out_s + rho * OUTW : dst;
     const int npc = (len + 7) >> 3;
-    int rounds = (npc + NL - 1) / NL;
-#pragma unroll
-    for (int off = 1; off < NL; off <<= 1)
-        rounds = max(rounds, __shfl_xor(rounds, off, NL));  // uniform over the residue's lanes
-    // the first PF pieces of this lane are loaded up front, so their
-    // latencies overlap
-    constexpr int PF = 8;
     uint4 pre[PF];
 #pragma unroll
     for (int m = 0; m < PF; ++m)
         pre[m] = m * NL + q < npc ? src[m * NL + q] : make_uint4(0u, 0u, 0u, 0u);
-    int base = 0;
-    for (int m = 0; m < rounds; ++m) {
-        const int pc = m * NL + q;
-        unsigned e[8];
-        unsigned bits = 0u;
-        if (pc < npc) {
-            uint4 w;
-            if (m < PF) {
-#pragma unroll
-                for (int mm = 0; mm < PF; ++mm)
-                    if (mm == m)
-                        w = pre[mm];
-            } else {
-                w = src[pc];
-            }
+    const float4 pi = a.pos[2 * i];
+    unsigned char *pb = pbits + rho * MAXP;
+    // the predicate, window by window of the staging set (one window for
+    // nearly every tile): each entry is tested in the window holding its slot
+    for (int w0 = 0; w0 < S || w0 == 0; w0 += SW) {
+        const int wn = min(SW, S - w0);
+        if (w0 > 0)
+            __syncthreads();  // the previous window's readers are done
+        for (int sl = t; sl < wn; sl += 256)
+            hs[sl] = a.pos[2 * st[w0 + sl]];
+        __syncthreads();
+        auto test = [&](const uint4 &w, int pc) {
             const unsigned ws[4] = {w.x, w.y, w.z, w.w};
+            unsigned bits = w0 == 0 ? 0u : pb[pc];
+            const int valid = min(8, max(0, len - pc * 8));
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                e[u] = (ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
-                if (pc * 8 + u < len && within_cutoff(pi, hs[e[u]], a.rc2))
+                const int e = (int)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu) - w0;
+                if (u < valid && (unsigned)e < (unsigned)wn && within_cutoff(pi, hs[e], a.rc2))
                     bits |= 1u << u;
             }
-        }
+            pb[pc] = (unsigned char)bits;
+        };
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+            if (m * NL + q < npc)
+                test(pre[m], m * NL + q);
+        for (int pc = PF * NL + q; pc < npc; pc += NL)
+            test(src[pc], pc);
+    }
+    unsigned short *dst = a.list16 + (size_t)i * a.cap;
+    // rows that fit are gathered in LDS and written out in 16-byte pieces
+    const bool in_lds = len <= OUTW - 8;
+    unsigned short *ob = in_lds ? out_s + rho * OUTW : dst;
+    int rounds = (npc + NL - 1) / NL;
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1)
+        rounds = max(rounds, __shfl_xor(rounds, off, NL));  // uniform over the residue's lanes
+    int base = 0;
+    auto emit = [&](const uint4 &w, int pc) {
+        const unsigned ws[4] = {w.x, w.y, w.z, w.w};
+        unsigned bits = pc < npc ? pb[pc] : 0u;
         const int c = __popc(bits);
         // passing entries before this lane's piece: scan over the residue's lanes
         int v = c;
@@ -1073,14 +1087,22 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
         while (bits) {
             const int u = __ffs(bits) - 1;
             bits &= bits - 1u;
-            ob[o++] = (unsigned short)e[u];
+            ob[o++] = (unsigned short)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
         }
         base += __shfl(v, NL - 1, NL);
-    }
+    };
+#pragma unroll
+    for (int m = 0; m < PF; ++m)
+        if (m < rounds)
+            emit(pre[m], m * NL + q);
+    for (int m = PF; m < rounds; ++m)
+        emit(m * NL + q < npc ? src[m * NL + q] : make_uint4(0u, 0u, 0u, 0u), m * NL + q);
     if (act && q == NL - 1) {
-        // pad the row to a multiple of 8 entries with the empty slot SM
+        // pad the row to a multiple of 8 entries: with the LDS slot of the
+        // far-away position when the tile fits one window, else the empty slot
+        const unsigned short pad = S <= SW ? (unsigned short)SW : EMPTY_SLOT;
         for (int k = base; k < ((base + 7) & ~7); ++k)
-            ob[k] = (unsigned short)SM;
+            ob[k] = pad;
         a.list_cnt[i] = base;
         lens[rho] = base;
     }
@@ -1092,13 +1114,17 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
             dp[pc] = sp[pc];
     }
     // the step kernel hands the rows to its waves longest first, so that the
-    // rows a wave sums have about the same length (ties in index order)
-    if (act && q == 0) {
-        int r = 0;
-        for (int u = 0; u < tcnt; ++u)
+    // rows a wave sums have about the same length (ties in index order):
+    // the residue's rank, counted by its NL lanes over a share of the tile
+    int r = 0;
+    if (act)
+        for (int u = q * (TILE / NL); u < min(tcnt, (q + 1) * (TILE / NL)); ++u)
             r += (lens[u] > base || (lens[u] == base && u < rho)) ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1)
+        r += __shfl_xor(r, off, NL);
+    if (act && q == 0)
         a.tile_ord[(size_t)tile * TILE + r] = (unsigned char)rho;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,25 +1154,67 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
     constexpr int G = 64;           // residues per pass
     constexpr int NLG = 256 / G;    // lanes per residue in a pass
     constexpr int MW = SM / 32;     // mask words per residue
+    constexpr int BW = 2048;        // bitmap words: ids spanning up to 65,536 values
     __shared__ int sid[SM];
     __shared__ unsigned short nslot[SM];
     __shared__ unsigned mask[G * MW];
+    __shared__ unsigned bmp[BW];
+    __shared__ int wpre[BW];
+    __shared__ int part[256];
+    __shared__ int id_lo, id_hi;
     if (*a.skin_flag == 0u)
         return;  // no search ran (uniform over the grid)
     const int tile = blockIdx.x, t = threadIdx.x;
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
     const int S = min(a.stage_cnt[tile], SM);
     int *st = a.stage + (size_t)tile * SM;
-    for (int k = t; k < S; k += 256)
-        sid[k] = st[k];
+    if (t == 0) {
+        id_lo = 0x7fffffff;
+        id_hi = -1;
+    }
     __syncthreads();
-    // new slot = rank of the residue id among the tile's slots (ids distinct)
     for (int k = t; k < S; k += 256) {
-        const int id = sid[k];
-        int r = 0;
-        for (int m = 0; m < S; ++m)
-            r += sid[m] < id ? 1 : 0;
-        nslot[k] = (unsigned short)r;
+        const int id = st[k];
+        sid[k] = id;
+        atomicMin(&id_lo, id);
+        atomicMax(&id_hi, id);
+    }
+    __syncthreads();
+    // new slot = rank of the residue id among the tile's slots (ids distinct):
+    // from a bitmap of the ids when they span few enough values, else by
+    // counting
+    const int lo = id_lo, span = id_hi - id_lo + 1;
+    if (S > 0 && span <= 32 * BW) {
+        const int nw = (span + 31) >> 5;
+        for (int w = t; w < nw; w += 256)
+            bmp[w] = 0u;
+        __syncthreads();
+        for (int k = t; k < S; k += 256)
+            atomicOr(&bmp[(sid[k] - lo) >> 5], 1u << ((sid[k] - lo) & 31));
+        __syncthreads();
+        constexpr int WPL = BW / 256;
+        int c = 0;
+        for (int w = t * WPL; w < min(nw, (t + 1) * WPL); ++w)
+            c += __popc(bmp[w]);
+        int total = 0;
+        int o = block_exclusive_scan<256>(c, part, total);
+        for (int w = t * WPL; w < min(nw, (t + 1) * WPL); ++w) {
+            wpre[w] = o;
+            o += __popc(bmp[w]);
+        }
+        __syncthreads();
+        for (int k = t; k < S; k += 256) {
+            const int v = sid[k] - lo;
+            nslot[k] = (unsigned short)(wpre[v >> 5] + __popc(bmp[v >> 5] & ((1u << (v & 31)) - 1u)));
+        }
+    } else {
+        for (int k = t; k < S; k += 256) {
+            const int id = sid[k];
+            int r = 0;
+            for (int m = 0; m < S; ++m)
+                r += sid[m] < id ? 1 : 0;
+            nslot[k] = (unsigned short)r;
+        }
     }
     __syncthreads();
     for (int k = t; k < S; k += 256)
@@ -1364,11 +1432,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
-    constexpr int PER = SM / 256;    // staging slots per lane
+    constexpr int SW = stage_win<TILE>();
+    constexpr int PER = SW / 256;    // staging slots per lane
     constexpr int EPI = 256 - TILE;  // first lane of the update lanes
     constexpr int PRE = 6;           // list chunks per lane loaded before the staging
     constexpr int TPRE = 3;          // bonded/native entries per lane loaded before the staging
-    __shared__ float4 sl_s[SM + 1];  // {rh.xyz, packed rl}; slot SM: the far-away empty slot
+    __shared__ float4 sl_s[SW + 1];  // {rh.xyz, packed rl}; slot SW: the far-away empty slot
     __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
     __shared__ double e_s[ENERGY ? 4 : 1][ENERGY ? TILE : 1];
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
@@ -1378,8 +1447,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         return;  // uniform over the workgroup
     const int t = threadIdx.x;
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
-    const int S = a.stage_cnt[tile];
+    const int S = min(a.stage_cnt[tile], SM);
     const int *st = a.stage + (size_t)tile * SM;
+    // rare: a staging set larger than one LDS window is taken window by window
+    const bool windowed = S > SW;
     const int mid = first + tcnt / 2;
     const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     const int q = t % NL;
@@ -1393,7 +1464,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     int ids[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u)
-        ids[u] = t + u * 256 < S ? st[t + u * 256] : -1;
+        ids[u] = (!windowed && t + u * 256 < S) ? st[t + u * 256] : -1;
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
     int cnt = 0;
@@ -1455,7 +1526,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         }
     }
     if (t == 0)
-        sl_s[SM] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+        sl_s[SW] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
     const PairConsts k = pair_consts(a.c);
     Acc A;   // bonded and native terms
     bool broken = false;
@@ -1485,9 +1556,9 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     }
     float4 rh0, rl0;
     tile_frame(hi0, lo0, O, rh0, rl0);
-    const bool far = act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE);
+    const bool far = windowed || (act && !(fmaxf(fabsf(rh0.x), fmaxf(fabsf(rh0.y), fabsf(rh0.z))) < NARROW_TILE));
     const bool wide = __syncthreads_or(far ? 1 : 0) != 0;
-    if (wide) {
+    if (wide && !windowed) {
         // rare: the low parts of the staged positions, packed beside them
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -1500,37 +1571,70 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         rh0.w = __uint_as_float(pack_low(rh0, rl0));
         __syncthreads();
     }
+    if (windowed)
+        rh0.w = __uint_as_float(pack_low(rh0, rl0));
     // ---- 3. list chunks of this lane ----
     Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
-    if (act) {
-        const float3 pl0 = unpack_low(rh0);
-        auto pairs4 = [&](const uint2 &w) {
-            float4 pj[4];
+    const float3 pl0 = unpack_low(rh0);
+    // slot -> LDS index of the current window (identity for one window)
+    int w0 = 0, wn = S;
+    auto pairs4 = [&](const uint2 &w) {
+        float4 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sl = (int)(((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu);
+            if (windowed) {
+                const int e = sl - w0;
+                pj[u] = sl_s[(unsigned)e < (unsigned)wn ? e : SW];
+            } else {
+                pj[u] = sl_s[sl];
+            }
+        }
+        if (!wide) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                pj[u] = sl_s[((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu];
-            if (!wide) {
+                add_repulsive_u(L, make_float3(rh0.x - pj[u].x, rh0.y - pj[u].y, rh0.z - pj[u].z), k,
+                                ENERGY);
+        } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    add_repulsive_u(L, make_float3(rh0.x - pj[u].x, rh0.y - pj[u].y, rh0.z - pj[u].z), k,
-                                    ENERGY);
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float3 lj = unpack_low(pj[u]);
-                    add_repulsive_u(L,
-                                    make_float3((rh0.x - pj[u].x) + (pl0.x - lj.x), (rh0.y - pj[u].y) + (pl0.y - lj.y),
-                                                (rh0.z - pj[u].z) + (pl0.z - lj.z)),
-                                    k, ENERGY);
-                }
+            for (int u = 0; u < 4; ++u) {
+                const float3 lj = unpack_low(pj[u]);
+                add_repulsive_u(L,
+                                make_float3((rh0.x - pj[u].x) + (pl0.x - lj.x), (rh0.y - pj[u].y) + (pl0.y - lj.y),
+                                            (rh0.z - pj[u].z) + (pl0.z - lj.z)),
+                                k, ENERGY);
             }
-        };
+        }
+    };
+    auto list_pass = [&]() {
+        if (!act)
+            return;
 #pragma unroll
         for (int kk = 0; kk < PRE; ++kk)
             if (q + kk * NL < nch)
                 pairs4(lw[kk]);
         for (int c = q + PRE * NL; c < nch; c += NL)
             pairs4(lp[c]);
+    };
+    if (!windowed) {
+        list_pass();
+    } else {
+        // every window's slots staged with their low parts; each entry
+        // contributes in the window holding its slot (elsewhere it reads the
+        // far-away slot, whose term is exactly zero)
+        for (w0 = 0; w0 < S; w0 += SW) {
+            wn = min(SW, S - w0);
+            __syncthreads();  // the previous window's readers are done
+            for (int sl = t; sl < wn; sl += 256) {
+                const int id = st[w0 + sl];
+                float4 rh, rl;
+                tile_frame(a.pin[2 * id], a.pin[2 * id + 1], O, rh, rl);
+                rh.w = __uint_as_float(pack_low(rh, rl));
+                sl_s[sl] = rh;
+            }
+            __syncthreads();
+            list_pass();
+        }
     }
     // the residue's total over its NL lanes (butterfly: every lane gets the same bits)
     float fx = k.c6 * L.fx + A.fx, fy = k.c6 * L.fy + A.fy, fz = k.c6 * L.fz + A.fz;
@@ -1638,13 +1742,14 @@ __global__ __launch_bounds__(256) void k_pair_forces(PairArgs a)
 {
     constexpr int NL = 256 / TILE;
     constexpr int SM = stage_max<TILE>();
-    __shared__ float acc_s[3][SM];
+    constexpr int SW = stage_win<TILE>();
+    __shared__ float acc_s[3][SW];  // slots beyond SW take device-wide atomics
     const int tile = blockIdx.x, t = threadIdx.x;
     const int rho = t / NL, q = t % NL;
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
-    const int S = a.stage_cnt[tile];
+    const int S = min(a.stage_cnt[tile], SM);
     const int *st = a.stage + (size_t)tile * SM;
-    for (int sl = t; sl < S; sl += 256) {
+    for (int sl = t; sl < min(S, SW); sl += 256) {
         acc_s[0][sl] = 0.0f;
         acc_s[1][sl] = 0.0f;
         acc_s[2][sl] = 0.0f;
@@ -1668,9 +1773,15 @@ __global__ __launch_bounds__(256) void k_pair_forces(PairArgs a)
             own.fx += d.fx;
             own.fy += d.fy;
             own.fz += d.fz;
-            atomicAdd(&acc_s[0][sl], -d.fx);
-            atomicAdd(&acc_s[1][sl], -d.fy);
-            atomicAdd(&acc_s[2][sl], -d.fz);
+            if (sl < SW) {
+                atomicAdd(&acc_s[0][sl], -d.fx);
+                atomicAdd(&acc_s[1][sl], -d.fy);
+                atomicAdd(&acc_s[2][sl], -d.fz);
+            } else {
+                unsafeAtomicAdd(&a.facc[j].x, -d.fx);
+                unsafeAtomicAdd(&a.facc[j].y, -d.fy);
+                unsafeAtomicAdd(&a.facc[j].z, -d.fz);
+            }
             if (ENERGY) {
                 const double he = 0.5 * d.e_r, hv = 0.5 * d.vir;
                 own.e_r += he;
@@ -1738,7 +1849,7 @@ __global__ __launch_bounds__(256) void k_pair_forces(PairArgs a)
     }
     __syncthreads();
     // the slots' shares
-    for (int sl = t; sl < S; sl += 256) {
+    for (int sl = t; sl < min(S, SW); sl += 256) {
         const float fx = acc_s[0][sl], fy = acc_s[1][sl], fz = acc_s[2][sl];
         if (fx != 0.0f || fy != 0.0f || fz != 0.0f) {
             const int j = st[sl];

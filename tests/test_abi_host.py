@@ -77,10 +77,13 @@ def test_workspace_size_and_bind_checks(lib):
     s = make_config("c1")
     c = _ctx(s)
     n1 = c.workspace_size()
-    c2 = P.Context(RunParams(list_capacity=1024))  # above the default 512 of the plain schedule
+    c2 = P.Context(RunParams(list_capacity=256))  # below the default 1024 of the plain schedule
     c2.load_topology(s.res_offsets, s.bonds, s.bond_r0, s.natives, s.native_r0)
     n2 = c2.workspace_size()
-    assert n2 > n1 > s.n_res * 64
+    assert n1 > n2 > s.n_res * 64
+    with pytest.raises(P.SopError) as e:
+        P.Context(RunParams(list_capacity=1040))   # the largest row is 1024 entries
+    assert e.value.name == "SOP_E_ARG"
     # null, misaligned or short workspaces are rejected before any device use
     L = P.lib()
     assert L.sop_bind_workspace(c.h, None, n1) == -3
