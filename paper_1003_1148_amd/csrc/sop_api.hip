@@ -59,7 +59,7 @@ struct sop_ctx {
     long long max_len = 0;           // longest trajectory
     std::vector<int> pack_off;       // batched: first slot of each pack
     std::vector<int> slot_res;       // batched: residue of each slot
-    hipGraphExec_t bgraphs[2] = {nullptr, nullptr};  // batched launch graphs by layer parity
+    hipGraphExec_t bgraphs[2][2] = {};  // batched launch graphs by layer parity, records
 
     // device state
     bool topo = false, bound = false, coords = false, list_valid = false;
@@ -182,6 +182,7 @@ size_t layout(const sop_ctx *c, char *base, DevBufs *b)
     d.skin_flag = (unsigned *)take(sizeof(unsigned));
     d.list_stats = (unsigned long long *)take(2 * sizeof(unsigned long long));
     d.tile_ord = (unsigned char *)take(plain ? n_tiles_max * 256 : 0);
+    d.skin_ord = (unsigned short *)take((plain ? n_tiles_max * 256 : 0) * sizeof(unsigned short));
     d.vel = (float4 *)take((plain ? n : 0) * sizeof(float4));
     d.facc = (float4 *)take((plain ? n : 0) * sizeof(float4));
     d.re_kbt = (double *)take((plain ? 0 : T) * sizeof(double));
@@ -241,11 +242,12 @@ void destroy_graphs(sop_ctx *c)
                 (void)hipGraphExecDestroy(g);
                 g = nullptr;
             }
-    for (auto &g : c->bgraphs)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto &gp : c->bgraphs)
+        for (auto &g : gp)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
 }
 
 // Packs of whole trajectories for the batched schedule: first-fit
@@ -485,12 +487,16 @@ void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, b
         launch_reduce_energy(c->b, c->n_traj, s);
 }
 
+// mode 1: one force evaluation; otherwise n_steps steps, recording energies
+// only when `records` (a launch whose steps hold a multiple of the energy
+// interval).
 void batch_launch(sop_ctx *c, hipStream_t s, int n_steps, int stale, int mode, const long long *base,
-                  long long off)
+                  long long off, bool records = false)
 {
     launch_batch(c->b, c->cur, n_packs(c), c->batch_wg, c->cap, step_consts(c), c->tip,
                  c->pulls.empty() ? 0 : 1, list_rc2(c), c->p.list_every, c->energy_every, n_steps,
-                 stale, mode, base, off, s, c->re_rep > 0 ? c->b.re_tscale : nullptr);
+                 stale, mode == 1 ? 1 : (records ? 2 : 0), base, off, s,
+                 c->re_rep > 0 ? c->b.re_tscale : nullptr);
 }
 
 // Last step in [first, first + n) whose energies are recorded, or -1.
@@ -505,8 +511,9 @@ long long last_record(const sop_ctx *c, long long first, long long n)
 }
 
 // Batched schedule: a graph of one persistent launch of batch_steps steps plus
-// the device step-counter advance, for layer parity `par`.
-sop_status capture_batch_graph(sop_ctx *c, int par)
+// the device step-counter advance, for layer parity `par`, with or without
+// energy records.
+sop_status capture_batch_graph(sop_ctx *c, int par, int records)
 {
     if (!c->cap_stream)
         HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -514,7 +521,7 @@ sop_status capture_batch_graph(sop_ctx *c, int par)
     c->cur = par;
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-    batch_launch(c, c->cap_stream, c->batch_steps, 0, 0, c->b.step_base, 0);
+    batch_launch(c, c->cap_stream, c->batch_steps, 0, 0, c->b.step_base, 0, records != 0);
     launch_add_step(c->b.step_base, c->batch_steps, c->cap_stream);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     c->cur = saved;
@@ -525,7 +532,7 @@ sop_status capture_batch_graph(sop_ctx *c, int par)
     (void)hipGraphDestroy(g);
     if (e != hipSuccess)
         return hip_fail(c, e, "hipGraphInstantiate");
-    c->bgraphs[par] = ex;
+    c->bgraphs[par][records] = ex;
     return SOP_OK;
 }
 
@@ -896,11 +903,12 @@ sop_status sop_set_batch(sop_ctx *c, int32_t wg, int32_t steps)
         return fail(c, SOP_E_ARG, "workgroup smaller than the longest trajectory");
     c->batch_wg_req = wg;
     c->batch_steps = steps;
-    for (auto &g : c->bgraphs)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto &gp : c->bgraphs)
+        for (auto &g : gp)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
     if (c->bound && c->schedule == SOP_SCHEDULE_BATCHED) {
         c->batch_wg = pick_batch_wg(c);
         make_packs(c);
@@ -1221,6 +1229,7 @@ sop_status sop_bind_workspace(sop_ctx *c, void *dev, size_t bytes)
         HIP_TRY(c, hipMemsetAsync(b.facc, 0, n * sizeof(float4), s));
         HIP_TRY(c, hipMemsetAsync(b.vel, 0, n * sizeof(float4), s));
         HIP_TRY(c, hipMemsetAsync(b.tile_ord, 0, n_tiles_max * 256, s));
+        HIP_TRY(c, hipMemsetAsync(b.skin_ord, 0, n_tiles_max * 256 * sizeof(unsigned short), s));
         HIP_TRY(c, hipMemsetAsync(b.eacc, 0, n * sizeof(double4), s));
         HIP_TRY(c, hipMemsetAsync(b.topo2, 0, topo2_elems * sizeof(uint2), s));
         HIP_TRY(c, hipMemsetAsync(b.stage_cnt, 0, n_tiles_max * sizeof(int), s));
@@ -1483,8 +1492,9 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
                 k = std::min<long long>(k, X - c->step % X);  // stop at the next exchange
             const long long rec = last_record(c, c->step, k);
             if (c->graph_steps > 0 && c->list_valid && k == K && X == 0) {
-                if (!c->bgraphs[c->cur]) {
-                    st = capture_batch_graph(c, c->cur);
+                const int rg = rec >= 0 ? 1 : 0;
+                if (!c->bgraphs[c->cur][rg]) {
+                    st = capture_batch_graph(c, c->cur, rg);
                     if (st != SOP_OK)
                         return st;
                 }
@@ -1492,9 +1502,9 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
                     launch_set_step(c->b.step_base, c->step, c->stream);
                     base_set = true;
                 }
-                HIP_TRY(c, hipGraphLaunch(c->bgraphs[c->cur], c->stream));
+                HIP_TRY(c, hipGraphLaunch(c->bgraphs[c->cur][rg], c->stream));
             } else {
-                batch_launch(c, c->stream, (int)k, c->list_valid ? 0 : 1, 0, nullptr, c->step);
+                batch_launch(c, c->stream, (int)k, c->list_valid ? 0 : 1, 0, nullptr, c->step, rec >= 0);
                 base_set = false;
             }
             if (rec >= 0)
@@ -1588,7 +1598,7 @@ sop_status sop_step_timed(sop_ctx *c, int64_t n_steps, double *ms_out)
             const long long k = std::min<long long>(c->batch_steps, n_steps - q);
             const long long rec = last_record(c, c->step, k);
             (void)hipEventRecord(ev[0], c->stream);
-            batch_launch(c, c->stream, (int)k, c->list_valid ? 0 : 1, 0, nullptr, c->step);
+            batch_launch(c, c->stream, (int)k, c->list_valid ? 0 : 1, 0, nullptr, c->step, rec >= 0);
             (void)hipEventRecord(ev[1], c->stream);
             hipError_t e = hipEventSynchronize(ev[1]);
             if (e != hipSuccess) {

@@ -82,6 +82,8 @@ struct DevBufs {
     unsigned *skin_flag;     // plain: nonzero when the next rebuild must rebuild the skin
     unsigned long long *list_stats;  // plain: {rebuilds, skin builds} since binding
     unsigned char *tile_ord; // plain: per tile (tile * T + rank), its residues by decreasing list length
+    unsigned short *skin_ord;  // plain: per tile (tile * T + rank), 1 + its residues by decreasing
+                               // skin row length (0 before the first skin search: identity)
     float4 *vel;             // plain, underdamped: per-residue velocity before its last half kick
     double *re_kbt;          // batched, replica exchange: the temperature ladder (kB T)
     int *re_tidx;            // batched, replica exchange: temperature index of each trajectory
@@ -156,8 +158,9 @@ void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const 
 // Residues per chunk of the energy reduction (chunks never span trajectories).
 constexpr int ECHUNK = 1024;
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);
-// Batched ensemble: n_steps steps of every pack in one launch (mode 1: one
-// force evaluation, no update).
+// Batched ensemble: n_steps steps of every pack in one launch.  mode 0:
+// steps without energy records; 2: steps that record at multiples of
+// energy_every; 1: one force evaluation with records, no update.
 void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const StepConsts &c,
                   const TipDev &tip, int has_pull, float rc2, int list_every, long long energy_every,
                   int n_steps, int stale, int mode, const long long *step_base, long long step_off,

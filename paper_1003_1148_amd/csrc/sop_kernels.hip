@@ -142,22 +142,36 @@ __device__ __forceinline__ PairConsts pair_consts(const StepConsts &c)
     return k;
 }
 
+// The force arithmetic of the pair and external terms states every fused
+// multiply-add and lets the compiler fuse nothing else, so a term's force has
+// the same bits in every kernel that evaluates it, whether or not that
+// kernel also takes the term's energy (which shares its subexpressions).
+__device__ __forceinline__ float len2(const float3 &d)
+{
+#pragma clang fp contract(off)
+    return __builtin_fmaf(d.z, d.z, __builtin_fmaf(d.y, d.y, d.x * d.x));
+}
+
+__device__ __forceinline__ void acc_force(Acc &A, float c, const float3 &d)
+{
+    A.fx = __builtin_fmaf(c, d.x, A.fx);
+    A.fy = __builtin_fmaf(c, d.y, A.fy);
+    A.fz = __builtin_fmaf(c, d.z, A.fz);
+}
+
 // FENE: -(k R0^2/2) ln(1 - (r - r0)^2/R0^2); |r - r0| >= R0 sets `broken`.
 __device__ __forceinline__ void add_fene_d(Acc &A, const float3 &d, float r0, const PairConsts &k, bool rec,
                                            bool &broken)
 {
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const float rr = __builtin_amdgcn_sqrtf(r2);
+#pragma clang fp contract(off)
+    const float rr = __builtin_amdgcn_sqrtf(len2(d));
     const float dl = rr - r0;
-    float x = 1.0f - dl * dl * k.inv_R0sq;
+    float x = __builtin_fmaf(-(dl * dl), k.inv_R0sq, 1.0f);
     if (!(x > 0.0f)) {
         broken = true;
         x = 1.0f;
     }
-    const float coef = -k.kf * dl * fast_rcp(x * rr);
-    A.fx += coef * d.x;
-    A.fy += coef * d.y;
-    A.fz += coef * d.z;
+    acc_force(A, -k.kf * dl * fast_rcp(x * rr), d);
     if (rec) {
         const double dd = (double)dl;
         const double R0sq = (double)k.R0sq;
@@ -169,30 +183,25 @@ __device__ __forceinline__ void add_fene_d(Acc &A, const float3 &d, float r0, co
 // Native contact: eps_h [(r0/r)^12 - 2 (r0/r)^6].
 __device__ __forceinline__ void add_native_d(Acc &A, const float3 &d, float r0, const PairConsts &k, bool rec)
 {
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const float ir2 = fast_rcp(r2);
+#pragma clang fp contract(off)
+    const float ir2 = fast_rcp(len2(d));
     const float s = r0 * r0 * ir2;
     const float q = s * s * s;
-    const float coef = k.eh12 * (q * q - q) * ir2;
-    A.fx += coef * d.x;
-    A.fy += coef * d.y;
-    A.fz += coef * d.z;
+    const float w = __builtin_fmaf(q, q, -q);  // q^2 - q
+    acc_force(A, k.eh12 * w * ir2, d);
     if (rec) {
-        A.e_n += (double)(k.eh * (q * q - 2.0f * q));
-        A.vir += (double)(k.eh12 * (q * q - q));
+        A.e_n += (double)(k.eh * __builtin_fmaf(q, q, -2.0f * q));
+        A.vir += (double)(k.eh12 * w);
     }
 }
 
 // Soft repulsion: eps_l (sigma/r)^6.
 __device__ __forceinline__ void add_repulsive_d(Acc &A, const float3 &d, const PairConsts &k, bool rec)
 {
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const float ir2 = fast_rcp(r2);
+#pragma clang fp contract(off)
+    const float ir2 = fast_rcp(len2(d));
     const float ir4 = ir2 * ir2;
-    const float coef = k.c6 * ir4 * ir4;
-    A.fx += coef * d.x;
-    A.fy += coef * d.y;
-    A.fz += coef * d.z;
+    acc_force(A, k.c6 * ir4 * ir4, d);
     if (rec) {
         const float q = k.sg6 * ir4 * ir2;
         A.e_r += (double)(k.el * q);
@@ -205,13 +214,10 @@ __device__ __forceinline__ void add_repulsive_d(Acc &A, const float3 &d, const P
 // pair; the energy and virial terms are the full ones.
 __device__ __forceinline__ void add_repulsive_u(Acc &A, const float3 &d, const PairConsts &k, bool rec)
 {
-    const float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const float ir2 = fast_rcp(r2);
+#pragma clang fp contract(off)
+    const float ir2 = fast_rcp(len2(d));
     const float ir4 = ir2 * ir2;
-    const float ir8 = ir4 * ir4;
-    A.fx += ir8 * d.x;
-    A.fy += ir8 * d.y;
-    A.fz += ir8 * d.z;
+    acc_force(A, ir4 * ir4, d);
     if (rec) {
         const float q = k.sg6 * ir4 * ir2;
         A.e_r += (double)(k.el * q);
@@ -239,6 +245,7 @@ __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep,
                                              const PullDev *pulls, const TipDev &tip, bool rec,
                                              unsigned *err)
 {
+#pragma clang fp contract(off)
     if (pull < 0 && !tip.on)
         return;
     const double tn = (double)step * h;
@@ -247,9 +254,9 @@ __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep,
     const double pz = (double)hi.z + (double)lo.z;
     if (pull >= 0) {
         const PullDev pd = pulls[pull];
-        const double dx = pd.anchor0[0] + pd.v[0] * tn - px;
-        const double dy = pd.anchor0[1] + pd.v[1] * tn - py;
-        const double dz = pd.anchor0[2] + pd.v[2] * tn - pz;
+        const double dx = __builtin_fma(pd.v[0], tn, pd.anchor0[0]) - px;
+        const double dy = __builtin_fma(pd.v[1], tn, pd.anchor0[1]) - py;
+        const double dz = __builtin_fma(pd.v[2], tn, pd.anchor0[2]) - pz;
         A.fx += (float)(pd.kappa * dx);
         A.fy += (float)(pd.kappa * dy);
         A.fz += (float)(pd.kappa * dz);
@@ -261,10 +268,10 @@ __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep,
         }
     }
     if (tip.on) {
-        const float dx = (float)(px - (tip.c0[0] + tip.v[0] * tn));
-        const float dy = (float)(py - (tip.c0[1] + tip.v[1] * tn));
-        const float dz = (float)(pz - (tip.c0[2] + tip.v[2] * tn));
-        const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float dx = (float)(px - __builtin_fma(tip.v[0], tn, tip.c0[0]));
+        const float dy = (float)(py - __builtin_fma(tip.v[1], tn, tip.c0[1]));
+        const float dz = (float)(pz - __builtin_fma(tip.v[2], tn, tip.c0[2]));
+        const float rr = sqrtf(len2(make_float3(dx, dy, dz)));
         const float gap = rr - (float)tip.radius;
         if (!(gap > 0.0f)) {
             atomicOr(err, ERR_TIP);
@@ -275,14 +282,12 @@ __device__ __forceinline__ void add_external(Acc &A, double &e_x, double &f_rep,
         const float s3 = sg * sg * sg;
         const float q = s3 * s3;
         const float mag_r = 6.0f * (float)tip.eps * q * igap * fast_rcp(rr);  // magnitude / r
-        const float cx = mag_r * dx, cy = mag_r * dy, cz = mag_r * dz;
-        A.fx += cx;
-        A.fy += cy;
-        A.fz += cz;
+        acc_force(A, mag_r, make_float3(dx, dy, dz));
         if (rec) {
             e_x += tip.eps * (double)q;
             if (tip.has_dir)
-                f_rep += (double)cx * tip.vhat[0] + (double)cy * tip.vhat[1] + (double)cz * tip.vhat[2];
+                f_rep += (double)(mag_r * dx) * tip.vhat[0] + (double)(mag_r * dy) * tip.vhat[1] +
+                         (double)(mag_r * dz) * tip.vhat[2];
         }
     }
 }
@@ -301,6 +306,7 @@ __device__ __forceinline__ uint4 noise_words(unsigned tag, unsigned stream, long
 __device__ __forceinline__ void update_with_noise(float4 &hi, float4 &lo, const Acc &A, const float g[3],
                                                   const StepConsts &c, unsigned *err)
 {
+#pragma clang fp contract(off)
     if (__float_as_uint(hi.w) >> 31)
         return;  // fixed residue
     float nh[3], nl[3];
@@ -308,7 +314,7 @@ __device__ __forceinline__ void update_with_noise(float4 &hi, float4 &lo, const 
     for (int ax = 0; ax < 3; ++ax) {
         const float f = ax == 0 ? A.fx : (ax == 1 ? A.fy : A.fz);
         const float h0 = comp(hi, ax), l0 = comp(lo, ax);
-        const float delta = c.c_drift * f + c.c_noise * g[ax];
+        const float delta = __builtin_fmaf(c.c_drift, f, c.c_noise * g[ax]);
         const float y = delta + l0;
         const float t = h0 + y;
         const float bp = t - h0;
@@ -335,6 +341,7 @@ struct UdConsts {
 __device__ __forceinline__ void underdamped_update(float4 &hi, float4 &lo, float4 &v, const Acc &A,
                                                    const float g[3], const UdConsts &u, unsigned *err)
 {
+#pragma clang fp contract(off)
     if (__float_as_uint(hi.w) >> 31) {
         v = make_float4(0.f, 0.f, 0.f, 0.f);  // fixed residue
         return;
@@ -343,9 +350,9 @@ __device__ __forceinline__ void underdamped_update(float4 &hi, float4 &lo, float
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const float f = ax == 0 ? A.fx : (ax == 1 ? A.fy : A.fz);
-        const float w0 = comp(v, ax) + u.kick * f;
-        const float w1 = u.c1 * w0 + u.c2 * g[ax];
-        const float delta = u.half_h * w0 + u.half_h * w1;
+        const float w0 = __builtin_fmaf(u.kick, f, comp(v, ax));
+        const float w1 = __builtin_fmaf(u.c1, w0, u.c2 * g[ax]);
+        const float delta = __builtin_fmaf(u.half_h, w0, u.half_h * w1);
         const float h0 = comp(hi, ax), l0 = comp(lo, ax);
         const float y = delta + l0;
         const float t = h0 + y;
@@ -982,6 +989,7 @@ struct FilterArgs {
     unsigned *skin_flag;
     unsigned long long *stats;
     unsigned char *tile_ord;  // per tile: its residues by decreasing list length
+    const unsigned short *skin_ord;  // per tile: 1 + its residues by decreasing skin row length
     long long *step_base;     // graph replays: advanced once per rebuild, or NULL
     long long *step_next;
     float rc2;
@@ -989,20 +997,27 @@ struct FilterArgs {
 };
 
 template <int TILE>
-__global__ __launch_bounds__(256) void k_filter(FilterArgs a)
+__global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a)
 {
     constexpr int NL = 256 / TILE;  // lanes per residue, adjacent in the wave
     constexpr int SM = stage_max<TILE>();
     constexpr int SW = stage_win<TILE>();
-    constexpr int OUTW = 12288 / TILE;  // filtered entries of a residue gathered in LDS (24 KB in all)
-    constexpr int PF = 8;               // row pieces per lane loaded up front
-    constexpr int MAXP = 128;           // pieces of 8 entries in a row (cap <= 1024)
-    __shared__ float4 hs[SW];
+    // filtered entries of a residue gathered in LDS (a multiple of 8, so
+    // rows start 16-byte aligned); sized so that 64-residue tiles fit five
+    // workgroups per CU
+    constexpr int OUTW = TILE == 64 ? 184 : (TILE == 128 ? 96 : 48);
+    constexpr int PF = 8;      // row pieces per lane loaded up front
+    constexpr int MAXP = 128;  // pieces of 8 entries in a row (cap <= 1024)
+    // the staged positions (predicate) and the gathered rows (emit) share
+    // one region
+    constexpr int HS_B = SW * 16, OUT_B = TILE * OUTW * 2;
+    __shared__ __align__(16) unsigned char region[HS_B > OUT_B ? HS_B : OUT_B];
+    float4 *hs = reinterpret_cast<float4 *>(region);
+    unsigned short *out_s = reinterpret_cast<unsigned short *>(region);
     __shared__ int lens[TILE];
-    __shared__ __align__(16) unsigned short out_s[TILE * OUTW];
     __shared__ unsigned char pbits[TILE * MAXP];  // passing entries of each piece
     const int tile = blockIdx.x, t = threadIdx.x;
-    const int rho = t / NL, q = t % NL;
+    const int q = t % NL;
     // the cell counts are read only by the skin build, which is done: clear
     // them for the next one; the flag is read only by the skin build too
     for (int k = tile * 256 + t; k < a.n_cells; k += gridDim.x * 256)
@@ -1020,7 +1035,11 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
     const int S = min(a.stage_cnt[tile], SM);
     const int *st = a.stage + (size_t)tile * SM;
-    const bool act = rho < tcnt;
+    // the residue of this lane group: rows longest first (the order of the
+    // last skin search)
+    const bool act = t / NL < tcnt;
+    const int ord = act ? (int)a.skin_ord[(size_t)tile * TILE + t / NL] : 0;
+    const int rho = act ? (ord > 0 ? ord - 1 : t / NL) : t / NL;
     const int i = first + (act ? rho : 0);
     const int len = act ? min(a.skin_cnt[i], a.cap) : 0;
     // the row in 16-byte pieces of 8 entries, piece m NL + q to lane q, so
@@ -1034,6 +1053,9 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
         pre[m] = m * NL + q < npc ? src[m * NL + q] : make_uint4(0u, 0u, 0u, 0u);
     const float4 pi = a.pos[2 * i];
     unsigned char *pb = pbits + rho * MAXP;
+    // passing entries of this lane's first PF pieces, eight bits a piece, in
+    // registers; later pieces (rows longer than 8 PF NL entries) in LDS
+    unsigned pbr[PF / 4] = {};
     // the predicate, window by window of the staging set (one window for
     // nearly every tile): each entry is tested in the window holding its slot
     for (int w0 = 0; w0 < S || w0 == 0; w0 += SW) {
@@ -1043,37 +1065,59 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
         for (int sl = t; sl < wn; sl += 256)
             hs[sl] = a.pos[2 * st[w0 + sl]];
         __syncthreads();
-        auto test = [&](const uint4 &w, int pc) {
+        // branch-free: the eight staged positions are read (an entry past
+        // the row's end or outside the window reads slot 0), then all eight
+        // are tested and the results masked
+        auto test = [&](const uint4 &w, int pc) -> unsigned {
             const unsigned ws[4] = {w.x, w.y, w.z, w.w};
-            unsigned bits = w0 == 0 ? 0u : pb[pc];
-            const int valid = min(8, max(0, len - pc * 8));
+            const int valid = len - pc * 8;
+            float4 pj[8];
+            unsigned ok = 0u;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int e = (int)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu) - w0;
-                if (u < valid && (unsigned)e < (unsigned)wn && within_cutoff(pi, hs[e], a.rc2))
-                    bits |= 1u << u;
+                const bool in = (u < valid) & ((unsigned)e < (unsigned)wn);
+                ok |= (unsigned)in << u;
+                pj[u] = hs[in ? e : 0];
             }
-            pb[pc] = (unsigned char)bits;
+            unsigned bits = 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                bits |= (unsigned)within_cutoff(pi, pj[u], a.rc2) << u;
+            return bits & ok;
         };
 #pragma unroll
         for (int m = 0; m < PF; ++m)
             if (m * NL + q < npc)
-                test(pre[m], m * NL + q);
-        for (int pc = PF * NL + q; pc < npc; pc += NL)
-            test(src[pc], pc);
+                pbr[m >> 2] |= test(pre[m], m * NL + q) << (8 * (m & 3));
+        for (int pc = PF * NL + q; pc < npc; pc += NL) {
+            const unsigned bits = test(src[pc], pc);
+            pb[pc] = (unsigned char)(w0 == 0 ? bits : (bits | pb[pc]));
+        }
     }
+    // the row's passing entries, over the residue's lanes
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < PF / 4; ++k)
+        tot += __popc(pbr[k]);
+    for (int pc = PF * NL + q; pc < npc; pc += NL)
+        tot += __popc((unsigned)pb[pc]);
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1)
+        tot += __shfl_xor(tot, off, NL);
+    __syncthreads();  // the staged positions are dead: the region takes the rows
     unsigned short *dst = a.list16 + (size_t)i * a.cap;
-    // rows that fit are gathered in LDS and written out in 16-byte pieces
-    const bool in_lds = len <= OUTW - 8;
+    // rows that fit (padding included) are gathered in LDS and written out
+    // in 16-byte pieces
+    const bool in_lds = ((tot + 7) & ~7) <= OUTW;
     unsigned short *ob = in_lds ? out_s + rho * OUTW : dst;
     int rounds = (npc + NL - 1) / NL;
 #pragma unroll
     for (int off = 1; off < NL; off <<= 1)
         rounds = max(rounds, __shfl_xor(rounds, off, NL));  // uniform over the residue's lanes
     int base = 0;
-    auto emit = [&](const uint4 &w, int pc) {
+    auto emit = [&](const uint4 &w, unsigned bits) {
         const unsigned ws[4] = {w.x, w.y, w.z, w.w};
-        unsigned bits = pc < npc ? pb[pc] : 0u;
         const int c = __popc(bits);
         // passing entries before this lane's piece: scan over the residue's lanes
         int v = c;
@@ -1094,9 +1138,11 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a)
 #pragma unroll
     for (int m = 0; m < PF; ++m)
         if (m < rounds)
-            emit(pre[m], m * NL + q);
-    for (int m = PF; m < rounds; ++m)
-        emit(m * NL + q < npc ? src[m * NL + q] : make_uint4(0u, 0u, 0u, 0u), m * NL + q);
+            emit(pre[m], (pbr[m >> 2] >> (8 * (m & 3))) & 0xffu);
+    for (int m = PF; m < rounds; ++m) {
+        const int pc = m * NL + q;
+        emit(pc < npc ? src[pc] : make_uint4(0u, 0u, 0u, 0u), pc < npc ? (unsigned)pb[pc] : 0u);
+    }
     if (act && q == NL - 1) {
         // pad the row to a multiple of 8 entries: with the LDS slot of the
         // far-away position when the tile fits one window, else the empty slot
@@ -1144,6 +1190,7 @@ struct CanonArgs {
     const int *skin_cnt;
     uint2 *topo2;
     const unsigned *skin_flag;
+    unsigned short *skin_ord;
     int cap;
 };
 
@@ -1297,6 +1344,19 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
             }
         }
         __syncthreads();  // the masks are reused by the next pass
+    }
+    // the filter hands the skin rows to its waves longest first, so that the
+    // rows a wave tests have about the same length (ties in index order)
+    int *slen = sid;  // the ids are written out
+    for (int u = t; u < tcnt; u += 256)
+        slen[u] = min(a.skin_cnt[first + u], a.cap);
+    __syncthreads();
+    for (int u = t; u < tcnt; u += 256) {
+        const int L = slen[u];
+        int r = 0;
+        for (int v = 0; v < tcnt; ++v)
+            r += (slen[v] > L || (slen[v] == L && v < u)) ? 1 : 0;
+        a.skin_ord[(size_t)tile * TILE + r] = (unsigned short)(u + 1);
     }
 }
 
@@ -1500,6 +1560,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     float g[3] = {0.0f, 0.0f, 0.0f};
     Acc X;
     double e_x = 0.0, f_rep = 0.0;
+    // the last step of a list period bins the new positions for the next
+    // skin search; the cell slot is taken in the cell of the position before
+    // the update (nearly always the cell of the new one), so the atomic's
+    // round trip overlaps the step
     if (upd) {
         hu = a.pin[2 * iu];
         lu = a.pin[2 * iu + 1];
@@ -1573,6 +1637,16 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     }
     if (windowed)
         rh0.w = __uint_as_float(pack_low(rh0, rl0));
+    // the binning's slot and the displacement check's reference, requested
+    // now so that they arrive during the list sums
+    float4 hsk = make_float4(0.f, 0.f, 0.f, 0.f);
+    int bin_s0 = 0;
+    if (MODE == 0 && upd) {
+        if (a.check_thr2 > 0.0f)
+            hsk = a.hi_skin[iu];
+        if (a.do_bin)
+            bin_s0 = atomicAdd(&a.cell_count[cell_index(hu, a.traj_cell[__float_as_int(lu.w)], a.g)], 1);
+    }
     // ---- 3. list chunks of this lane ----
     Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
     const float3 pl0 = unpack_low(rh0);
@@ -1697,13 +1771,30 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     if (a.check_thr2 > 0.0f) {
         // moved farther than skin/2 from the last skin build: the next
         // rebuild rebuilds the skin
-        const float4 hs = a.hi_skin[iu];
-        const float dx = hi.x - hs.x, dy = hi.y - hs.y, dz = hi.z - hs.z;
+        const float dx = hi.x - hsk.x, dy = hi.y - hsk.y, dz = hi.z - hsk.z;
         if (!(dx * dx + dy * dy + dz * dz <= a.check_thr2))
             atomicOr(a.skin_flag, 1u);
     }
-    if (a.do_bin)
-        bin_one(hi, iu, __float_as_int(lo.w), a.g, a.traj_cell, a.cell_count, a.cells, a.cell_of, a.err);
+    if (a.do_bin) {
+        const int traj = __float_as_int(lo.w);
+        const int bin_c0 = cell_index(hu, a.traj_cell[traj], a.g);
+        const int c1 = cell_index(hi, a.traj_cell[traj], a.g);
+        if (c1 == bin_c0) {
+            a.cell_of[iu] = c1;
+            if (bin_s0 < CELL_CAP)
+                a.cells[(size_t)c1 * CELL_CAP + bin_s0] = make_float4(hi.x, hi.y, hi.z, __int_as_float(iu));
+            else
+                atomicOr(a.err, ERR_CELL);
+        } else {
+            // moved into another cell: the slot taken holds a far-away copy
+            // (no predicate passes it; the id keeps the cell's ids distinct)
+            // and the residue is binned again
+            if (bin_s0 < CELL_CAP)
+                a.cells[(size_t)bin_c0 * CELL_CAP + bin_s0] =
+                    make_float4(1.0e18f, 1.0e18f, 1.0e18f, __int_as_float(iu));
+            bin_one(hi, iu, traj, a.g, a.traj_cell, a.cell_count, a.cells, a.cell_of, a.err);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2233,7 +2324,9 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             }
             assign();  // its barriers also publish the rows written above
         }
-        const bool rec = MODE == 1 || (a.energy_every > 0 && step % a.energy_every == 0);
+        // mode 0 never records (no FP64 sums in its registers), mode 2
+        // records at multiples of the energy interval
+        const bool rec = MODE == 1 || (MODE == 2 && a.energy_every > 0 && step % a.energy_every == 0);
         {
             // ---- list partners (forces) of the row this lane was given ----
             const int r = my & 0xffff, nch = my >> 16;
@@ -2343,7 +2436,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         }
         __syncthreads();
     }
-    if (MODE == 0 && act) {
+    if (MODE != 1 && act) {
         a.pout[2 * i] = hi;
         a.pout[2 * i + 1] = lo;
     }
@@ -2500,6 +2593,7 @@ void canon_tile(const DevBufs &b, int cap, hipStream_t s)
     a.skin_cnt = b.list_cnt;
     a.topo2 = b.topo2;
     a.skin_flag = b.skin_flag;
+    a.skin_ord = b.skin_ord;
     a.cap = cap;
     hipLaunchKernelGGL((k_canon<TILE>), dim3(b.n_tiles[tile_index(TILE)]), dim3(256), 0, s, a);
 }
@@ -2524,6 +2618,7 @@ void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2
     a.skin_flag = b.skin_flag;
     a.stats = b.list_stats;
     a.tile_ord = b.tile_ord;
+    a.skin_ord = b.skin_ord;
     a.rc2 = rc2;
     a.cap = cap;
     a.n_cells = g.n_cells;
@@ -2804,6 +2899,12 @@ void launch_batch(const DevBufs &b, int cur, int n_packs, int wg, int cap, const
         case 256: hipLaunchKernelGGL((k_batch<256, 1>), grid, dim3(256), 0, s, a); break;
         case 512: hipLaunchKernelGGL((k_batch<512, 1>), grid, dim3(512), 0, s, a); break;
         default: hipLaunchKernelGGL((k_batch<1024, 1>), grid, dim3(1024), 0, s, a); break;
+        }
+    } else if (mode == 2) {
+        switch (wg) {
+        case 256: hipLaunchKernelGGL((k_batch<256, 2>), grid, dim3(256), 0, s, a); break;
+        case 512: hipLaunchKernelGGL((k_batch<512, 2>), grid, dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_batch<1024, 2>), grid, dim3(1024), 0, s, a); break;
         }
     } else {
         switch (wg) {

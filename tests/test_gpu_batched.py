@@ -114,6 +114,20 @@ def test_batched_results_do_not_depend_on_the_schedule(P, ens):
         assert np.array_equal(E, runs[0][1])
 
 
+@pytest.mark.parametrize("graph", [1, 0])
+def test_energy_records_do_not_change_the_trajectory(P, ens, graph):
+    """Launches without energy records run a kernel of their own; its forces
+    and updates have the same bits as those of the recording kernel."""
+    a = ctx(P, ens, steps=20, graph=graph, energy_every=0)
+    b = ctx(P, ens, steps=20, graph=graph, energy_every=40)
+    a.step(120)
+    b.step(120)
+    assert np.array_equal(a.get_coordinates(), b.get_coordinates())
+    assert b.get_energies()[1] == 80
+    a.close()
+    b.close()
+
+
 def test_batched_energy_interval_change(P, ens):
     """A new energy interval drops the captured launch graphs: energies and
     their step equal those of launches made without graphs."""

@@ -280,6 +280,19 @@ def test_graph_span_change_and_energy_alignment(P):
     assert np.array_equal(Ea, Eb)
 
 
+@pytest.mark.parametrize("graph_steps", [1, 0])
+def test_energy_records_do_not_change_the_trajectory(P, graph_steps):
+    """Record steps run the step kernel's energy variant; its forces and
+    update have the same bits as those of the plain variant."""
+    s = cfg("c2cap")
+    a = ctx_for(P, s, graph_steps=graph_steps, energy_every=0)
+    b = ctx_for(P, s, graph_steps=graph_steps, energy_every=10)
+    a.step(60)
+    b.step(60)
+    assert np.array_equal(a.get_coordinates(), b.get_coordinates())
+    assert b.get_energies()[1] == 50
+
+
 def test_runs_are_bit_reproducible(P):
     s = cfg("c2cap")
     xs = []
