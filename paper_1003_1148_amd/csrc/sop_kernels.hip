@@ -1496,7 +1496,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     constexpr int PER = SW / 256;    // staging slots per lane
     constexpr int EPI = 256 - TILE;  // first lane of the update lanes
     constexpr int PRE = 6;           // list chunks per lane loaded before the staging
-    constexpr int TPRE = 3;          // bonded/native entries per lane loaded before the staging
+    constexpr int TPRE = 2;          // bonded/native entries per lane loaded before the staging
     __shared__ float4 sl_s[SW + 1];  // {rh.xyz, packed rl}; slot SW: the far-away empty slot
     __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
     __shared__ double e_s[ENERGY ? 4 : 1][ENERGY ? TILE : 1];
@@ -1542,14 +1542,21 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     for (int k = 0; k < PRE; ++k)
         lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
     const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
+    // bonded entries: lane q takes bonds q, q + NL, ... and natives nb + q,
+    // nb + q + NL, ..., in loops of their own so that a wave runs each
+    // term's code once a round; its first bond and first TPRE - 1 natives
+    // are loaded here
     float2 te[TPRE];
 #pragma unroll
-    for (int k = 0; k < TPRE; ++k)
-        te[k] = q + k * NL < ntop ? a.tent[row.x + q + k * NL] : make_float2(0.f, 0.f);
+    for (int k = 0; k < TPRE; ++k) {
+        const int e = k == 0 ? q : nb + q + (k - 1) * NL;
+        te[k] = (k == 0 ? e < nb : e < ntop) ? a.tent[row.x + e] : make_float2(0.f, 0.f);
+    }
     float4 ph[TPRE], pl[TPRE];
 #pragma unroll
     for (int k = 0; k < TPRE; ++k) {
-        if (q + k * NL < ntop) {
+        const int e = k == 0 ? q : nb + q + (k - 1) * NL;
+        if (k == 0 ? e < nb : e < ntop) {
             const int j = __float_as_int(te[k].x);
             ph[k] = a.pin[2 * j];
             pl[k] = a.pin[2 * j + 1];
@@ -1595,25 +1602,21 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     Acc A;   // bonded and native terms
     bool broken = false;
     if (act) {
-#pragma unroll
-        for (int kk = 0; kk < TPRE; ++kk) {
-            const int e = q + kk * NL;
-            if (e < ntop) {
-                const float3 d = pair_delta(hi0, lo0, ph[kk], pl[kk]);
-                if (e < nb)
-                    add_fene_d(A, d, te[kk].y, k, ENERGY, broken);
-                else
-                    add_native_d(A, d, te[kk].y, k, ENERGY);
-            }
-        }
-        for (int e = q + TPRE * NL; e < ntop; e += NL) {
+        if (q < nb)
+            add_fene_d(A, pair_delta(hi0, lo0, ph[0], pl[0]), te[0].y, k, ENERGY, broken);
+        for (int e = q + NL; e < nb; e += NL) {
             const float2 tv = a.tent[row.x + e];
             const int j = __float_as_int(tv.x);
-            const float3 d = pair_delta(hi0, lo0, a.pin[2 * j], a.pin[2 * j + 1]);
-            if (e < nb)
-                add_fene_d(A, d, tv.y, k, ENERGY, broken);
-            else
-                add_native_d(A, d, tv.y, k, ENERGY);
+            add_fene_d(A, pair_delta(hi0, lo0, a.pin[2 * j], a.pin[2 * j + 1]), tv.y, k, ENERGY, broken);
+        }
+#pragma unroll
+        for (int kk = 1; kk < TPRE; ++kk)
+            if (nb + q + (kk - 1) * NL < ntop)
+                add_native_d(A, pair_delta(hi0, lo0, ph[kk], pl[kk]), te[kk].y, k, ENERGY);
+        for (int e = nb + q + (TPRE - 1) * NL; e < ntop; e += NL) {
+            const float2 tv = a.tent[row.x + e];
+            const int j = __float_as_int(tv.x);
+            add_native_d(A, pair_delta(hi0, lo0, a.pin[2 * j], a.pin[2 * j + 1]), tv.y, k, ENERGY);
         }
         if (broken)
             atomicOr(a.err, ERR_FENE);
