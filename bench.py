@@ -372,6 +372,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000, help="timed list periods")
     ap.add_argument("--warmup", type=int, default=100, help="untimed list periods")
     ap.add_argument("--tile", type=int, default=0, help="residues per workgroup (64/128/256; 0 = autotune)")
+    ap.add_argument("--skin", type=float, default=6.0,
+                    help="Verlet skin in A (the library's default is 4); it changes no result, "
+                         "only how often the cell-grid search runs (6 A: best of 3-7 A on this "
+                         "workload)")
     ap.add_argument("--graph-periods", type=int, default=10)
     ap.add_argument("--energy-every", type=int, default=1000)
     ap.add_argument("--timing-steps", type=int, default=300)
@@ -441,6 +445,8 @@ def main():
     L = p.list_every
     ctx = P.from_system(s, p, tile=args.tile, graph_steps=args.graph_periods,
                         energy_every=args.energy_every)
+    if args.skin is not None:
+        ctx.set_list_skin(args.skin)
     if args.tile == 0:
         ctx.autotune(budget_ms=300.0)
     ctx.build_pairlist()
@@ -517,6 +523,7 @@ def main():
             "md_steps_per_step": L,
             "energy_every": args.energy_every,
             "tile": ctx.get_tile(),
+            "skin_A": ctx.get_list_skin(),
             "graph_periods": args.graph_periods,
             "capture_steps_untimed": capture_steps,
             "bonds_per_res": round(b, 4),

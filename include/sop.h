@@ -333,6 +333,9 @@ sop_status sop_get_force_mode(const sop_ctx *ctx, int32_t *mode);
  */
 sop_status sop_set_list_skin(sop_ctx *ctx, double skin);
 
+/* The Verlet skin in use (host only). */
+sop_status sop_get_list_skin(const sop_ctx *ctx, double *skin);
+
 /* Rebuilds of the list and cell-grid searches of the skin since the
  * workspace was bound (plain schedule).  Synchronizes. */
 sop_status sop_get_list_stats(sop_ctx *ctx, int64_t *rebuilds, int64_t *skin_builds);

@@ -96,6 +96,7 @@ def lib():
             "sop_get_velocities": [vp, vp],
             "sop_get_force_mode": [vp, vp],
             "sop_get_list_stats": [vp, vp, vp],
+            "sop_get_list_skin": [vp, vp],
             "sop_running_average": [vp, i64, i32, vp],
             "sop_peak_force": [vp, i64, i32, vp, vp],
             "sop_virial_temperature": [vp, i64, i64, dbl, vp],
@@ -257,6 +258,11 @@ class Context:
 
     def set_list_skin(self, skin):
         self._check(lib().sop_set_list_skin(self.h, float(skin)))
+
+    def get_list_skin(self):
+        v = C.c_double(0.0)
+        self._check(lib().sop_get_list_skin(self.h, C.byref(v)))
+        return v.value
 
     def get_list_stats(self):
         """(list rebuilds, skin cell-grid searches) since binding."""

@@ -135,8 +135,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Row capacity: the requested one, else 1024 entries for the plain schedule
 // (its skin rows hold the partners within r_list + skin: at protein density,
-// about 120 A^3 per residue, up to some 500 within 24 A) and 256 for the
-// batched one; a multiple of 16.
+// about 120 A^3 per residue, some 480 within 24 A) and 256 for the batched
+// one; a multiple of 16.
 int list_cap(const sop_ctx *c)
 {
     const int cap = c->cap_req ? c->cap_req : (c->schedule == SOP_SCHEDULE_PLAIN ? 1024 : 256);
@@ -1109,6 +1109,14 @@ sop_status sop_set_list_skin(sop_ctx *c, double skin)
     if (c->bound && c->coords)
         HIP_TRY(c, hipMemcpyAsync(c->b.traj_cell, c->traj_cell.data(), c->n_traj * sizeof(int4),
                                   hipMemcpyHostToDevice, c->stream));
+    return SOP_OK;
+}
+
+sop_status sop_get_list_skin(const sop_ctx *c, double *skin)
+{
+    if (!c || !skin)
+        return SOP_E_ARG;
+    *skin = c->skin;
     return SOP_OK;
 }
 

@@ -56,7 +56,7 @@ struct GridDev {
 // Residues per cell of the list-rebuild grid (fixed capacity; more is the
 // list-overflow error).  A cell's edge is the search radius, 24 A by
 // default: at protein density (about 120 A^3 per residue) a cell holds some
-// 115 residues on average, so the capacity leaves room for twice that.
+// 115 residues on average.
 constexpr int CELL_CAP = 256;
 // Bonded plus native partners per residue (larger is rejected at load).
 constexpr int TOPO_CAP = 64;
