@@ -69,8 +69,9 @@ def copy_bandwidth(torch, mib=1024, reps=10):
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def host_cpu():
-    """CPU model and the number of cores this process may run on."""
+def host_cpu(raw=False):
+    """CPU model and the number of cores this process may run on (with raw,
+    also the count before the cap of 16 worker threads)."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -85,6 +86,8 @@ def host_cpu():
     except AttributeError:
         ncpu = os.cpu_count() or 1
     # the box's share of its host: at most 16 worker threads per GPU
+    if raw:
+        return model, max(1, min(ncpu, 16)), ncpu
     return model, max(1, min(ncpu, 16))
 
 
@@ -95,7 +98,7 @@ def cpu_baseline(P, np, system, params, n_steps, n_steps_par):
     agreement with it on the serial sample: the force error at the start and
     the largest coordinate difference after the sample's steps."""
     import oracle
-    model, ncpu = host_cpu()
+    model, ncpu, nproc = host_cpu(raw=True)
     o = oracle.OracleSystem(system, params)
     t0 = time.perf_counter()
     xp, _, _, st = o.run_par(system.x, n_steps_par, threads=ncpu)
@@ -131,6 +134,7 @@ def cpu_baseline(P, np, system, params, n_steps, n_steps_par):
                       f"{system.n_res}-residue workload, FP64, residue-parallel form on {ncpu} threads",
             "seconds": dt_par,
             "cpu_model": model,
+            "host_cpus_available": nproc,
             "single_thread": {"value": rate_1, "unit": "residue-steps/s", "cores": 1,
                               "sample": f"{n_steps} steps, serial form", "seconds": dt},
             "agreement": {
