@@ -1643,12 +1643,33 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     // the binning's slot and the displacement check's reference, requested
     // now so that they arrive during the list sums
     float4 hsk = make_float4(0.f, 0.f, 0.f, 0.f);
-    int bin_s0 = 0;
-    if (MODE == 0 && upd) {
-        if (a.check_thr2 > 0.0f)
-            hsk = a.hi_skin[iu];
-        if (a.do_bin)
-            bin_s0 = atomicAdd(&a.cell_count[cell_index(hu, a.traj_cell[__float_as_int(lu.w)], a.g)], 1);
+    if (MODE == 0 && upd && a.check_thr2 > 0.0f)
+        hsk = a.hi_skin[iu];
+    // the lanes of a wave that bin into one cell take consecutive slots
+    // from one atomic, issued by the group's first lane (uniform branch:
+    // the whole wave takes part in the ballots)
+    int bin_lead = 0, bin_rank = 0, bin_base = 0;
+    if (MODE == 0 && a.do_bin) {
+        const bool binning = upd;
+        const int c0 = binning ? cell_index(hu, a.traj_cell[__float_as_int(lu.w)], a.g) : -1;
+        const int lane = (int)__lane_id();
+        const unsigned long long below = (1ull << lane) - 1ull;
+        unsigned long long todo = __ballot(binning);
+        unsigned long long mine = 0ull;
+        while (todo) {
+            const int lead = __ffsll((long long)todo) - 1;
+            const int cl = __shfl(c0, lead);
+            const unsigned long long same = __ballot(binning && c0 == cl) & todo;
+            if ((same >> lane) & 1ull) {
+                bin_lead = lead;
+                bin_rank = __popcll(same & below);
+            }
+            if (lane == lead)
+                mine = same;
+            todo &= ~same;
+        }
+        if (binning && lane == bin_lead)
+            bin_base = atomicAdd(&a.cell_count[c0], __popcll(mine));
     }
     // ---- 3. list chunks of this lane ----
     Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
@@ -1739,6 +1760,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             e_s[3][rho] = vir;
         }
     }
+    // this residue's slot in its cell (the group's atomic has returned)
+    int bin_s0 = 0;
+    if (MODE == 0 && a.do_bin)
+        bin_s0 = __shfl(bin_base, bin_lead) + bin_rank;
     __syncthreads();
     if (!upd)
         return;

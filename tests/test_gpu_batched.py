@@ -97,6 +97,46 @@ def test_batched_trajectory_200_steps(P, orc, ens):
     assert np.array_equal(xg[ens.res_offsets[5]], c_first(P, ens)[ens.res_offsets[5]])
 
 
+def far_ensemble(ens):
+    """The ensemble with every trajectory moved 5e3-1e4 A from the origin in
+    a seeded direction (the cantilever's anchor with it), where a
+    coordinate's single-precision spacing is about 1e-3 A."""
+    import copy
+    s = copy.deepcopy(ens)
+    rng = np.random.default_rng(17)
+    for t in range(len(s.res_offsets) - 1):
+        v = rng.standard_normal(3)
+        v *= 1.0e4 * (0.5 + 0.5 * rng.random()) / np.linalg.norm(v)
+        s.x[s.res_offsets[t]:s.res_offsets[t + 1]] += v
+        for pl in s.pulls:
+            if pl.traj == t:
+                pl.anchor0 = pl.anchor0 + v
+    return s
+
+
+def test_batched_far_from_the_origin(P, orc, ens):
+    """Forces element by element and a 200-step trajectory with every
+    trajectory about 1e4 A out: the list pairs take the low parts too."""
+    s = far_ensemble(ens)
+    log(f"far ensemble: |x| up to {np.abs(s.x).max():.0f} A")
+    x = perturbed(s)
+    c = ctx(P, s, x=x)
+    F, E, _ = c.compute_forces()
+    o = orc.OracleSystem(s, RunParams())
+    Fo, Eo, _, S, Em = oracle_reference(o, x)
+    assert_forces(F, Fo, S, "batched far")
+    assert_energies(E, Eo, Em, s.res_offsets, "batched far")
+    c.close()
+    c = ctx(P, s, steps=50)
+    c.step(200)
+    xg = c.get_coordinates()
+    xo, _, _, st = o.run(s.x, 200)
+    assert st == 0
+    d = float(np.linalg.norm(xg - xo, axis=1).max())
+    log(f"batched far 200-step max |dx| {d:.3e} A")
+    assert d <= TRAJ_TOL
+
+
 def c_first(P, ens):
     return ctx(P, ens).get_coordinates()
 
