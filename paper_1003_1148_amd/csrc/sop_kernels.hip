@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
     // rows start 16-byte aligned); sized so that 64-residue tiles fit five
     // workgroups per CU
     constexpr int OUTW = TILE == 64 ? 184 : (TILE == 128 ? 96 : 48);
-    constexpr int PF = 8;      // row pieces per lane loaded up front
+    constexpr int PF = 6;      // row pieces per lane loaded up front
     constexpr int MAXP = 128;  // pieces of 8 entries in a row (cap <= 1024)
     // the staged positions (predicate) and the gathered rows (emit) share
     // one region
@@ -1055,9 +1055,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
     unsigned char *pb = pbits + rho * MAXP;
     // passing entries of this lane's first PF pieces, eight bits a piece, in
     // registers; later pieces (rows longer than 8 PF NL entries) in LDS
-    unsigned pbr[PF / 4] = {};
+    unsigned pbr[(PF + 3) / 4] = {};
     // the predicate, window by window of the staging set (one window for
     // nearly every tile): each entry is tested in the window holding its slot
+    const bool one_win = S <= SW;
     for (int w0 = 0; w0 < S || w0 == 0; w0 += SW) {
         const int wn = min(SW, S - w0);
         if (w0 > 0)
@@ -1065,26 +1066,33 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
         for (int sl = t; sl < wn; sl += 256)
             hs[sl] = a.pos[2 * st[w0 + sl]];
         __syncthreads();
-        // branch-free: the eight staged positions are read (an entry past
-        // the row's end or outside the window reads slot 0), then all eight
-        // are tested and the results masked
+        // branch-free: the eight staged positions are read, then all eight
+        // are tested and the results masked.  One window (nearly every
+        // tile): every entry of the row is a staged slot, and entries past
+        // the row's end (masked afterwards) are clamped into the window.
+        // Several windows: an entry outside the current one reads slot 0
+        // and is masked.
         auto test = [&](const uint4 &w, int pc) -> unsigned {
             const unsigned ws[4] = {w.x, w.y, w.z, w.w};
             const int valid = len - pc * 8;
-            float4 pj[8];
-            unsigned ok = 0u;
+            const unsigned tail = valid >= 8 ? 0xffu : (valid > 0 ? (1u << valid) - 1u : 0u);
+            unsigned ok = 0u, bits = 0u;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = (int)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu) - w0;
-                const bool in = (u < valid) & ((unsigned)e < (unsigned)wn);
-                ok |= (unsigned)in << u;
-                pj[u] = hs[in ? e : 0];
+            for (int h = 0; h < 8; h += 4) {  // four reads in flight, then their tests
+                float4 pj[4];
+#pragma unroll
+                for (int u = h; u < h + 4; ++u) {
+                    const unsigned sl = (ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
+                    const int e = (int)sl - w0;
+                    const bool in = one_win || (unsigned)e < (unsigned)wn;
+                    ok |= (unsigned)in << u;
+                    pj[u - h] = hs[one_win ? min(sl, (unsigned)(SW - 1)) : (in ? (unsigned)e : 0u)];
+                }
+#pragma unroll
+                for (int u = h; u < h + 4; ++u)
+                    bits |= (unsigned)within_cutoff(pi, pj[u - h], a.rc2) << u;
             }
-            unsigned bits = 0u;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                bits |= (unsigned)within_cutoff(pi, pj[u], a.rc2) << u;
-            return bits & ok;
+            return bits & ok & tail;
         };
 #pragma unroll
         for (int m = 0; m < PF; ++m)
@@ -1098,7 +1106,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
     // the row's passing entries, over the residue's lanes
     int tot = 0;
 #pragma unroll
-    for (int k = 0; k < PF / 4; ++k)
+    for (int k = 0; k < (PF + 3) / 4; ++k)
         tot += __popc(pbr[k]);
     for (int pc = PF * NL + q; pc < npc; pc += NL)
         tot += __popc((unsigned)pb[pc]);
@@ -1110,7 +1118,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
     // rows that fit (padding included) are gathered in LDS and written out
     // in 16-byte pieces
     const bool in_lds = ((tot + 7) & ~7) <= OUTW;
-    unsigned short *ob = in_lds ? out_s + rho * OUTW : dst;
+    unsigned short *ob_l = out_s + rho * OUTW;  // LDS
     int rounds = (npc + NL - 1) / NL;
 #pragma unroll
     for (int off = 1; off < NL; off <<= 1)
@@ -1127,11 +1135,21 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
             if (q >= off)
                 v += y;
         }
-        int o = base + v - c;
-        while (bits) {
-            const int u = __ffs(bits) - 1;
-            bits &= bits - 1u;
-            ob[o++] = (unsigned short)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+        const int o = base + v - c;
+        // passing entry u goes to o + (passing entries before it): unrolled
+        // stores, LDS for rows that fit, else straight to the list
+        if (in_lds) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if ((bits >> u) & 1u)
+                    ob_l[o + __popc(bits & ((1u << u) - 1u))] =
+                        (unsigned short)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+        } else {
+            for (int k = o; bits; ++k) {
+                const int u = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                dst[k] = (unsigned short)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+            }
         }
         base += __shfl(v, NL - 1, NL);
     };
@@ -1147,8 +1165,12 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a
         // pad the row to a multiple of 8 entries: with the LDS slot of the
         // far-away position when the tile fits one window, else the empty slot
         const unsigned short pad = S <= SW ? (unsigned short)SW : EMPTY_SLOT;
-        for (int k = base; k < ((base + 7) & ~7); ++k)
-            ob[k] = pad;
+        for (int k = base; k < ((base + 7) & ~7); ++k) {
+            if (in_lds)
+                ob_l[k] = pad;
+            else
+                dst[k] = pad;
+        }
         a.list_cnt[i] = base;
         lens[rho] = base;
     }
