@@ -16,7 +16,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sop_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SOP_ORACLE_LIB names another build of the same source (the sanitizer test
+# loads one built with AddressSanitizer and UndefinedBehaviorSanitizer)
+_LIB = os.environ.get("SOP_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 OK, E_ARG, E_FENE, E_OVERFLOW, E_NONFINITE, E_TIP = 0, -1, -5, -6, -7, -8
 NTERMS = 5

@@ -14,7 +14,9 @@ import re
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsop.so")
+# SOP_LIB names another build of the same sources (the sanitizer test loads
+# one whose host code is built with AddressSanitizer)
+LIB_PATH = os.environ.get("SOP_LIB") or os.path.join(_PKG, "libsop.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "sop.h")
 
 NTERMS = 5

@@ -997,7 +997,7 @@ struct FilterArgs {
 };
 
 template <int TILE>
-__global__ __launch_bounds__(256, TILE == 64 ? 5 : 3) void k_filter(FilterArgs a)
+__global__ __launch_bounds__(256, TILE == 64 ? 5 : (TILE == 128 ? 3 : 2)) void k_filter(FilterArgs a)
 {
     constexpr int NL = 256 / TILE;  // lanes per residue, adjacent in the wave
     constexpr int SM = stage_max<TILE>();
