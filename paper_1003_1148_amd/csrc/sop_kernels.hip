@@ -2151,7 +2151,7 @@ template <int WGS, int MODE>
 __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
 {
     constexpr int TCAP = 8 * WGS;  // bonded/native entries of a pack kept in LDS
-    __shared__ float4 shh[WGS + 1];     // hi per residue; slot WGS: the far-away empty slot
+    __shared__ float4 shh[WGS + 1];     // {hi.xyz, packed lo} per residue; slot WGS: the far-away empty slot
     __shared__ float4 shl[WGS + 1];     // lo per residue
     __shared__ double red[WGS];         // trajectory sums
     __shared__ unsigned short tpart[TCAP];  // bonded/native entries of the pack: local partner
@@ -2182,7 +2182,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         thi = a.traj_hi[i] + shift;
         row = a.trow[i];
         cnt = a.list_cnt[i];
-        shh[t] = hi;
+        shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low(hi, lo)));
         shl[t] = lo;
     }
     sres[t] = i;
@@ -2388,15 +2388,17 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             Acc L;  // the row's sum, pair by pair in row order
             auto chunk = [&](unsigned wx, unsigned wy) {
                 const unsigned idx[4] = {wx & 0xffffu, wx >> 16, wy & 0xffffu, wy >> 16};
-                float4 qh[4], ql[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    qh[u] = shh[idx[u]];
-                    ql[u] = shl[idx[u]];
-                }
+                // one 16-byte read a partner: the high part and its packed
+                // low part (a 10-bit multiple of ulp/1000 per axis)
+                float4 qh[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    add_repulsive_u(L, pair_delta(ph, pl, qh[u], ql[u]), kc, false);
+                    qh[u] = shh[idx[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float3 l = unpack_low(qh[u]);
+                    add_repulsive_u(L, pair_delta(ph, pl, qh[u], make_float4(l.x, l.y, l.z, 0.0f)), kc, false);
+                }
             };
             uint4 w = rp[0];
             for (int c2 = 0; c2 < nc2; ++c2) {
@@ -2481,7 +2483,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         }
         if (act) {
             langevin_update(hi, lo, A, step, stream, cn, a.err);
-            shh[t] = hi;
+            shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low(hi, lo)));
             shl[t] = lo;
         }
         __syncthreads();
