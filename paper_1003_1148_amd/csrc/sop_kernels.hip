@@ -1220,15 +1220,20 @@ template <int TILE>
 __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
 {
     constexpr int SM = stage_max<TILE>();
-    constexpr int G = 64;           // residues per pass
+    constexpr int G = 32;           // residues per pass
     constexpr int NLG = 256 / G;    // lanes per residue in a pass
     constexpr int MW = SM / 32;     // mask words per residue
+    constexpr int MWP = MW + 1;     // their stride: a residue's word w in another bank than its neighbour's
     constexpr int BW = 2048;        // bitmap words: ids spanning up to 65,536 values
-    __shared__ int sid[SM];
+    // the ranks (ids, bitmap, word prefixes) and the row masks use one
+    // region in turn, so that three workgroups fit a CU
+    constexpr int P1 = (SM + 2 * BW) * 4, P2 = G * MWP * 4;
+    __shared__ __align__(16) unsigned char region[P1 > P2 ? P1 : P2];
+    int *sid = reinterpret_cast<int *>(region);
+    unsigned *bmp = reinterpret_cast<unsigned *>(region + SM * 4);
+    int *wpre = reinterpret_cast<int *>(region + (SM + BW) * 4);
+    unsigned *mask = reinterpret_cast<unsigned *>(region);
     __shared__ unsigned short nslot[SM];
-    __shared__ unsigned mask[G * MW];
-    __shared__ unsigned bmp[BW];
-    __shared__ int wpre[BW];
     __shared__ int part[256];
     __shared__ int id_lo, id_hi;
     if (*a.skin_flag == 0u)
@@ -1242,11 +1247,23 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
         id_hi = -1;
     }
     __syncthreads();
-    for (int k = t; k < S; k += 256) {
-        const int id = st[k];
-        sid[k] = id;
-        atomicMin(&id_lo, id);
-        atomicMax(&id_hi, id);
+    {
+        int mn = 0x7fffffff, mx = -1;
+        for (int k = t; k < S; k += 256) {
+            const int id = st[k];
+            sid[k] = id;
+            mn = min(mn, id);
+            mx = max(mx, id);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {  // one atomic a wave
+            mn = min(mn, __shfl_xor(mn, off));
+            mx = max(mx, __shfl_xor(mx, off));
+        }
+        if ((t & 63) == 0) {
+            atomicMin(&id_lo, mn);
+            atomicMax(&id_hi, mx);
+        }
     }
     __syncthreads();
     // new slot = rank of the residue id among the tile's slots (ids distinct):
@@ -1288,10 +1305,11 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
     __syncthreads();
     for (int k = t; k < S; k += 256)
         st[nslot[k]] = sid[k];
+    __syncthreads();  // the ids are dead: the region takes the masks
     for (int g0 = 0; g0 < tcnt; g0 += G) {
         const int rho = g0 + t / NLG, q = t % NLG;
         const bool act = rho < tcnt && t / NLG < G;
-        for (int w = t; w < G * MW; w += 256)
+        for (int w = t; w < G * MWP; w += 256)
             mask[w] = 0u;
         __syncthreads();
         int len = 0;
@@ -1325,7 +1343,7 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
                 for (int u = 0; u < 8; ++u) {
                     if (pc * 8 + u < len) {
                         const int ns = nslot[(ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu];
-                        atomicOr(&mask[(t / NLG) * MW + (ns >> 5)], 1u << (ns & 31));
+                        atomicOr(&mask[(t / NLG) * MWP + (ns >> 5)], 1u << (ns & 31));
                     }
                 }
             }
@@ -1345,7 +1363,7 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
         int c = 0;
         if (act)
             for (int w = q * WPL; w < (q + 1) * WPL; ++w)
-                c += __popc(mask[(t / NLG) * MW + w]);
+                c += __popc(mask[(t / NLG) * MWP + w]);
         // entries before this lane's words: scan over the residue's lanes (adjacent)
         int v = c;
 #pragma unroll
@@ -1357,7 +1375,7 @@ __global__ __launch_bounds__(256) void k_canon(CanonArgs a)
         if (act) {
             int o = v - c;
             for (int w = q * WPL; w < (q + 1) * WPL; ++w) {
-                unsigned b = mask[(t / NLG) * MW + w];
+                unsigned b = mask[(t / NLG) * MWP + w];
                 while (b) {
                     const int kb = __ffs(b) - 1;
                     b &= b - 1u;
