@@ -458,7 +458,8 @@ sop_status need_ready(sop_ctx *c)
 // when there is no skin, or unless the displacement check of the step before
 // left it valid (graph replays capture rebuilds that rely on that check:
 // `captured`).
-void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false)
+// `filter` false: the step kernel that follows filters the skin rows.
+void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false, bool filter = true)
 {
     // in cadence: the step before was a period's last step, which binned its
     // positions and checked their displacements (a rebuild consumes the bins)
@@ -467,7 +468,7 @@ void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false)
     if (skin_check_thr2(c) <= 0.0f || !checked)
         launch_force_skin(c->b, s);
     launch_rebuild(c->b, c->cur, (int)c->n_res, c->cap, c->tile, c->grid, list_rc2(c), skin_rs2(c),
-                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every, binned);
+                   c->n_traj > 1 ? 1 : 0, s, advance, c->p.list_every, binned, filter);
     if (!captured)
         c->binned_at = -1;
 }
@@ -476,13 +477,22 @@ void rebuild(sop_ctx *c, hipStream_t s, bool advance, bool captured = false)
 // displacements against the skin.
 bool checks_skin(const sop_ctx *c, long long step) { return (step + 1) % c->p.list_every == 0; }
 
+// Whether the first step after a rebuild filters the skin rows itself: the
+// particle-based step kernel does, unless that step is also the period's
+// last (it would clear the cell counts it bins into).
+bool fuses_filter(const sop_ctx *c, bool check) { return c->force_mode == SOP_FORCES_PARTICLE && !check; }
+
 // `check`: the last step of a list period, which bins its new positions for
 // the next skin search and checks their displacements.
-void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy, bool check)
+// `first`: the first step after a rebuild launched without its filter,
+// which filters the skin rows itself.
+void one_step(sop_ctx *c, hipStream_t s, const long long *base, long long off, bool energy, bool check,
+              bool first = false)
 {
     launch_step(c->b, c->cur, (int)c->n_res, c->cap, c->tile, step_consts(c), c->tip,
                 c->pulls.empty() ? 0 : 1, energy, 0, base, off, check ? skin_check_thr2(c) : 0.0f, s,
-                c->force_mode, ud_kick(c), check ? &c->grid : nullptr);
+                c->force_mode, ud_kick(c), check ? &c->grid : nullptr, first ? list_rc2(c) : 0.0f,
+                c->grid.n_cells);
     if (energy)
         launch_reduce_energy(c->b, c->n_traj, s);
 }
@@ -549,10 +559,11 @@ sop_status capture_graph(sop_ctx *c, int par, int energy)
     const bool half_saved = c->ud_half;
     c->ud_half = false;  // graphs start only after the first (half-kick) step
     for (int q = 0; q < c->graph_steps; ++q) {
-        rebuild(c, c->cap_stream, true, true);
+        const bool fuse = fuses_filter(c, c->p.list_every == 1);
+        rebuild(c, c->cap_stream, true, true, !fuse);
         for (int k = 0; k < c->p.list_every; ++k) {
             one_step(c, c->cap_stream, c->b.step_base, k, energy && q == 0 && k == 0,
-                     k == c->p.list_every - 1);
+                     k == c->p.list_every - 1, fuse && k == 0);
             c->cur ^= 1;
         }
     }
@@ -1565,13 +1576,15 @@ sop_status sop_step(sop_ctx *c, int64_t n_steps)
             q += span;
             continue;
         }
-        if (!c->list_valid || c->step % L == 0) {
-            rebuild(c, c->stream, false);
-            c->list_valid = true;
-        }
         const bool en = E > 0 && c->step % E == 0;
         const bool chk = checks_skin(c, c->step);
-        one_step(c, c->stream, nullptr, c->step, en, chk);
+        bool fused = false;
+        if (!c->list_valid || c->step % L == 0) {
+            fused = fuses_filter(c, chk);
+            rebuild(c, c->stream, false, false, !fused);
+            c->list_valid = true;
+        }
+        one_step(c, c->stream, nullptr, c->step, en, chk, fused);
         c->ud_half = false;
         if (en)
             c->energy_step = c->step;

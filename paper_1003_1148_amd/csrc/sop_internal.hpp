@@ -136,12 +136,13 @@ struct StepConsts {
 // Plain schedule, tiles of `tile` residues (64, 128 or 256).
 // The skin search (the per-tile rows within sqrt(rs2) from the cell grid,
 // renumbered by residue id) runs only when the device skin flag is set; the
-// filter to rc2 always runs.  `binned`: the cells already hold the current
+// filter to rc2 runs unless `filter` is false (then the next step kernel
+// filters).  `binned`: the cells already hold the current
 // positions (binned by the last step kernel of the period); otherwise they
 // are cleared and filled first.
 void launch_rebuild(const DevBufs &b, int cur, int n_res, int cap, int tile, const GridDev &g,
                     float rc2, float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every,
-                    bool binned);
+                    bool binned, bool filter = true);
 // Sets the skin flag so that the next rebuild rebuilds the skin.
 void launch_force_skin(const DevBufs &b, hipStream_t s);
 // Clears the cells and bins every residue at its current position.
@@ -151,10 +152,15 @@ void launch_bin_all(const DevBufs &b, int cur, int n_res, const GridDev &g, hipS
 // last skin build sets the skin flag.
 // force_mode 0: particle-based (each residue sums its own rows); 1:
 // pair-based (each pair once, atomic accumulation, then the update kernel).
+// filter_rc2 > 0 (particle-based stepping only): the first step after a
+// rebuild launched without its filter (launch_rebuild, filter = false),
+// which filters the skin rows at filter_rc2 itself, then clears the
+// n_cells cell counts and the skin flag.
 void launch_step(const DevBufs &b, int cur, int n_res, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode,
                  const long long *step_base, long long step_off, float check_thr2, hipStream_t s,
-                 int force_mode = 0, float ud_kick = 0.0f, const GridDev *bin_grid = nullptr);
+                 int force_mode = 0, float ud_kick = 0.0f, const GridDev *bin_grid = nullptr,
+                 float filter_rc2 = 0.0f, int n_cells = 0);
 // Residues per chunk of the energy reduction (chunks never span trajectories).
 constexpr int ECHUNK = 1024;
 void launch_reduce_energy(const DevBufs &b, int n_traj, hipStream_t s);

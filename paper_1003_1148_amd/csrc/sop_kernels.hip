@@ -432,9 +432,11 @@ struct BuildArgs {
     const unsigned *skin_flag;
     float4 *hi_skin;
     unsigned long long *stats;
+    long long *step_base;  // graph replays: advanced once per rebuild, or NULL
+    long long *step_next;
     GridDev g;
     float rc2;
-    int n, cap;
+    int n, cap, period;
 };
 
 // Exclusive prefix sum over the NT lanes of a workgroup (all lanes call it).
@@ -525,6 +527,16 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
     __shared__ int part[NT];
     __shared__ int n_cu, n_extra, bad_cells, n_used_w;
 
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // every rebuild starts here (the kernels after it do not read these)
+        ++a.stats[0];
+        if (a.step_base) {
+            // graph replays: this rebuild starts the next list period
+            const long long nb = *a.step_next;
+            *a.step_base = nb;
+            *a.step_next = nb + a.period;
+        }
+    }
     if (*a.skin_flag == 0u)
         return;  // the skin rows are still valid (uniform over the grid)
     const int tile = blockIdx.x, t = threadIdx.x;
@@ -987,13 +999,10 @@ struct FilterArgs {
     int *list_cnt;
     int *cell_count;
     unsigned *skin_flag;
-    unsigned long long *stats;
     unsigned char *tile_ord;  // per tile: its residues by decreasing list length
     const unsigned short *skin_ord;  // per tile: 1 + its residues by decreasing skin row length
-    long long *step_base;     // graph replays: advanced once per rebuild, or NULL
-    long long *step_next;
     float rc2;
-    int cap, n_cells, period;
+    int cap, n_cells;
 };
 
 template <int TILE>
@@ -1022,16 +1031,8 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : (TILE == 128 ? 3 : 2)) void k
     // them for the next one; the flag is read only by the skin build too
     for (int k = tile * 256 + t; k < a.n_cells; k += gridDim.x * 256)
         a.cell_count[k] = 0;
-    if (tile == 0 && t == 0) {
+    if (tile == 0 && t == 0)
         *a.skin_flag = 0u;
-        ++a.stats[0];
-        if (a.step_base) {
-            // graph replays: this rebuild starts the next list period
-            const long long nb = *a.step_next;
-            *a.step_base = nb;
-            *a.step_next = nb + a.period;
-        }
-    }
     const int first = a.tile_first[tile], tcnt = a.tile_first[tile + 1] - first;
     const int S = min(a.stage_cnt[tile], SM);
     const int *st = a.stage + (size_t)tile * SM;
@@ -1437,6 +1438,17 @@ struct TileArgs {
     StepConsts c;
     UdConsts ud;
     TipDev tip;
+    // the first step of a list period filters the skin rows itself (FIRST):
+    // it writes the list rows, their counts and the longest-first order the
+    // later steps read, clears the cell counts and the skin flag
+    const unsigned short *skin16;
+    const int *skin_cnt;
+    const unsigned short *skin_ord;
+    unsigned short *list16_out;
+    int *list_cnt_out;
+    unsigned char *tile_ord_out;
+    float rc2;
+    int n_cells;
 };
 
 // Position relative to the tile's origin O as an unevaluated sum rh + rl:
@@ -1527,7 +1539,14 @@ constexpr float NARROW_TILE = 40.0f;
 //     which give every lane the same bits.
 //  4. After a second barrier the last TILE lanes add the external terms and
 //     the noise and take the compensated step (first-order, or BAOAB).
-template <int TILE, bool ENERGY, int MODE>
+// FIRST (the first step after a rebuild, which then needs no filter kernel):
+// the rows read are the skin rows, in the order of the last skin search
+// (longest first); the staging also keeps each slot's global high part, and
+// after the barrier each residue's lanes test their skin row pieces with the
+// list predicate and write the passing entries, in order, as its list row,
+// which the list sums then read back: the same rows, sums and bits as a
+// filter kernel followed by a plain step.
+template <int TILE, bool ENERGY, int MODE, bool FIRST>
 __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_tile_step(TileArgs a)
 {
     constexpr int NL = 256 / TILE;
@@ -1538,8 +1557,18 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     constexpr int PRE = 6;           // list chunks per lane loaded before the staging
     constexpr int TPRE = 2;          // bonded/native entries per lane loaded before the staging
     __shared__ float4 sl_s[SW + 1];  // {rh.xyz, packed rl}; slot SW: the far-away empty slot
+    __shared__ float hg_s[FIRST ? 3 * SW : 1];  // FIRST: each slot's global high part (x, y, z)
+    __shared__ int lens_s[FIRST ? TILE : 1];    // FIRST: list row lengths
     __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
     __shared__ double e_s[ENERGY ? 4 : 1][ENERGY ? TILE : 1];
+    if (FIRST) {
+        // the cell counts were read by the skin search, which is done:
+        // cleared for the binning at the end of this period; the flag too
+        for (int k = blockIdx.x * 256 + threadIdx.x; k < a.n_cells; k += gridDim.x * 256)
+            a.cell_count[k] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            *a.skin_flag = 0u;
+    }
     // XCD-aware order: consecutive tiles stay on one XCD's L2.
     const int per = gridDim.x >> 3;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -1555,7 +1584,13 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     const long long step = (a.step_base ? *a.step_base : 0) + a.step_off;
     const int q = t % NL;
     const bool act = t / NL < tcnt;
-    const int rho = act ? (int)a.tile_ord[(size_t)tile * TILE + t / NL] : 0;
+    int rho = 0;
+    if (FIRST) {
+        const int ord = act ? (int)a.skin_ord[(size_t)tile * TILE + t / NL] : 0;
+        rho = act ? (ord > 0 ? ord - 1 : t / NL) : 0;
+    } else {
+        rho = act ? (int)a.tile_ord[(size_t)tile * TILE + t / NL] : 0;
+    }
     const int i = first + rho;
     const int ue = t - EPI;
     const bool upd = ue >= 0 && ue < tcnt;
@@ -1568,19 +1603,34 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     float4 hi0 = make_float4(0.f, 0.f, 0.f, 0.f), lo0 = hi0;
     int2 row = make_int2(0, 0);
     int cnt = 0;
+    int slen = 0;  // FIRST: the skin row's length
     if (act) {
         hi0 = a.pin[2 * i];
         lo0 = a.pin[2 * i + 1];
         row = a.trow[i];
-        cnt = min(a.list_cnt[i], a.cap);
+        if (FIRST)
+            slen = min(a.skin_cnt[i], a.cap);
+        else
+            cnt = min(a.list_cnt[i], a.cap);
     }
     const float4 O = a.pin[2 * mid];
-    const int nch = (cnt + 3) >> 2;
+    int nch = (cnt + 3) >> 2;
     const uint2 *lp = reinterpret_cast<const uint2 *>(a.list16 + (size_t)i * a.cap);
-    uint2 lw[PRE];
+    constexpr int NPRE = FIRST ? 3 : PRE;
+    uint2 lw[NPRE];
+    constexpr int SPF = 1;  // FIRST: skin row pieces (8 entries) loaded up front
+    uint4 spre[SPF];
+    const uint4 *sp = reinterpret_cast<const uint4 *>(FIRST ? a.skin16 + (size_t)i * a.cap : nullptr);
+    const int npc = (slen + 7) >> 3;
+    if (FIRST) {
 #pragma unroll
-    for (int k = 0; k < PRE; ++k)
-        lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
+        for (int m = 0; m < SPF; ++m)
+            spre[m] = m * NL + q < npc ? sp[m * NL + q] : make_uint4(0u, 0u, 0u, 0u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k)
+            lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
+    }
     const int nb = row.y & 4095, ntop = nb + (row.y >> 12);
     // bonded entries: lane q takes bonds q, q + NL, ... and natives nb + q,
     // nb + q + NL, ..., in loops of their own so that a wave runs each
@@ -1630,14 +1680,21 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         if (ids[u] >= 0) {
+            const float4 gh = a.pin[2 * ids[u]];
             float4 rh, rl;
-            tile_frame(a.pin[2 * ids[u]], a.pin[2 * ids[u] + 1], O, rh, rl);
+            tile_frame(gh, a.pin[2 * ids[u] + 1], O, rh, rl);
             rh.w = 0.0f;
             sl_s[t + u * 256] = rh;
+            if (FIRST) {
+                hg_s[3 * (t + u * 256)] = gh.x;
+                hg_s[3 * (t + u * 256) + 1] = gh.y;
+                hg_s[3 * (t + u * 256) + 2] = gh.z;
+            }
         }
     }
     if (t == 0)
         sl_s[SW] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+
     const PairConsts k = pair_consts(a.c);
     Acc A;   // bonded and native terms
     bool broken = false;
@@ -1711,6 +1768,99 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         if (binning && lane == bin_lead)
             bin_base = atomicAdd(&a.cell_count[c0], __popcll(mine));
     }
+    if (FIRST) {
+        // ---- the list rows, filtered from the skin rows (Algorithm 3's
+        // predicate at r_list) and written in order ----
+        const bool one_win = S <= SW;
+        auto test = [&](const uint4 &w, int pc) -> unsigned {
+            const unsigned ws[4] = {w.x, w.y, w.z, w.w};
+            const int valid = slen - pc * 8;
+            const unsigned tail = valid >= 8 ? 0xffu : (valid > 0 ? (1u << valid) - 1u : 0u);
+            unsigned bits = 0u;
+#pragma unroll
+            for (int h = 0; h < 8; h += 4) {  // four reads in flight, then their tests
+                float4 pj[4];
+#pragma unroll
+                for (int u = h; u < h + 4; ++u) {
+                    const unsigned sl = (ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
+                    if (one_win) {
+                        // entries past the row's end (masked) clamped into the set
+                        const int e = (int)min(sl, (unsigned)(SW - 1));
+                        pj[u - h] = make_float4(hg_s[3 * e], hg_s[3 * e + 1], hg_s[3 * e + 2], 0.0f);
+                    } else {
+                        // rare: a set larger than one window reads the positions themselves
+                        pj[u - h] = a.pin[2 * st[min(sl, (unsigned)(SM - 1))]];
+                    }
+                }
+#pragma unroll
+                for (int u = h; u < h + 4; ++u)
+                    bits |= (unsigned)within_cutoff(hi0, pj[u - h], a.rc2) << u;
+            }
+            return bits & tail;
+        };
+        unsigned short *dst = a.list16_out + (size_t)i * a.cap;
+        int rounds = (npc + NL - 1) / NL;
+#pragma unroll
+        for (int off = 1; off < NL; off <<= 1)
+            rounds = max(rounds, __shfl_xor(rounds, off, NL));  // uniform over the residue's lanes
+        int base = 0;
+        // lane q's piece of this round: its passing entries go after those
+        // of the residue's earlier pieces
+        auto emit = [&](const uint4 &w, unsigned bits) {
+            const unsigned ws[4] = {w.x, w.y, w.z, w.w};
+            const int c = __popc(bits);
+            int v = c;
+#pragma unroll
+            for (int off = 1; off < NL; off <<= 1) {
+                const int y = __shfl_up(v, off, NL);
+                if (q >= off)
+                    v += y;
+            }
+            for (int k = base + v - c; bits; ++k) {
+                const int u = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                dst[k] = (unsigned short)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+            }
+            base += __shfl(v, NL - 1, NL);
+        };
+#pragma unroll
+        for (int m = 0; m < SPF; ++m)
+            if (m < rounds)
+                emit(spre[m], m * NL + q < npc ? test(spre[m], m * NL + q) : 0u);
+        for (int m = SPF; m < rounds; ++m) {
+            const int pc = m * NL + q;
+            const uint4 w = pc < npc ? sp[pc] : make_uint4(0u, 0u, 0u, 0u);
+            emit(w, pc < npc ? test(w, pc) : 0u);
+        }
+        if (act && q == NL - 1) {
+            // padded to a multiple of 8 entries: with the LDS slot of the
+            // far-away position when the set fits one window, else the empty slot
+            const unsigned short pad = S <= SW ? (unsigned short)SW : EMPTY_SLOT;
+            for (int k = base; k < ((base + 7) & ~7); ++k)
+                dst[k] = pad;
+            a.list_cnt_out[i] = base;
+            lens_s[rho] = base;
+        }
+        cnt = act ? base : 0;
+        nch = (cnt + 3) >> 2;
+        __syncthreads();  // the rows are written (read back below) and the lengths known
+        // the later steps hand the rows to their waves longest first (ties
+        // in index order): the residue's rank, counted by its NL lanes
+        int r = 0;
+        if (act)
+            for (int u = q * (TILE / NL); u < min(tcnt, (q + 1) * (TILE / NL)); ++u)
+                r += (lens_s[u] > base || (lens_s[u] == base && u < rho)) ? 1 : 0;
+#pragma unroll
+        for (int off = 1; off < NL; off <<= 1)
+            r += __shfl_xor(r, off, NL);
+        if (act && q == 0)
+            a.tile_ord_out[(size_t)tile * TILE + r] = (unsigned char)rho;
+        // the row's first chunks requested together, as the other steps do
+        // before their staging
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k)
+            lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
+    }
     // ---- 3. list chunks of this lane ----
     Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
     const float3 pl0 = unpack_low(rh0);
@@ -1748,10 +1898,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         if (!act)
             return;
 #pragma unroll
-        for (int kk = 0; kk < PRE; ++kk)
+        for (int kk = 0; kk < NPRE; ++kk)
             if (q + kk * NL < nch)
                 pairs4(lw[kk]);
-        for (int c = q + PRE * NL; c < nch; c += NL)
+        for (int c = q + NPRE * NL; c < nch; c += NL)
             pairs4(lp[c]);
     };
     if (!windowed) {
@@ -2669,13 +2819,9 @@ void canon_tile(const DevBufs &b, int cap, hipStream_t s)
 }
 
 template <int TILE>
-void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2, hipStream_t s,
-                 bool advance, int period)
+void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2, hipStream_t s)
 {
     FilterArgs a{};
-    a.step_base = advance ? b.step_base : nullptr;
-    a.step_next = b.step_next;
-    a.period = period;
     a.tile_first = b.tile_first[tile_index(TILE)];
     a.pos = b.pos[cur];
     a.stage = b.stage;
@@ -2686,7 +2832,6 @@ void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2
     a.list_cnt = b.fcnt;
     a.cell_count = b.cell_count;
     a.skin_flag = b.skin_flag;
-    a.stats = b.list_stats;
     a.tile_ord = b.tile_ord;
     a.skin_ord = b.skin_ord;
     a.rc2 = rc2;
@@ -2697,9 +2842,12 @@ void filter_tile(const DevBufs &b, int cur, int cap, const GridDev &g, float rc2
 
 template <int TILE>
 void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, float rc2, int multi,
-                  hipStream_t s)
+                  hipStream_t s, bool advance, int period)
 {
     BuildArgs a{};
+    a.step_base = advance ? b.step_base : nullptr;
+    a.step_next = b.step_next;
+    a.period = period;
     a.tile_first = b.tile_first[tile_index(TILE)];
     a.pos = b.pos[cur];
     a.cell_of = b.cell_of;
@@ -2730,46 +2878,50 @@ void rebuild_tile(const DevBufs &b, int cur, int n, int cap, const GridDev &g, f
         hipLaunchKernelGGL((k_tile_build<TILE, false>), dim3(nt), dim3(256), 0, s, a);
 }
 
-template <int TILE, bool ENERGY, int MODE>
+template <int TILE, bool ENERGY, int MODE, bool FIRST>
 void tile_step(const TileArgs &a, hipStream_t s)
 {
     const int blocks = ((a.n_tiles + 7) / 8) * 8;
     const TileArgs &x = a;
-    hipLaunchKernelGGL((k_tile_step<TILE, ENERGY, MODE>), dim3(blocks), dim3(256), 0, s, x);
+    hipLaunchKernelGGL((k_tile_step<TILE, ENERGY, MODE, FIRST>), dim3(blocks), dim3(256), 0, s, x);
 }
 
-template <bool ENERGY, int MODE>
+template <bool ENERGY, int MODE, bool FIRST = false>
 void tile_dispatch(int tile, const TileArgs &a, hipStream_t s)
 {
     switch (tile) {
-    case 64: tile_step<64, ENERGY, MODE>(a, s); break;
-    case 128: tile_step<128, ENERGY, MODE>(a, s); break;
-    default: tile_step<256, ENERGY, MODE>(a, s); break;
+    case 64: tile_step<64, ENERGY, MODE, FIRST>(a, s); break;
+    case 128: tile_step<128, ENERGY, MODE, FIRST>(a, s); break;
+    default: tile_step<256, ENERGY, MODE, FIRST>(a, s); break;
     }
 }
 
 }  // namespace
 
 void launch_rebuild(const DevBufs &b, int cur, int n, int cap, int tile, const GridDev &g, float rc2,
-                    float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every, bool binned)
+                    float rs2, int multi, hipStream_t s, bool advance_step_base, int list_every, bool binned,
+                    bool filter)
 {
     if (!binned)
         launch_bin_all(b, cur, n, g, s);  // not binned by a period's last step kernel
     switch (tile) {
     case 64:
-        rebuild_tile<64>(b, cur, n, cap, g, rs2, multi, s);
+        rebuild_tile<64>(b, cur, n, cap, g, rs2, multi, s, advance_step_base, list_every);
         canon_tile<64>(b, cap, s);
-        filter_tile<64>(b, cur, cap, g, rc2, s, advance_step_base, list_every);
+        if (filter)
+            filter_tile<64>(b, cur, cap, g, rc2, s);
         break;
     case 128:
-        rebuild_tile<128>(b, cur, n, cap, g, rs2, multi, s);
+        rebuild_tile<128>(b, cur, n, cap, g, rs2, multi, s, advance_step_base, list_every);
         canon_tile<128>(b, cap, s);
-        filter_tile<128>(b, cur, cap, g, rc2, s, advance_step_base, list_every);
+        if (filter)
+            filter_tile<128>(b, cur, cap, g, rc2, s);
         break;
     default:
-        rebuild_tile<256>(b, cur, n, cap, g, rs2, multi, s);
+        rebuild_tile<256>(b, cur, n, cap, g, rs2, multi, s, advance_step_base, list_every);
         canon_tile<256>(b, cap, s);
-        filter_tile<256>(b, cur, cap, g, rc2, s, advance_step_base, list_every);
+        if (filter)
+            filter_tile<256>(b, cur, cap, g, rc2, s);
         break;
     }
 }
@@ -2866,7 +3018,7 @@ void launch_pair_step(const DevBufs &b, int cur, int n, int cap, int tile, const
 void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const StepConsts &c,
                  const TipDev &tip, int has_pull, bool energy, int mode, const long long *step_base,
                  long long step_off, float check_thr2, hipStream_t s, int force_mode, float ud_kick,
-                 const GridDev *bin_grid)
+                 const GridDev *bin_grid, float filter_rc2, int n_cells)
 {
     // underdamped when ud_kick > 0 (velocities in b.vel)
     const float4 *vel = ud_kick > 0.0f ? b.vel : nullptr;
@@ -2915,6 +3067,22 @@ void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const Step
     a.has_pull = has_pull;
     a.c = c;
     a.tip = tip;
+    if (mode == 0 && filter_rc2 > 0.0f) {
+        // the first step after a rebuild, which filters the skin rows itself
+        a.skin16 = b.list16;
+        a.skin_cnt = b.list_cnt;
+        a.skin_ord = b.skin_ord;
+        a.list16_out = b.flist16;
+        a.list_cnt_out = b.fcnt;
+        a.tile_ord_out = b.tile_ord;
+        a.rc2 = filter_rc2;
+        a.n_cells = n_cells;
+        if (energy)
+            tile_dispatch<true, 0, true>(tile, a, s);
+        else
+            tile_dispatch<false, 0, true>(tile, a, s);
+        return;
+    }
     if (mode == 1) {
         if (energy)
             tile_dispatch<true, 1>(tile, a, s);
