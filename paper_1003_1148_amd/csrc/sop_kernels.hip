@@ -1827,9 +1827,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         for (int m = 0; m < SPF; ++m)
             if (m < rounds)
                 emit(spre[m], m * NL + q < npc ? test(spre[m], m * NL + q) : 0u);
+        // later pieces: the next one requested before the current one is used
+        uint4 wn = SPF * NL + q < npc ? sp[SPF * NL + q] : make_uint4(0u, 0u, 0u, 0u);
         for (int m = SPF; m < rounds; ++m) {
             const int pc = m * NL + q;
-            const uint4 w = pc < npc ? sp[pc] : make_uint4(0u, 0u, 0u, 0u);
+            const uint4 w = wn;
+            wn = pc + NL < npc ? sp[pc + NL] : make_uint4(0u, 0u, 0u, 0u);
             emit(w, pc < npc ? test(w, pc) : 0u);
         }
         if (act && q == NL - 1) {
