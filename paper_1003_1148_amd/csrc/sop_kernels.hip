@@ -4,6 +4,7 @@
 // Eq. 2 / Algorithm 7 with compensated single-precision positions), and the
 // double-precision energy reduction.
 #include <algorithm>
+#include <type_traits>
 
 #include "sop_internal.hpp"
 #include "sop_rng.hpp"
@@ -410,7 +411,7 @@ constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640
 template <int TILE>
 constexpr int chash_bits() { return TILE == 128 ? 11 : 10; }
 constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
-constexpr int TREG = 20;        // bonded/native entries per residue kept in registers
+constexpr int TREG = 12;        // bonded/native entries per residue kept in registers (more: global)
 
 struct BuildArgs {
     const int *tile_first;  // first residue of each tile, then n
@@ -1557,7 +1558,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     constexpr int PRE = 6;           // list chunks per lane loaded before the staging
     constexpr int TPRE = 2;          // bonded/native entries per lane loaded before the staging
     __shared__ float4 sl_s[SW + 1];  // {rh.xyz, packed rl}; slot SW: the far-away empty slot
-    __shared__ float hg_s[FIRST ? 3 * SW : 1];  // FIRST: each slot's global high part (x, y, z)
+    __shared__ float hg_s[3][FIRST ? SW : 1];  // FIRST: each slot's global high part, by axis
     __shared__ int lens_s[FIRST ? TILE : 1];    // FIRST: list row lengths
     __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
     __shared__ double e_s[ENERGY ? 4 : 1][ENERGY ? TILE : 1];
@@ -1686,9 +1687,9 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             rh.w = 0.0f;
             sl_s[t + u * 256] = rh;
             if (FIRST) {
-                hg_s[3 * (t + u * 256)] = gh.x;
-                hg_s[3 * (t + u * 256) + 1] = gh.y;
-                hg_s[3 * (t + u * 256) + 2] = gh.z;
+                hg_s[0][t + u * 256] = gh.x;
+                hg_s[1][t + u * 256] = gh.y;
+                hg_s[2][t + u * 256] = gh.z;
             }
         }
     }
@@ -1771,8 +1772,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     if (FIRST) {
         // ---- the list rows, filtered from the skin rows (Algorithm 3's
         // predicate at r_list) and written in order ----
-        const bool one_win = S <= SW;
-        auto test = [&](const uint4 &w, int pc) -> unsigned {
+        // ONE (compile time): the set fits one LDS window, as for nearly
+        // every tile; the round loop below is compiled once for each case
+        auto test = [&](const uint4 &w, int pc, auto one) -> unsigned {
+            constexpr bool ONE = decltype(one)::value;
             const unsigned ws[4] = {w.x, w.y, w.z, w.w};
             const int valid = slen - pc * 8;
             const unsigned tail = valid >= 8 ? 0xffu : (valid > 0 ? (1u << valid) - 1u : 0u);
@@ -1783,10 +1786,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
 #pragma unroll
                 for (int u = h; u < h + 4; ++u) {
                     const unsigned sl = (ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
-                    if (one_win) {
+                    if constexpr (ONE) {
                         // entries past the row's end (masked) clamped into the set
                         const int e = (int)min(sl, (unsigned)(SW - 1));
-                        pj[u - h] = make_float4(hg_s[3 * e], hg_s[3 * e + 1], hg_s[3 * e + 2], 0.0f);
+                        pj[u - h] = make_float4(hg_s[0][e], hg_s[1][e], hg_s[2][e], 0.0f);
                     } else {
                         // rare: a set larger than one window reads the positions themselves
                         pj[u - h] = a.pin[2 * st[min(sl, (unsigned)(SM - 1))]];
@@ -1816,25 +1819,39 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
                 if (q >= off)
                     v += y;
             }
-            for (int k = base + v - c; bits; ++k) {
-                const int u = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                dst[k] = (unsigned short)((ws[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+            // entry u goes after the passing entries below it: eight masked
+            // stores, not a loop as long as the wave's longest run
+            unsigned short *d = dst + (base + v - c);
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {  // the piece's two halves, four entries each
+                const unsigned w0 = h ? ws[2] : ws[0], w1 = h ? ws[3] : ws[1];
+                const unsigned hb = bits >> (4 * h);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if ((hb >> u) & 1u)
+                        d[__popc(hb & ((1u << u) - 1u))] = (unsigned short)((u < 2 ? w0 : w1) >> ((u & 1) * 16));
+                d += __popc(hb & 0xfu);
             }
             base += __shfl(v, NL - 1, NL);
         };
+        auto filter_rows = [&](auto one) {
 #pragma unroll
-        for (int m = 0; m < SPF; ++m)
-            if (m < rounds)
-                emit(spre[m], m * NL + q < npc ? test(spre[m], m * NL + q) : 0u);
-        // later pieces: the next one requested before the current one is used
-        uint4 wn = SPF * NL + q < npc ? sp[SPF * NL + q] : make_uint4(0u, 0u, 0u, 0u);
-        for (int m = SPF; m < rounds; ++m) {
-            const int pc = m * NL + q;
-            const uint4 w = wn;
-            wn = pc + NL < npc ? sp[pc + NL] : make_uint4(0u, 0u, 0u, 0u);
-            emit(w, pc < npc ? test(w, pc) : 0u);
-        }
+            for (int m = 0; m < SPF; ++m)
+                if (m < rounds)
+                    emit(spre[m], m * NL + q < npc ? test(spre[m], m * NL + q, one) : 0u);
+            // later pieces: the next one requested before the current one is used
+            uint4 wn = SPF * NL + q < npc ? sp[SPF * NL + q] : make_uint4(0u, 0u, 0u, 0u);
+            for (int m = SPF; m < rounds; ++m) {
+                const int pc = m * NL + q;
+                const uint4 w = wn;
+                wn = pc + NL < npc ? sp[pc + NL] : make_uint4(0u, 0u, 0u, 0u);
+                emit(w, pc < npc ? test(w, pc, one) : 0u);
+            }
+        };
+        if (S <= SW)
+            filter_rows(std::true_type{});
+        else
+            filter_rows(std::false_type{});
         if (act && q == NL - 1) {
             // padded to a multiple of 8 entries: with the LDS slot of the
             // far-away position when the set fits one window, else the empty slot
@@ -1869,19 +1886,24 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     const float3 pl0 = unpack_low(rh0);
     // slot -> LDS index of the current window (identity for one window)
     int w0 = 0, wn = S;
-    auto pairs4 = [&](const uint2 &w) {
+    // FORM: 0 high parts, 1 high and low parts, 2 high and low parts of one
+    // window (compile-time copies of `wide` and `windowed`, so that each list
+    // loop holds one form)
+    auto pairs4 = [&](const uint2 &w, auto form) {
+        constexpr int FORM = decltype(form)::value;
+        constexpr bool WIDE = FORM > 0;
         float4 pj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int sl = (int)(((u < 2 ? w.x : w.y) >> ((u & 1) * 16)) & 0xffffu);
-            if (windowed) {
+            if constexpr (FORM == 2) {
                 const int e = sl - w0;
                 pj[u] = sl_s[(unsigned)e < (unsigned)wn ? e : SW];
             } else {
                 pj[u] = sl_s[sl];
             }
         }
-        if (!wide) {
+        if constexpr (!WIDE) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 add_repulsive_u(L, make_float3(rh0.x - pj[u].x, rh0.y - pj[u].y, rh0.z - pj[u].z), k,
@@ -1897,18 +1919,21 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             }
         }
     };
-    auto list_pass = [&]() {
+    auto list_pass = [&](auto form) {
         if (!act)
             return;
 #pragma unroll
         for (int kk = 0; kk < NPRE; ++kk)
             if (q + kk * NL < nch)
-                pairs4(lw[kk]);
+                pairs4(lw[kk], form);
         for (int c = q + NPRE * NL; c < nch; c += NL)
-            pairs4(lp[c]);
+            pairs4(lp[c], form);
     };
     if (!windowed) {
-        list_pass();
+        if (wide)
+            list_pass(std::integral_constant<int, 1>{});
+        else
+            list_pass(std::integral_constant<int, 0>{});
     } else {
         // every window's slots staged with their low parts; each entry
         // contributes in the window holding its slot (elsewhere it reads the
@@ -1924,7 +1949,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
                 sl_s[sl] = rh;
             }
             __syncthreads();
-            list_pass();
+            list_pass(std::integral_constant<int, 2>{});
         }
     }
     // the residue's total over its NL lanes (butterfly: every lane gets the same bits)
