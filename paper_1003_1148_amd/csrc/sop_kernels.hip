@@ -411,7 +411,7 @@ constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640
 template <int TILE>
 constexpr int chash_bits() { return TILE == 128 ? 11 : 10; }
 constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
-constexpr int TREG = 12;        // bonded/native entries per residue kept in registers (more: global)
+constexpr int TREG = 12;  // bonded/native entries per residue kept in registers during a search (more: global)
 
 struct BuildArgs {
     const int *tile_first;  // first residue of each tile, then n
@@ -781,7 +781,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
             if (__any(reach)) {
                 // branch-free: BB LDS reads in flight, then the tests; the
                 // window's tail and inactive lanes are masked afterwards
-                constexpr int BB = TILE == 64 ? 4 : 8;
+                constexpr int BB = TILE == 64 ? (MULTI ? 2 : 4) : 8;
 #pragma unroll 1
                 for (int k0 = 0; k0 < 32; k0 += BB) {
                     float4 c8[BB];
@@ -2570,119 +2570,134 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             }
             assign();  // its barriers also publish the rows written above
         }
-        // mode 0 never records (no FP64 sums in its registers), mode 2
-        // records at multiples of the energy interval
-        const bool rec = MODE == 1 || (MODE == 2 && a.energy_every > 0 && step % a.energy_every == 0);
-        {
-            // ---- list partners (forces) of the row this lane was given ----
-            const int r = my & 0xffff, nch = my >> 16;
-            const float4 ph = shh[r], pl = shl[r];
-            // rows are read two chunks (16 bytes) at a time, the next pair
-            // requested before the current one is used
-            const uint4 *rp = reinterpret_cast<const uint4 *>(a.list + (size_t)myg * a.cap);
-            const int nc2 = (nch + 1) >> 1;
-            Acc L;  // the row's sum, pair by pair in row order
-            auto chunk = [&](unsigned wx, unsigned wy) {
-                const unsigned idx[4] = {wx & 0xffffu, wx >> 16, wy & 0xffffu, wy >> 16};
-                // one 16-byte read a partner: the high part and its packed
-                // low part (a 10-bit multiple of ulp/1000 per axis)
-                float4 qh[4];
+        // mode 0 never records (no FP64 sums in its registers); mode 2
+        // records at multiples of the energy interval, in a copy of the
+        // forces and update compiled for record steps alone
+        const bool rec_step = MODE == 1 || (MODE == 2 && a.energy_every > 0 && step % a.energy_every == 0);
+        auto forces_and_update = [&](auto rec_tag) {
+            constexpr bool rec = decltype(rec_tag)::value;
+            {
+                // ---- list partners (forces) of the row this lane was given ----
+                const int r = my & 0xffff, nch = my >> 16;
+                const float4 ph = shh[r], pl = shl[r];
+                // rows are read two chunks (16 bytes) at a time, the next pair
+                // requested before the current one is used
+                const uint4 *rp = reinterpret_cast<const uint4 *>(a.list + (size_t)myg * a.cap);
+                const int nc2 = (nch + 1) >> 1;
+                Acc L;  // the row's sum, pair by pair in row order
+                auto chunk = [&](unsigned wx, unsigned wy) {
+                    const unsigned idx[4] = {wx & 0xffffu, wx >> 16, wy & 0xffffu, wy >> 16};
+                    // one 16-byte read a partner: the high part and its packed
+                    // low part (a 10-bit multiple of ulp/1000 per axis)
+                    float4 qh[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    qh[u] = shh[idx[u]];
+                    for (int u = 0; u < 4; ++u)
+                        qh[u] = shh[idx[u]];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float3 l = unpack_low(qh[u]);
-                    add_repulsive_u(L, pair_delta(ph, pl, qh[u], make_float4(l.x, l.y, l.z, 0.0f)), kc, false);
+                    for (int u = 0; u < 4; ++u) {
+                        const float3 l = unpack_low(qh[u]);
+                        add_repulsive_u(L, pair_delta(ph, pl, qh[u], make_float4(l.x, l.y, l.z, 0.0f)), kc, false);
+                    }
+                };
+                uint4 w = rp[0];
+                for (int c2 = 0; c2 < nc2; ++c2) {
+                    const uint4 wn = rp[min(c2 + 1, nc2 - 1)];
+                    chunk(w.x, w.y);
+                    if (2 * c2 + 1 < nch)  // the second chunk of an odd row's last pair is not written
+                        chunk(w.z, w.w);
+                    w = wn;
                 }
-            };
-            uint4 w = rp[0];
-            for (int c2 = 0; c2 < nc2; ++c2) {
-                const uint4 wn = rp[min(c2 + 1, nc2 - 1)];
-                chunk(w.x, w.y);
-                if (2 * c2 + 1 < nch)  // the second chunk of an odd row's last pair is not written
-                    chunk(w.z, w.w);
-                w = wn;
-            }
-            if (t < n) {
-                lsum[0][r] = kc.c6 * L.fx;
-                lsum[1][r] = kc.c6 * L.fy;
-                lsum[2][r] = kc.c6 * L.fz;
-            }
-        }
-        Acc A;  // energy sums are only accumulated on record steps
-        bool broken = false;
-        double e_x = 0.0, f_rep = 0.0;
-        if (act) {
-            // bonded, then native partners: two loops, so a wave whose
-            // residues have different bond counts (chain ends) runs each
-            // term's code alone
-            auto entry = [&](int e, int &j, float &r0) {
-                if (toff + e < TCAP) {
-                    j = tpart[toff + e];
-                    r0 = tr0[toff + e];
-                } else {
-                    const float2 te = a.tent[row.x + e];
-                    j = __float_as_int(te.x) + shift;
-                    r0 = te.y;
+                if (t < n) {
+                    lsum[0][r] = kc.c6 * L.fx;
+                    lsum[1][r] = kc.c6 * L.fy;
+                    lsum[2][r] = kc.c6 * L.fz;
                 }
-            };
-            for (int e = 0; e < nb; ++e) {
-                int j;
-                float r0;
-                entry(e, j, r0);
-                add_fene(A, hi, lo, shh[j], shl[j], r0, kc, rec, broken);
             }
-            for (int e = nb; e < ntop; ++e) {
-                int j;
-                float r0;
-                entry(e, j, r0);
-                add_native(A, hi, lo, shh[j], shl[j], r0, kc, rec);
+            Acc A;  // energy sums are only accumulated on record steps
+            bool broken = false;
+            double e_x = 0.0, f_rep = 0.0;
+            if (act) {
+                // bonded, then native partners: two loops, so a wave whose
+                // residues have different bond counts (chain ends) runs each
+                // term's code alone
+                auto entry = [&](int e, int &j, float &r0) {
+                    if (toff + e < TCAP) {
+                        j = tpart[toff + e];
+                        r0 = tr0[toff + e];
+                    } else {
+                        const float2 te = a.tent[row.x + e];
+                        j = __float_as_int(te.x) + shift;
+                        r0 = te.y;
+                    }
+                };
+                for (int e = 0; e < nb; ++e) {
+                    int j;
+                    float r0;
+                    entry(e, j, r0);
+                    add_fene(A, hi, lo, shh[j], shl[j], r0, kc, rec, broken);
+                }
+                for (int e = nb; e < ntop; ++e) {
+                    int j;
+                    float r0;
+                    entry(e, j, r0);
+                    add_native(A, hi, lo, shh[j], shl[j], r0, kc, rec);
+                }
+                add_external(A, e_x, f_rep, hi, lo, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
+                             a.tip, rec, a.err);
+                if (broken)
+                    atomicOr(a.err, ERR_FENE);
+                if (rec) {
+                    // record steps: the repulsive energy and virial over the own row
+                    Acc E;
+                    for (int k = 0; k < min(cnt, a.cap); ++k)
+                        add_repulsive_d(E, pair_delta(hi, lo, shh[lrow16[k]], shl[lrow16[k]]), kc, true);
+                    A.e_r = E.e_r;
+                    A.vir += E.vir;
+                }
             }
-            add_external(A, e_x, f_rep, hi, lo, step, a.c.h, a.has_pull ? a.pull_slot[i] : -1, a.pulls,
-                         a.tip, rec, a.err);
-            if (broken)
-                atomicOr(a.err, ERR_FENE);
+            __syncthreads();
+            if (act) {
+                A.fx += lsum[0][t];
+                A.fy += lsum[1][t];
+                A.fz += lsum[2][t];
+            }
             if (rec) {
-                // record steps: the repulsive energy and virial over the own row
-                Acc E;
-                for (int k = 0; k < min(cnt, a.cap); ++k)
-                    add_repulsive_d(E, pair_delta(hi, lo, shh[lrow16[k]], shl[lrow16[k]]), kc, true);
-                A.e_r = E.e_r;
-                A.vir += E.vir;
-            }
-        }
-        __syncthreads();
-        if (act) {
-            A.fx += lsum[0][t];
-            A.fy += lsum[1][t];
-            A.fz += lsum[2][t];
-        }
-        if (rec) {
-            // each internal pair appears in both partners' rows
-            const double vals[RES_E] = {0.5 * A.e_b, 0.5 * A.e_n, 0.5 * A.e_r, e_x, 0.5 * A.vir, f_rep};
+                // each internal pair appears in both partners' rows
+                const double vals[RES_E] = {0.5 * A.e_b, 0.5 * A.e_n, 0.5 * A.e_r, e_x, 0.5 * A.vir, f_rep};
 #pragma unroll
-            for (int kk = 0; kk < RES_E; ++kk) {
-                const double sum = traj_sum(red, t, act, vals[kk], tlo, thi);
-                if (act && t == tlo) {
-                    if (kk < SOP_NTERMS)
-                        a.energy[(size_t)traj * SOP_NTERMS + kk] = sum;
-                    else
-                        a.f_ext[traj] = sum;
+                for (int kk = 0; kk < RES_E; ++kk) {
+                    const double sum = traj_sum(red, t, act, vals[kk], tlo, thi);
+                    if (act && t == tlo) {
+                        if (kk < SOP_NTERMS)
+                            a.energy[(size_t)traj * SOP_NTERMS + kk] = sum;
+                        else
+                            a.f_ext[traj] = sum;
+                    }
                 }
             }
-        }
-        if (MODE == 1) {
-            if (act)
-                a.fout[i] = make_float4(A.fx, A.fy, A.fz, 0.0f);
+            if (MODE == 1) {
+                if (act)
+                    a.fout[i] = make_float4(A.fx, A.fy, A.fz, 0.0f);
+                return;
+            }
+            if (act) {
+                langevin_update(hi, lo, A, step, stream, cn, a.err);
+                shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low(hi, lo)));
+                shl[t] = lo;
+            }
+            __syncthreads();
+        };
+        if constexpr (MODE == 1) {
+            forces_and_update(std::true_type{});
             return;
+        } else if constexpr (MODE == 0) {
+            forces_and_update(std::false_type{});
+        } else {
+            if (rec_step)
+                forces_and_update(std::true_type{});
+            else
+                forces_and_update(std::false_type{});
         }
-        if (act) {
-            langevin_update(hi, lo, A, step, stream, cn, a.err);
-            shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low(hi, lo)));
-            shl[t] = lo;
-        }
-        __syncthreads();
     }
     if (MODE != 1 && act) {
         a.pout[2 * i] = hi;
