@@ -411,7 +411,7 @@ constexpr int cells_max() { return TILE >= 256 ? 512 : (TILE >= 128 ? 1024 : 640
 template <int TILE>
 constexpr int chash_bits() { return TILE == 128 ? 11 : 10; }
 constexpr int EXTRA_MAX = 128;  // bonded/native partners outside the tile's cells
-constexpr int TREG = 12;  // bonded/native entries per residue kept in registers during a search (more: global)
+constexpr int TREG = 8;  // bonded/native entries per residue kept in registers during a search (more: global)
 
 struct BuildArgs {
     const int *tile_first;  // first residue of each tile, then n
@@ -684,9 +684,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
         if (t == 0)
             cbase[NC] = M;
     }
-    // this part's entries beyond TREG live in the topology output meanwhile
-    if (lead)
-        for (int e = TREG; e < ntop; ++e)
+    // entries beyond TREG live in the topology output meanwhile; entry
+    // e >= TREG belongs to part (e - TREG) mod NLB throughout
+    if (act)
+        for (int e = TREG + q; e < ntop; e += NLB)
             trw[(size_t)e * TILE] = make_uint2(CODE_NONE, __float_as_uint(a.tent[row.x + e].y));
     __syncthreads();
     // partners' cells -> sorted cell numbers (or -1 outside the tile's cells)
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
             if (__any(reach)) {
                 // branch-free: BB LDS reads in flight, then the tests; the
                 // window's tail and inactive lanes are masked afterwards
-                constexpr int BB = TILE == 64 ? (MULTI ? 2 : 4) : 8;
+                constexpr int BB = TILE == 64 ? 4 : 8;
 #pragma unroll 1
                 for (int k0 = 0; k0 < 32; k0 += BB) {
                     float4 c8[BB];
@@ -831,7 +832,9 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
             const int rs = find(i, own_m);
             if (rs >= 0)
                 atomicAnd(&bits[(rs >> 5) * TILE + rho], ~(1u << (rs & 31)));
-            for (int e = TREG; e < ntop; ++e) {
+        }
+        if (act) {
+            for (int e = TREG + q; e < ntop; e += NLB) {
                 if (trw[(size_t)e * TILE].x != CODE_NONE)
                     continue;
                 const int j = __float_as_int(a.tent[row.x + e].x);
@@ -910,12 +913,11 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
             for (int v = 0; v < TPP; ++v)
                 if (tcode[v] != CODE_NONE && (tcode[v] & CODE_WINDOW))
                     tcode[v] = slot_of(tcode[v]);
-            if (lead)
-                for (int e = TREG; e < ntop; ++e) {
-                    const unsigned v = trw[(size_t)e * TILE].x;
-                    if (v != CODE_NONE && (v & CODE_WINDOW))
-                        trw[(size_t)e * TILE].x = slot_of(v);
-                }
+            for (int e = TREG + q; e < ntop; e += NLB) {
+                const unsigned v = trw[(size_t)e * TILE].x;
+                if (v != CODE_NONE && (v & CODE_WINDOW))
+                    trw[(size_t)e * TILE].x = slot_of(v);
+            }
         }
         slot_base += nu;
         mA = mB;
@@ -938,14 +940,13 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
                     extra[k] = tj[v];
                 tcode[v] = CODE_EXTRA | (unsigned)k;
             }
-        if (lead)
-            for (int e = TREG; e < ntop; ++e)
-                if (trw[(size_t)e * TILE].x == CODE_NONE) {
-                    const int k = atomicAdd(&n_extra, 1);
-                    if (k < EXTRA_MAX)
-                        extra[k] = __float_as_int(a.tent[row.x + e].x);
-                    trw[(size_t)e * TILE].x = CODE_EXTRA | (unsigned)k;
-                }
+        for (int e = TREG + q; e < ntop; e += NLB)
+            if (trw[(size_t)e * TILE].x == CODE_NONE) {
+                const int k = atomicAdd(&n_extra, 1);
+                if (k < EXTRA_MAX)
+                    extra[k] = __float_as_int(a.tent[row.x + e].x);
+                trw[(size_t)e * TILE].x = CODE_EXTRA | (unsigned)k;
+            }
     }
     __syncthreads();
     const int n_ex = n_extra;
@@ -967,10 +968,10 @@ __global__ __launch_bounds__(256, TILE == 64 ? 5 : 2) void k_tile_build(BuildArg
     for (int v = 0; v < TPP; ++v)
         if (v * NLB + q < ntop)
             trw[(size_t)(v * NLB + q) * TILE] = make_uint2(final_slot(tcode[v]), tr0[v]);
+    for (int e = TREG + q; e < ntop; e += NLB)
+        trw[(size_t)e * TILE].x = final_slot(trw[(size_t)e * TILE].x);
     if (!lead)
         return;
-    for (int e = TREG; e < ntop; ++e)
-        trw[(size_t)e * TILE].x = final_slot(trw[(size_t)e * TILE].x);
     // count; the last chunk padded with the empty slot
     const int cnt = rowbase[rho];
     for (int k = cnt; k < ((cnt + 3) & ~3); ++k)
