@@ -430,8 +430,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the ensemble shards with no communication; see the design notes).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(an ensemble shards by trajectory with no communication).",
               file=sys.stderr)
         sys.exit(2)
 

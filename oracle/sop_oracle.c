@@ -25,8 +25,7 @@
  *   - update: the first-order Ermak-McCammon scheme of Eq. 2 / Algorithm 7,
  *     r <- r + f h/xi + g sqrt(2 kB T h/xi), every force taken at r(t_n).
  *
- * Readings of the paper that this code takes (each is listed with its reason
- * in the design notes of the repository):
+ * Readings of the paper that this code takes, each with its reason:
  *   - Eq. 2 prints f*xi*h; Algorithm 7 prints f*h/xi.  h/xi is taken (it is
  *     the dimensionally consistent form).
  *   - The third sum of Eq. 1 is garbled; it is read as the i,i+2 repulsion
