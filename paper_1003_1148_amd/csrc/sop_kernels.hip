@@ -1559,6 +1559,12 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     constexpr int PRE = 6;           // list chunks per lane loaded before the staging
     constexpr int TPRE = 2;          // bonded/native entries per lane loaded before the staging
     __shared__ float4 sl_s[SW + 1];  // {rh.xyz, packed rl}; slot SW: the far-away empty slot
+    // SOA: the same high parts by axis, read by the list sums of compact
+    // tiles: three 4-byte reads a partner spread over all banks, where
+    // 16-byte elements start on one bank in four (not in the first step or
+    // with 2,048-slot windows, short of LDS)
+    constexpr bool SOA = !FIRST && SW <= 1024;
+    __shared__ float sr_s[3][SOA ? SW + 1 : 1];
     __shared__ float hg_s[3][FIRST ? SW : 1];  // FIRST: each slot's global high part, by axis
     __shared__ int lens_s[FIRST ? TILE : 1];    // FIRST: list row lengths
     __shared__ float f_s[3][TILE];   // list + bonded/native force of each residue
@@ -1687,6 +1693,11 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             tile_frame(gh, a.pin[2 * ids[u] + 1], O, rh, rl);
             rh.w = 0.0f;
             sl_s[t + u * 256] = rh;
+            if (SOA) {
+                sr_s[0][t + u * 256] = rh.x;
+                sr_s[1][t + u * 256] = rh.y;
+                sr_s[2][t + u * 256] = rh.z;
+            }
             if (FIRST) {
                 hg_s[0][t + u * 256] = gh.x;
                 hg_s[1][t + u * 256] = gh.y;
@@ -1694,8 +1705,11 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             }
         }
     }
-    if (t == 0)
+    if (t == 0) {
         sl_s[SW] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+        if (SOA)
+            sr_s[0][SW] = sr_s[1][SW] = sr_s[2][SW] = 1.0e18f;
+    }
 
     const PairConsts k = pair_consts(a.c);
     Acc A;   // bonded and native terms
@@ -1901,7 +1915,10 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
                 const int e = sl - w0;
                 pj[u] = sl_s[(unsigned)e < (unsigned)wn ? e : SW];
             } else {
-                pj[u] = sl_s[sl];
+                if constexpr (FORM == 0 && SOA)
+                    pj[u] = make_float4(sr_s[0][sl], sr_s[1][sl], sr_s[2][sl], 0.0f);
+                else
+                    pj[u] = sl_s[sl];
             }
         }
         if constexpr (!WIDE) {
