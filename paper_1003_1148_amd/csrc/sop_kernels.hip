@@ -1511,6 +1511,42 @@ __device__ __forceinline__ float3 unpack_low(const float4 &s)
     return make_float3(l[0], l[1], l[2]);
 }
 
+// Batched schedule: each residue packs its low part in units of one quantum,
+// ulp/1000 of its largest high coordinate (no coarser than ulp/1000 of any
+// other), so that a partner's three fields take one exponent to unpack.
+__device__ __forceinline__ float res_quantum(const float4 &h)
+{
+    return ulp_of(fmaxf(fabsf(h.x), fmaxf(fabsf(h.y), fabsf(h.z)))) * 1.0e-3f;
+}
+
+__device__ __forceinline__ unsigned pack_low_res(const float4 &hi, const float4 &lo)
+{
+    const int E = (__float_as_int(fmaxf(fabsf(hi.x), fmaxf(fabsf(hi.y), fabsf(hi.z)))) >> 23) & 0xff;
+    // 1/quantum: a power of two (biased exponent 277 - E) times 1000
+    const float inv_q = (E >= 24 && E <= 253) ? __int_as_float((277 - E) << 23) * 1000.0f : 0.0f;
+    unsigned bitsw = 0u;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int qv = (int)rintf(fminf(fmaxf(comp(lo, ax) * inv_q, -511.0f), 511.0f));
+        bitsw |= ((unsigned)qv & 0x3ffu) << (10 * ax);
+    }
+    return bitsw;
+}
+
+// hi_i + lo_i - (hj + its packed low part), per axis
+__device__ __forceinline__ float3 pair_delta_packed(const float4 &hi, const float4 &lo, const float4 &hj)
+{
+    const unsigned w = __float_as_uint(hj.w);
+    const float qm = res_quantum(hj);
+    float d[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int qv = ((int)(w << (22 - 10 * ax))) >> 22;  // sign-extended 10-bit field
+        d[ax] = (comp(hi, ax) - comp(hj, ax)) + __builtin_fmaf(-(float)qv, qm, comp(lo, ax));
+    }
+    return make_float3(d[0], d[1], d[2]);
+}
+
 // A tile whose residues all lie within this distance of its origin has its
 // list partners (within r_list = 20 A of one of them at the rebuild, a few
 // tenths of an Angstrom more after ten steps) within about 64 A of it, so
@@ -2396,7 +2432,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
         thi = a.traj_hi[i] + shift;
         row = a.trow[i];
         cnt = a.list_cnt[i];
-        shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low(hi, lo)));
+        shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low_res(hi, lo)));
         shl[t] = lo;
     }
     sres[t] = i;
@@ -2606,16 +2642,14 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
                 auto chunk = [&](unsigned wx, unsigned wy) {
                     const unsigned idx[4] = {wx & 0xffffu, wx >> 16, wy & 0xffffu, wy >> 16};
                     // one 16-byte read a partner: the high part and its packed
-                    // low part (a 10-bit multiple of ulp/1000 per axis)
+                    // low part (10-bit multiples of the partner's quantum)
                     float4 qh[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
                         qh[u] = shh[idx[u]];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float3 l = unpack_low(qh[u]);
-                        add_repulsive_u(L, pair_delta(ph, pl, qh[u], make_float4(l.x, l.y, l.z, 0.0f)), kc, false);
-                    }
+                    for (int u = 0; u < 4; ++u)
+                        add_repulsive_u(L, pair_delta_packed(ph, pl, qh[u]), kc, false);
                 };
                 uint4 w = rp[0];
                 for (int c2 = 0; c2 < nc2; ++c2) {
@@ -2700,7 +2734,7 @@ __global__ __launch_bounds__(WGS, 4) void k_batch(BatchArgs a)
             }
             if (act) {
                 langevin_update(hi, lo, A, step, stream, cn, a.err);
-                shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low(hi, lo)));
+                shh[t] = make_float4(hi.x, hi.y, hi.z, __uint_as_float(pack_low_res(hi, lo)));
                 shl[t] = lo;
             }
             __syncthreads();
