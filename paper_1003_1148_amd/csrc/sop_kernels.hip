@@ -1915,6 +1915,11 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         cnt = act ? base : 0;
         nch = (cnt + 3) >> 2;
         __syncthreads();  // the rows are written (read back below) and the lengths known
+        // the row's first chunks requested together, as the other steps do
+        // before their staging; they arrive while the rank is counted
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k)
+            lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
         // the later steps hand the rows to their waves longest first (ties
         // in index order): the residue's rank, counted by its NL lanes
         int r = 0;
@@ -1926,11 +1931,6 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
             r += __shfl_xor(r, off, NL);
         if (act && q == 0)
             a.tile_ord_out[(size_t)tile * TILE + r] = (unsigned char)rho;
-        // the row's first chunks requested together, as the other steps do
-        // before their staging
-#pragma unroll
-        for (int k = 0; k < NPRE; ++k)
-            lw[k] = q + k * NL < nch ? lp[q + k * NL] : make_uint2(0u, 0u);
     }
     // ---- 3. list chunks of this lane ----
     Acc L;   // list: sum of d / r^8 (scaled by 6 eps_l sigma^6 below)
