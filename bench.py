@@ -550,6 +550,14 @@ def main():
             "rebuild_us": rb_ms * 1e3,
             "rebuild_filter_us": filter_ms * 1e3,
             "rebuild_search_us": search_ms * 1e3,
+            "rebuild_note": "a rebuild run on its own (explicit list builds): the search kernels' "
+                            "early exits and the filter kernel, or the cell-grid search; while "
+                            "stepping, the first step of a period filters the skin rows itself",
+            "list_upkeep_us_per_period": dt * 1e6 / args.steps - L * k_ms * 1e3,
+            "list_upkeep_note": "the timed period less ten plain step launches: the first step's "
+                                "filtering, the search kernels (early exits, and the searches "
+                                "that fell in the timed periods), the last step's binning, "
+                                "energy records and launch gaps",
             "timed_rebuilds": n_reb,
             "timed_skin_searches": n_srch,
             "whole_step": {
