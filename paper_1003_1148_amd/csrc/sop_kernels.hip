@@ -1797,10 +1797,18 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     // the lanes of a wave that bin into one cell take consecutive slots
     // from one atomic, issued by the group's first lane (uniform branch:
     // the whole wave takes part in the ballots)
+    // the first step of a period never bins (it clears the cell counts the
+    // binning at the period's end fills; a period's first step is not its last)
+    const bool do_bin = MODE == 0 && !FIRST && a.do_bin;
     int bin_lead = 0, bin_rank = 0, bin_base = 0;
-    if (MODE == 0 && a.do_bin) {
+    int bin_c0 = -1;           // the cell of the position before the update
+    int4 bin_off = {0, 0, 0, 0};  // the trajectory's cell offset, kept for after the update
+    if (do_bin) {
         const bool binning = upd;
-        const int c0 = binning ? cell_index(hu, a.traj_cell[__float_as_int(lu.w)], a.g) : -1;
+        if (binning)
+            bin_off = a.traj_cell[__float_as_int(lu.w)];
+        const int c0 = binning ? cell_index(hu, bin_off, a.g) : -1;
+        bin_c0 = c0;
         const int lane = (int)__lane_id();
         const unsigned long long below = (1ull << lane) - 1ull;
         unsigned long long todo = __ballot(binning);
@@ -2034,7 +2042,7 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
     }
     // this residue's slot in its cell (the group's atomic has returned)
     int bin_s0 = 0;
-    if (MODE == 0 && a.do_bin)
+    if (do_bin)
         bin_s0 = __shfl(bin_base, bin_lead) + bin_rank;
     __syncthreads();
     if (!upd)
@@ -2075,10 +2083,9 @@ __global__ __launch_bounds__(256, ENERGY ? 2 : (TILE >= 256 ? 3 : 5)) void k_til
         if (!(dx * dx + dy * dy + dz * dz <= a.check_thr2))
             atomicOr(a.skin_flag, 1u);
     }
-    if (a.do_bin) {
+    if (do_bin) {
         const int traj = __float_as_int(lo.w);
-        const int bin_c0 = cell_index(hu, a.traj_cell[traj], a.g);
-        const int c1 = cell_index(hi, a.traj_cell[traj], a.g);
+        const int c1 = cell_index(hi, bin_off, a.g);
         if (c1 == bin_c0) {
             a.cell_of[iu] = c1;
             if (bin_s0 < CELL_CAP)
@@ -3164,6 +3171,7 @@ void launch_step(const DevBufs &b, int cur, int n, int cap, int tile, const Step
     a.tip = tip;
     if (mode == 0 && filter_rc2 > 0.0f) {
         // the first step after a rebuild, which filters the skin rows itself
+        // (never a binning step: the callers bin only at a period's end)
         a.skin16 = b.list16;
         a.skin_cnt = b.list_cnt;
         a.skin_ord = b.skin_ord;
